@@ -1,0 +1,299 @@
+"""Reference oracle for the randomly shifted rank-1 lattice QMC path.
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by the package smoke check
+and by the benchmark's CPU-baseline leg; never by the product.  It wraps the
+plain fp64 C implementation in ``oracle.c`` and adds the few host-level steps
+of the method that are plain arithmetic on m numbers:
+
+  * estimate and error from the m per-shift estimates (Sec. 2.1, eqs. lattice
+    and lattice-error);
+  * the error goal, real and complex ("all" / "largest", App. A.1 errormode);
+  * the "Case 1" growth loop (Sec. 3.3.1): evaluate minm shifts of the
+    smallest lattice >= minn, discard and move to a larger lattice until the
+    goal or maxeval is reached; only the last result counts.  The next size
+    is read as get_next_n(max(1.5 n, n * err / goal)), assuming err ~ 1/n.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+T_NONE, T_KOROBOV, T_BAKER = 0, 1, 2
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c with gcc (plain fp64: no fast-math, no contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-shared", "-fPIC",
+             "-std=gnu11", _SRC, "-o", tmp, "-lm"]
+        )
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Desc(C.Structure):
+    _fields_ = [
+        ("dim", C.c_uint32),
+        ("n_u", C.c_uint32),
+        ("n_f", C.c_uint32),
+        ("coef", C.POINTER(C.c_double)),
+        ("expo", C.POINTER(C.c_uint8)),
+        ("pow_u", C.c_double),
+        ("pow_f", C.c_double),
+        ("prefactor", C.c_double),
+        ("deform", C.c_int32),
+        ("lam", C.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = C.CDLL(_LIB)
+        dp = C.POINTER(C.c_double)
+        up = C.POINTER(C.c_uint64)
+        L.oracle_splitmix64_next.argtypes = [up]
+        L.oracle_splitmix64_next.restype = C.c_uint64
+        L.oracle_shifts.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, dp]
+        L.oracle_lattice_indices.argtypes = [C.c_uint64, C.c_uint32, up, C.c_uint64, C.c_uint64, up]
+        for f in ("oracle_korobov_omega", "oracle_korobov_phi"):
+            getattr(L, f).argtypes = [C.c_double, C.c_int, C.c_int]
+            getattr(L, f).restype = C.c_double
+        L.oracle_baker_phi.argtypes = [C.c_double]
+        L.oracle_baker_phi.restype = C.c_double
+        L.oracle_vr_map.argtypes = [dp, C.c_double, dp, dp]
+        L.oracle_eval_point.argtypes = [C.POINTER(_Desc), dp, dp, dp]
+        L.oracle_eval_point.restype = C.c_int
+        L.oracle_shift_sums.argtypes = [
+            C.POINTER(_Desc), C.c_uint64, up, C.c_uint32, dp, C.c_int, C.c_int, C.c_int, dp,
+            C.c_uint64, C.c_uint64, C.POINTER(C.c_uint32), C.c_uint32, dp, dp, dp, dp, up, up, C.c_int,
+        ]
+        L.oracle_shift_sums.restype = C.c_int
+        L.oracle_histogram.argtypes = [C.POINTER(_Desc), C.c_uint64, up, dp, C.c_uint32, dp]
+        L.oracle_histogram.restype = C.c_int
+        L.oracle_cbc_criterion.argtypes = [C.c_uint64, C.c_uint32, up, dp]
+        L.oracle_cbc_criterion.restype = C.c_double
+        L.oracle_cbc_brute.argtypes = [C.c_uint64, C.c_uint32, dp, C.c_double, up]
+        L.oracle_cbc_brute.restype = C.c_int
+        L.oracle_max_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _up(a):
+    return a.ctypes.data_as(C.POINTER(C.c_uint64))
+
+
+def _mk_desc(desc):
+    """ctypes view of a workloads.Desc; keeps the numpy arrays alive."""
+    coef = np.ascontiguousarray(desc.coef, dtype=np.float64)
+    expo = np.ascontiguousarray(desc.expo, dtype=np.uint8)
+    d = _Desc(desc.dim, desc.n_u, desc.n_f, _dp(coef), expo.ctypes.data_as(C.POINTER(C.c_uint8)),
+              desc.pow_u, desc.pow_f, desc.prefactor, 1 if desc.deform else 0, desc.lam)
+    return d, (coef, expo)
+
+
+# ---------------------------------------------------------------- shifts / lattice
+
+
+def splitmix64(seed: int, count: int) -> list[int]:
+    st = C.c_uint64(seed)
+    return [lib().oracle_splitmix64_next(C.byref(st)) for _ in range(count)]
+
+
+def shifts(seed: int, m: int, d: int) -> np.ndarray:
+    out = np.empty(m * d, dtype=np.float64)
+    lib().oracle_shifts(seed, m, d, _dp(out))
+    return out.reshape(m, d)
+
+
+def lattice_indices(n: int, z, k0: int, count: int) -> np.ndarray:
+    zz = np.asarray(z, dtype=np.uint64)
+    out = np.empty(count * zz.size, dtype=np.uint64)
+    lib().oracle_lattice_indices(n, zz.size, _up(zz), k0, count, _up(out))
+    return out.reshape(count, zz.size)
+
+
+# ---------------------------------------------------------------- transforms
+
+
+def korobov_phi(u, r0=3, r1=3):
+    return lib().oracle_korobov_phi(float(u), r0, r1)
+
+
+def korobov_omega(u, r0=3, r1=3):
+    return lib().oracle_korobov_omega(float(u), r0, r1)
+
+
+def baker_phi(u):
+    return lib().oracle_baker_phi(float(u))
+
+
+def vr_map(a, y):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    x = C.c_double()
+    dx = C.c_double()
+    lib().oracle_vr_map(_dp(a), float(y), C.byref(x), C.byref(dx))
+    return x.value, dx.value
+
+
+def eval_point(desc, x) -> complex:
+    d, keep = _mk_desc(desc)
+    xx = np.ascontiguousarray(x, dtype=np.float64)
+    re, im = C.c_double(), C.c_double()
+    lib().oracle_eval_point(C.byref(d), _dp(xx), C.byref(re), C.byref(im))
+    return complex(re.value, im.value)
+
+
+# ---------------------------------------------------------------- sums
+
+
+class ShiftSums:
+    """Per-shift sums over [k0, k1) for a subset of the shifts."""
+
+    def __init__(self, ids, re, im, abs_re, abs_im, nonfinite, sign_points):
+        self.ids = ids
+        self.re = re
+        self.im = im
+        self.abs_re = abs_re
+        self.abs_im = abs_im
+        self.nonfinite = nonfinite
+        self.sign_points = sign_points
+
+
+def shift_sums(desc, n, z, m, shift_table, transform=(T_KOROBOV, 3, 3), vr=None, k0=0, k1=None,
+               ids=None, threads=None) -> ShiftSums:
+    """S_s = sum_k w f over points k in [k0, k1), for shifts `ids` (default all)."""
+    if k1 is None:
+        k1 = n
+    if ids is None:
+        ids = list(range(m))
+    if threads is None:
+        threads = lib().oracle_max_threads()
+    d, keep = _mk_desc(desc)
+    zz = np.ascontiguousarray(z, dtype=np.uint64)
+    sh = np.ascontiguousarray(shift_table, dtype=np.float64).reshape(-1)
+    assert sh.size == m * desc.dim and zz.size == desc.dim
+    ida = np.ascontiguousarray(ids, dtype=np.uint32)
+    k = ida.size
+    re, im, ar, ai = (np.zeros(k) for _ in range(4))
+    nf = np.zeros(k, dtype=np.uint64)
+    sp = np.zeros(k, dtype=np.uint64)
+    vra = None if vr is None else np.ascontiguousarray(vr, dtype=np.float64).reshape(-1)
+    rc = lib().oracle_shift_sums(
+        C.byref(d), n, _up(zz), m, _dp(sh), int(transform[0]), int(transform[1]), int(transform[2]),
+        None if vra is None else _dp(vra), k0, k1, ida.ctypes.data_as(C.POINTER(C.c_uint32)), k,
+        _dp(re), _dp(im), _dp(ar), _dp(ai), _up(nf), _up(sp), int(threads))
+    if rc != 0:
+        raise ValueError("oracle_shift_sums rejected its arguments")
+    return ShiftSums(list(ids), re, im, ar, ai, nf, sp)
+
+
+def histogram(desc, n, z, delta, bins=1024) -> np.ndarray:
+    d, keep = _mk_desc(desc)
+    zz = np.ascontiguousarray(z, dtype=np.uint64)
+    dl = np.ascontiguousarray(delta, dtype=np.float64)
+    out = np.zeros(desc.dim * bins)
+    rc = lib().oracle_histogram(C.byref(d), n, _up(zz), _dp(dl), bins, _dp(out))
+    if rc != 0:
+        raise ValueError("oracle_histogram rejected its arguments")
+    return out.reshape(desc.dim, bins)
+
+
+# ---------------------------------------------------------------- estimate + error
+
+
+def estimate(per_shift: np.ndarray) -> tuple[float, float]:
+    """Mean of the m per-shift estimates and the error sqrt(sigma^2) of eq.
+    (lattice-error); m = 1 gives an infinite error."""
+    q = np.asarray(per_shift, dtype=np.float64)
+    m = q.size
+    mean = math.fsum(q.tolist()) / m
+    if m < 2:
+        return mean, math.inf
+    var = math.fsum(((q - mean) ** 2).tolist()) / (m * (m - 1))
+    return mean, math.sqrt(var)
+
+
+def goal_met(re, im, err_re, err_im, rel_tol, abs_tol, errormode, is_complex) -> bool:
+    """App. A.1: real |E-I| <= max(epsabs, epsrel |I|); complex 'all' checks each
+    component, 'largest' compares the larger error to epsrel * max(|Re|,|Im|)."""
+    if not is_complex:
+        return err_re <= max(abs_tol, rel_tol * abs(re))
+    if errormode == "all":
+        return err_re <= max(abs_tol, rel_tol * abs(re)) and err_im <= max(abs_tol, rel_tol * abs(im))
+    return max(err_re, err_im) <= max(abs_tol, rel_tol * max(abs(re), abs(im)))
+
+
+def integrate(desc, n, z_of, m, seed, transform=(T_KOROBOV, 3, 3), vr=None, rel_tol=0.0,
+              abs_tol=0.0, errormode="largest", max_evals=None, table_ns=None, threads=None):
+    """Oracle integration: Case 2 (one lattice) when rel_tol <= 0 and abs_tol <= 0,
+    else the Case-1 growth loop over `table_ns` with generating vectors z_of(n)."""
+    sh = shifts(seed, m, desc.dim)
+    evals = 0
+    it = 0
+    visited = []
+    while True:
+        visited.append(n)
+        s = shift_sums(desc, n, z_of(n), m, sh, transform, vr, threads=threads)
+        it += 1
+        evals += n * m
+        re, err_re = estimate(s.re / n)
+        im, err_im = estimate(s.im / n)
+        res = dict(re=re, im=im, err_re=err_re, err_im=err_im, n=n, m=m, iterations=it,
+                   evaluations=evals, sums_re=s.re.copy(), sums_im=s.im.copy(),
+                   abs_re=s.abs_re.copy(), abs_im=s.abs_im.copy(), converged=False,
+                   maxeval_hit=False, visited=list(visited))
+        if rel_tol <= 0 and abs_tol <= 0:
+            return res
+        if goal_met(re, im, err_re, err_im, rel_tol, abs_tol, errormode, desc.deform):
+            res["converged"] = True
+            return res
+        goal = max(abs_tol, rel_tol * (max(abs(re), abs(im)) if desc.deform else abs(re)))
+        err = max(err_re, err_im) if desc.deform else err_re
+        want = max(1.5 * n, n * (err / goal if goal > 0 else 2.0))
+        larger = [v for v in sorted(table_ns) if v >= want]
+        if not larger or (max_evals is not None and evals + larger[0] * m > max_evals):
+            res["maxeval_hit"] = True
+            return res
+        n = larger[0]
+
+
+# ---------------------------------------------------------------- CBC
+
+
+def cbc_criterion(n, z, gammas) -> float:
+    zz = np.ascontiguousarray(z, dtype=np.uint64)
+    g = np.ascontiguousarray(gammas, dtype=np.float64)
+    return lib().oracle_cbc_criterion(n, zz.size, _up(zz), _dp(g))
+
+
+def cbc_brute(n, d, gammas=None, tie_rtol=1e-9) -> list[int]:
+    if gammas is None:
+        gammas = [1.0 / (j + 1) ** 2 for j in range(d)]
+    g = np.ascontiguousarray(gammas, dtype=np.float64)
+    out = np.zeros(d, dtype=np.uint64)
+    rc = lib().oracle_cbc_brute(n, d, _dp(g), tie_rtol, _up(out))
+    if rc != 0:
+        raise ValueError("oracle_cbc_brute rejected its arguments")
+    return [int(v) for v in out]

@@ -1,0 +1,409 @@
+"""Pins of the oracle against facts fixed by the paper and by mathematics.
+
+None of these re-type the oracle's own formulas: each compares it with a
+value printed in the paper, a closed form, an exact identity or a
+statistical property, chosen so that a dropped term, a wrong sign or index
+or a transposed operand fails at least one of them.
+"""
+
+import math
+
+import mpmath as mp
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from conftest import golden
+from paper_1811_11720_amd import cbc
+
+KOR3 = (oracle.T_KOROBOV, 3, 3)
+
+
+def _gl(f, a, b, nodes=40):
+    x, w = np.polynomial.legendre.leggauss(nodes)
+    t = 0.5 * (b - a) * x + 0.5 * (b + a)
+    return 0.5 * (b - a) * sum(wi * f(ti) for ti, wi in zip(t, w))
+
+
+# ------------------------------------------------------------------ shifts
+
+
+def test_splitmix64_published_vector():
+    want = [int(r[0]) for r in golden("splitmix64_seed1234567.txt")]
+    assert oracle.splitmix64(1234567, 5) == want
+
+
+def test_shifts_are_53bit_uniform_in_unit_interval():
+    sh = oracle.shifts(42, 64, 10)
+    assert sh.shape == (64, 10)
+    assert np.all(sh >= 0.0) and np.all(sh < 1.0)
+    # every value is an integer multiple of 2^-53
+    assert np.all(np.floor(sh * 2.0 ** 53) == sh * 2.0 ** 53)
+    # shift-major order: the first shift is the first d draws
+    raw = oracle.splitmix64(42, 10)
+    assert np.array_equal(sh[0], np.array([(v >> 11) * 2.0 ** -53 for v in raw]))
+
+
+# ------------------------------------------------------------------ lattice indices
+
+
+@pytest.mark.parametrize("n,z", [(55, [1, 34]), (7, [1, 3]), (11, [1, 7]), (10007, [1, 3822, 2833])])
+def test_lattice_indices_match_integer_arithmetic(n, z):
+    got = oracle.lattice_indices(n, z, 0, n)
+    for k in range(0, n, max(1, n // 97)):
+        assert [int(v) for v in got[k]] == [(k * zj) % n for zj in z]
+    # a rank-1 lattice with z_1 = 1 visits every residue of every coordinate once
+    for j in range(len(z)):
+        assert sorted(int(v) for v in got[:, j]) == list(range(n))
+
+
+def test_lattice_indices_64bit_path():
+    """n beyond 2^32 (the paper's largest table, App. A.3: 15173222401)."""
+    n = 15173222401
+    z = [1, 5915492197, 12345678911]
+    rng = np.random.default_rng(0)
+    ks = [int(v) for v in rng.integers(0, n, size=64)] + [n - 1, 0, 1]
+    for k in ks:
+        got = oracle.lattice_indices(n, z, k, 1)[0]
+        assert [int(v) for v in got] == [(k * zj) % n for zj in z]
+
+
+# ------------------------------------------------------------------ CBC
+
+
+def test_cbc_criterion_one_dimension_closed_form():
+    """d=1, z=1: sum_k B2(k/n) = B2(0)/n (multiplication theorem), so
+    e^2 = gamma * 2 pi^2 / (6 n^2) = gamma pi^2 / (3 n^2)."""
+    for n in (7, 55, 1009):
+        for g in (0.5, 1.0):
+            got = oracle.cbc_criterion(n, [1], [g])
+            assert got == pytest.approx(g * math.pi ** 2 / (3 * n * n), rel=1e-12)
+
+
+def test_paper_vectors_reach_the_cbc_minimum():
+    """Fig. 1 and App. A.3 vectors, equal weights 1/d (Sec. 2.2): each is
+    optimal among all z_2 (brute force), and our CBC reaches the same value."""
+    for n, z1, z2 in golden("paper_generating_vectors.txt"):
+        n, z = int(n), [int(z1), int(z2)]
+        g = [0.5, 0.5]
+        paper = oracle.cbc_criterion(n, z, g)
+        best = min(oracle.cbc_criterion(n, [1, c], g) for c in range(1, n) if math.gcd(c, n) == 1)
+        assert paper == pytest.approx(best, rel=1e-12)
+        ours = oracle.cbc_brute(n, 2, g)
+        assert oracle.cbc_criterion(n, ours, g) == pytest.approx(best, rel=1e-12)
+
+
+def test_cbc_brute_matches_exhaustive_second_component():
+    n, g = 101, [1.0, 0.25]
+    z = oracle.cbc_brute(n, 2, g)
+    crit = {c: oracle.cbc_criterion(n, [1, c], g) for c in range(1, (n - 1) // 2 + 1)}
+    best = min(crit.values())
+    assert z[1] == min(c for c, v in crit.items() if v <= best * (1 + 1e-9))
+
+
+@pytest.mark.parametrize("n,d", [(101, 4), (1009, 3), (1999, 5)])
+def test_fast_cbc_equals_brute_force(n, d):
+    """The product's FFT CBC against the oracle's brute force (small n)."""
+    assert cbc.fast_cbc(n, d) == oracle.cbc_brute(n, d)
+
+
+# ------------------------------------------------------------------ transforms
+
+
+@pytest.mark.parametrize("r0,r1", [(3, 3), (1, 1), (2, 4), (5, 3), (0, 2), (6, 6)])
+def test_korobov_weight_normalised_and_map_is_its_integral(r0, r1):
+    """eq. korobov: int_0^1 omega = 1, phi(0)=0, phi(1)=1, phi' = omega."""
+    assert _gl(lambda t: oracle.korobov_omega(t, r0, r1), 0.0, 1.0) == pytest.approx(1.0, abs=1e-14)
+    assert oracle.korobov_phi(0.0, r0, r1) == 0.0
+    assert oracle.korobov_phi(1.0, r0, r1) == pytest.approx(1.0, abs=1e-15)
+    for u in (0.013, 0.25, 0.5, 0.77, 0.999):
+        want = _gl(lambda t: oracle.korobov_omega(t, r0, r1), 0.0, u)
+        assert oracle.korobov_phi(u, r0, r1) == pytest.approx(want, abs=1e-14)
+
+
+def test_korobov_symmetric_map_is_odd_about_half():
+    for u in np.linspace(0.0, 1.0, 33):
+        assert oracle.korobov_phi(u, 3, 3) + oracle.korobov_phi(1.0 - u, 3, 3) == pytest.approx(1.0, abs=1e-15)
+
+
+def test_korobov_r3_value_at_half():
+    """omega_3(1/2) = 7 * C(6,3) / 2^6 (eq. korobov with r0 = r1 = 3)."""
+    assert oracle.korobov_omega(0.5, 3, 3) == pytest.approx(7 * 20 / 64, rel=1e-15)
+
+
+def test_baker_preserves_integrals():
+    """eq. baker: int_0^1 q(phi(u)) du = int_0^1 q(x) dx (tent map, weight 1)."""
+    q = lambda x: 3.0 * x ** 5 - x ** 2 + 0.5
+    lhs = _gl(lambda u: q(oracle.baker_phi(u)), 0.0, 0.5) + _gl(lambda u: q(oracle.baker_phi(u)), 0.5, 1.0)
+    assert lhs == pytest.approx(0.5 - 1.0 / 3.0 + 0.5, abs=1e-14)
+    assert oracle.baker_phi(0.0) == 0.0 and oracle.baker_phi(0.5) == 1.0
+    assert oracle.baker_phi(0.25) == 0.5 and oracle.baker_phi(0.75) == 0.5
+
+
+# ------------------------------------------------------------------ VR map
+
+
+def _vr_params(rng):
+    return [1.001 + rng.exponential(0.5), -0.001 - rng.exponential(0.5), rng.uniform(0.0, 0.3),
+            rng.uniform(0.0, 0.3), rng.uniform(0.5, 1.0), rng.uniform(-0.2, 0.2)]
+
+
+def test_vr_map_endpoints_and_derivative():
+    """eq. ISfit: p(0)=0, p(1)=1; the Jacobian is p' (checked by quadrature)."""
+    rng = np.random.default_rng(3)
+    for _ in range(8):
+        a = _vr_params(rng)
+        assert oracle.vr_map(a, 0.0)[0] == 0.0
+        assert oracle.vr_map(a, 1.0)[0] == pytest.approx(1.0, abs=1e-14)
+        for y in (0.1, 0.5, 0.93):
+            want = mp.quad(lambda t: oracle.vr_map(a, float(t))[1], [0, y])
+            assert oracle.vr_map(a, y)[0] == pytest.approx(float(want), abs=1e-12)
+
+
+def test_vr_map_identity_parameters():
+    a = [2.0, -1.0, 0.0, 0.0, 1.0, 0.0]  # p(y) = y
+    for y in (0.0, 0.3, 0.999):
+        x, dx = oracle.vr_map(a, y)
+        assert x == pytest.approx(y, abs=1e-16) and dx == pytest.approx(1.0, abs=1e-15)
+
+
+# ------------------------------------------------------------------ integrand + rule
+
+
+def _integrate(desc, n, m=16, seed=11, transform=KOR3, vr=None):
+    z = cbc.fast_cbc(n, desc.dim) if desc.dim > 1 else [1]
+    sh = oracle.shifts(seed, m, desc.dim)
+    s = oracle.shift_sums(desc, n, z, m, sh, transform, vr)
+    re, er = oracle.estimate(s.re / n)
+    im, ei = oracle.estimate(s.im / n)
+    return complex(re, im), er, ei, s
+
+
+def test_minimal_example_one_eighth():
+    """Sec. 3.2, Fig. cppminimal: int x0 x1 x2 = 1/8 with Korobov weight 3."""
+    dim, exact = golden("minimal_example.txt")[0]
+    desc = W.monomial([1.0], [[1, 1, 1]], int(dim), n_u=1)
+    n = cbc.next_prime(8191)  # minn default, App. A.1
+    val, err, _, _ = _integrate(desc, n, m=32)
+    assert abs(val.real - float(exact)) < max(6 * err, 1e-14)
+    assert abs(val.real - float(exact)) < 1e-9
+
+
+@pytest.mark.parametrize("power", [-1.5, -2.0, 0.5])
+def test_product_of_linear_closed_form(power):
+    """F = prod_j (a_j + b_j x_j) expanded into monomials, f = F^p:
+    int f = prod_j [(a_j+b_j)^(p+1) - a_j^(p+1)] / (b_j (p+1))."""
+    rng = np.random.default_rng(5)
+    a = rng.uniform(0.5, 1.5, 3)
+    b = rng.uniform(0.2, 1.0, 3)
+    desc = W.product_of_linear(a, b, power)
+    exact = np.prod(((a + b) ** (power + 1) - a ** (power + 1)) / (b * (power + 1)))
+    val, err, _, _ = _integrate(desc, cbc.next_prime(50000), m=16)
+    assert abs(val.real - exact) < max(6 * err, 1e-13)
+    assert abs(val.real - exact) < 1e-9 * abs(exact)
+
+
+def test_plain_product_workload_integrates_to_one():
+    job = W.job_plain_product()
+    sh = oracle.shifts(job.seed, job.m, job.desc.dim)
+    s = oracle.shift_sums(job.desc, job.n, job.z, job.m, sh, job.transform)
+    val, err = oracle.estimate(s.re / job.n)
+    assert abs(val - 1.0) < max(6 * err, 1e-13)
+
+
+def test_full_grid_identity_tiny_lattice():
+    """Averaging a rank-1 rule over the n grid shifts (0, l/n) gives the tensor
+    rectangle rule (the union is the full n x n grid), which factorises for a
+    product integrand: pins indices, shifts, fractional part and the monomial
+    expansion without any smoothness assumption (transform None and Korobov)."""
+    n, z = 13, [1, 5]
+    c = [0.7, 1.9]
+    desc = W.product_of_linear([1.0, 1.0], c, 1.0)  # F = (1 + c0 x)(1 + c1 y)
+    base = np.array([0.3141592653589793, 0.2718281828459045])
+    for tr in ((oracle.T_NONE, 0, 0), KOR3):
+        rows = []
+        for l in range(n):
+            d2 = (base[1] + l / n) % 1.0
+            rows.append([base[0], d2])
+        sh = np.array(rows)
+        s = oracle.shift_sums(desc, n, z, n, sh, tr)
+        lhs = s.re.sum()
+
+        def g(u, cj):
+            if tr[0] == oracle.T_NONE:
+                return 1.0 + cj * u
+            return oracle.korobov_omega(u, 3, 3) * (1.0 + cj * oracle.korobov_phi(u, 3, 3))
+
+        s0 = sum(g((k / n + base[0]) % 1.0, c[0]) for k in range(n))
+        s1 = sum(g((k / n + base[1]) % 1.0, c[1]) for k in range(n))
+        assert lhs == pytest.approx(s0 * s1, rel=1e-13)
+
+
+def test_lattice_rule_exact_for_low_degree_trig_polynomial_via_none_transform():
+    """With transform None the rule integrates x -> 1 + (x - 1/2) exactly for any
+    shift only in the mean over the lattice: sum_k ({k/n + D}) = (n-1)/2 + n D - #wraps.
+    Check the unshifted case (D = 0) exactly: sum_k k/n = (n-1)/2."""
+    n = 101
+    desc = W.monomial([1.0], [[1]], 1, n_u=1)
+    s = oracle.shift_sums(desc, n, [1], 1, np.zeros((1, 1)), (oracle.T_NONE, 0, 0))
+    assert s.re[0] == pytest.approx((n - 1) / 2.0, rel=1e-15)
+
+
+def test_zero_weight_points_are_skipped_not_nan():
+    """A point with u = 0 has Korobov weight 0; f may be infinite there
+    (x^-1), but the contribution is exactly 0, not NaN."""
+    desc = W.monomial([1.0], [[1]], 1, n_u=1, pow_u=-1.0)
+    s = oracle.shift_sums(desc, 7, [1], 1, np.zeros((1, 1)), KOR3)
+    assert np.isfinite(s.re[0]) and s.nonfinite[0] == 0
+
+
+def test_nonfinite_contributions_are_counted():
+    """Real path, negative base with a non-integer power: NaN is kept and counted."""
+    desc = W.monomial([1.0, -3.0], [[0], [1]], 1, n_u=2, pow_u=-1.5)
+    s = oracle.shift_sums(desc, 11, [1], 1, np.full((1, 1), 0.05), (oracle.T_NONE, 0, 0))
+    assert s.nonfinite[0] > 0 and not np.isfinite(s.re[0])
+
+
+def test_error_estimate_coverage():
+    """eq. lattice-error is an unbiased variance estimate: over many seeds,
+    (Q - I)/sigma follows Student-t with m-1 dof (two-sided 95% band)."""
+    desc = W.product_of_linear([1.0, 1.0], [0.8, 0.5], -1.0)
+    exact = np.prod(np.log1p(np.array([0.8, 0.5])) / np.array([0.8, 0.5]))
+    n, m, z = 61, 8, [1, 23]
+    t975 = 2.3646  # Student-t, 7 dof
+    inside = 0
+    seeds = 240
+    for sd in range(seeds):
+        sh = oracle.shifts(1000 + sd, m, 2)
+        s = oracle.shift_sums(desc, n, z, m, sh, (oracle.T_NONE, 0, 0))
+        q, e = oracle.estimate(s.re / n)
+        inside += abs(q - exact) <= t975 * e
+    frac = inside / seeds
+    assert 0.90 <= frac <= 0.99
+
+
+def test_estimate_single_shift_has_infinite_error():
+    assert oracle.estimate(np.array([0.3]))[1] == math.inf
+
+
+# ------------------------------------------------------------------ deformation
+
+
+def _G(w, p):
+    """w^p on the principal branch with w - i0 on the negative real axis."""
+    ang = -mp.pi if w < 0 else 0
+    return mp.exp(p * (mp.log(abs(w)) + 1j * ang))
+
+
+def test_deformation_one_dimensional_root_crossing():
+    """F = a - b x with a root inside: the -i0 closed form
+    [a^(p+1) - (a-b-i0)^(p+1)] / (b (p+1))."""
+    a, b, p = 0.3, 1.0, -1.5
+    desc = W.monomial([1.0, a, -b], [[0], [0], [1]], 1, n_u=1, pow_f=p, deform=True, lam=0.5)
+    exact = complex((_G(a, p + 1) - _G(a - b, p + 1)) / (b * (p + 1)))
+    val, er, ei, s = _integrate(desc, cbc.next_prime(20000), m=8)
+    assert abs(val - exact) < 1e-10 * abs(exact)
+    assert int(s.sign_points.sum()) == 0
+
+
+def test_deformation_two_dimensional_linear_root_crossing():
+    a, b1, b2, p = 1.0, 0.7, 0.9, -1.5
+    desc = W.monomial([1.0, a, -b1, -b2], [[0, 0], [0, 0], [1, 0], [0, 1]], 2, n_u=1, pow_f=p,
+                      deform=True, lam=0.5)
+    exact = complex((_G(a, p + 2) - _G(a - b1, p + 2) - _G(a - b2, p + 2) + _G(a - b1 - b2, p + 2))
+                    / (b1 * b2 * (p + 1) * (p + 2)))
+    val, er, ei, _ = _integrate(desc, cbc.next_prime(50000), m=8)
+    assert abs(val - exact) < 1e-10 * abs(exact)
+
+
+def test_deformation_cauchy_invariance_with_mixed_hessian():
+    """F = a + b x y has no root: deforming must not change the integral
+    -Li2(-b/a)/b, and the off-diagonal Hessian enters the Jacobian."""
+    a, b = 1.0, 2.0
+    for lam in (0.5, 0.0):
+        desc = W.monomial([1.0, a, b], [[0, 0], [0, 0], [1, 1]], 2, n_u=1, pow_f=-1.0, deform=True,
+                          lam=lam)
+        exact = float(-mp.polylog(2, -b / a) / b)
+        val, er, ei, _ = _integrate(desc, cbc.next_prime(50000), m=8)
+        assert abs(val.real - exact) < 1e-11 and abs(val.imag) < 1e-12
+
+
+def test_deformation_bilinear_root_crossing():
+    """F = a - b x y, b > a: int 1/(a - b x y - i0) = Li2(b/a + i0) / b."""
+    a, b = 1.0, 2.5
+    desc = W.monomial([1.0, a, -b], [[0, 0], [0, 0], [1, 1]], 2, n_u=1, pow_f=-1.0, deform=True, lam=0.5)
+    exact = complex(mp.polylog(2, mp.mpc(b / a, 1e-60)) / b)
+    val, er, ei, _ = _integrate(desc, cbc.next_prime(50000), m=8)
+    assert abs(val - exact) < 1e-10 * abs(exact)
+
+
+def test_deformation_evaluates_u_on_the_contour():
+    """U = 1 + x, F = a - b x, powers -1 and -1: partial fractions give
+    [log 2 - log(a - b - i0) + log a] / (a + b)."""
+    a, b = 0.4, 1.0
+    desc = W.monomial([1.0, 1.0, a, -b], [[0], [1], [0], [1]], 1, n_u=2, pow_u=-1.0, pow_f=-1.0,
+                      deform=True, lam=0.5)
+    lg = lambda w: mp.log(abs(w)) + 1j * (-mp.pi if w < 0 else 0)
+    exact = complex((mp.log(2) - lg(a - b) + mp.log(a)) / (a + b))
+    val, er, ei, _ = _integrate(desc, cbc.next_prime(20000), m=8)
+    assert abs(val - exact) < 1e-10 * abs(exact)
+
+
+# ------------------------------------------------------------------ histogram
+
+
+def test_histogram_marginals_of_a_separable_integrand():
+    """For f = prod_j (1 + c_j x_j) the per-dimension CDF of |f| (Sec. 2.4)
+    is (x + c x^2/2) / (1 + c/2); every dimension's histogram sums to sum|f|."""
+    c = np.array([0.5, 2.0, 1.0])
+    desc = W.product_of_linear(np.ones(3), c, 1.0)
+    n = cbc.next_prime(100000)
+    z = cbc.fast_cbc(n, 3)
+    h = oracle.histogram(desc, n, z, np.array([0.11, 0.52, 0.93]), bins=64)
+    tot = h.sum(axis=1)
+    assert np.allclose(tot, tot[0], rtol=1e-13)
+    edges = np.arange(1, 65) / 64.0
+    for j in range(3):
+        cdf = np.cumsum(h[j]) / tot[j]
+        want = (edges + c[j] * edges ** 2 / 2) / (1 + c[j] / 2)
+        assert np.max(np.abs(cdf - want)) < 2e-4
+
+
+# ------------------------------------------------------------------ growth loop
+
+
+def test_growth_loop_stops_at_first_lattice_meeting_goal():
+    """Sec. 3.3.1 (Case 1): results of earlier lattices are discarded; the
+    returned n is the first in the table whose error meets the goal."""
+    desc = W.product_of_linear([1.0, 1.0], [0.8, 0.5], -1.5)
+    table = [cbc.next_prime(v) for v in (1000, 2000, 4000, 8000, 16000, 32000, 64000)]
+    zs = {n: cbc.fast_cbc(n, 2) for n in table}
+    res = oracle.integrate(desc, table[0], zs.__getitem__, 16, 77, KOR3, rel_tol=1e-10, table_ns=table)
+    assert res["converged"]
+    assert res["err_re"] <= 1e-10 * abs(res["re"])
+    assert res["visited"][-1] == res["n"] and len(res["visited"]) == res["iterations"] > 1
+    # every earlier visited lattice failed the goal (otherwise the loop stops there)
+    for n in res["visited"][:-1]:
+        r2 = oracle.integrate(desc, n, zs.__getitem__, 16, 77, KOR3)
+        assert r2["err_re"] > 1e-10 * abs(r2["re"])
+    assert res["evaluations"] == sum(res["visited"]) * 16
+
+
+def test_growth_loop_respects_maxeval():
+    desc = W.product_of_linear([1.0, 1.0], [0.8, 0.5], -1.5)
+    table = [cbc.next_prime(v) for v in (1000, 2000, 4000)]
+    zs = {n: cbc.fast_cbc(n, 2) for n in table}
+    res = oracle.integrate(desc, table[0], zs.__getitem__, 8, 1, KOR3, rel_tol=1e-15,
+                           max_evals=20000, table_ns=table)
+    assert res["maxeval_hit"] and not res["converged"]
+    assert res["evaluations"] <= 20000 or res["iterations"] == 1
+
+
+def test_goal_rules_complex():
+    """App. A.1 errormode: 'all' needs both components, 'largest' the larger
+    error against the larger component."""
+    assert oracle.goal_met(1.0, 1e-3, 1e-6, 1e-6, 1e-5, 0.0, "largest", True)
+    assert not oracle.goal_met(1.0, 1e-3, 1e-6, 1e-6, 1e-5, 0.0, "all", True)
+    assert oracle.goal_met(1.0, 1e-3, 1e-6, 1e-9, 1e-5, 0.0, "all", True)
+    assert oracle.goal_met(1.0, 0.0, 1e-8, 0.0, 0.0, 1e-7, "all", False)
