@@ -1,0 +1,230 @@
+/*
+ * qmc.h -- C interface of the MI355X rank-1 lattice quasi-Monte Carlo integrator.
+ *
+ * The library integrates f over the unit hypercube [0,1]^d with a randomly
+ * shifted rank-1 lattice rule (Borowka et al., CPC 2019, Sec. 2.1, eq. lattice):
+ *
+ *     Q^(s) = (1/n) sum_{k=0}^{n-1} w(u_k) f(x(u_k)),
+ *     u_k   = { k z / n + Delta_s },   s = 0..m-1,
+ *
+ * returning the mean of the m per-shift estimates and the error of eq.
+ * lattice-error.  x(u) applies a periodizing transform (Sec. 2.3: Korobov
+ * eq. korobov, baker eq. baker, or none) and optionally the per-dimension
+ * variance-reduction map of Sec. 2.4 (eq. ISfit).  The integrand is a
+ * sector-decomposed parameter integral prefactor * U(x)^pow_u * F(x)^pow_f
+ * with U, F given as monomial tables; under contour deformation it is
+ * complex.  Every step of a call runs in the library's HIP kernels on one
+ * gfx950 GPU; per-shift sums are reduced on the device in a fixed order.
+ *
+ * Conventions for every entry point:
+ *   - status codes: QMC_OK (0) on success, QMC_PENDING (1) for a request
+ *     still running, negative on error.  No entry point aborts the process;
+ *     qmc_last_error() returns a message for the calling thread's last error.
+ *   - "host" pointers are ordinary CPU memory; all input arrays are copied
+ *     during the call, so the caller may free them on return.  Outputs are
+ *     written into caller-owned host memory.  No entry point takes a device
+ *     pointer except the optional workspace of qmc_context_create.
+ *   - handles (qmc_context, qmc_integrand) are owned by the library and freed
+ *     only by their destroy function.
+ *   - calls on one context are serialised internally; submit/poll/wait/cancel
+ *     may be called from any thread.
+ */
+#ifndef QMC_H
+#define QMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+enum {
+  QMC_OK = 0,
+  QMC_PENDING = 1,     /* qmc_poll: request not finished yet */
+  QMC_EINVAL = -1,     /* an argument is out of range or inconsistent */
+  QMC_ENOMEM = -2,     /* device or host memory, or the workspace, is too small */
+  QMC_EDEVICE = -3,    /* a HIP call failed; the context is no longer usable */
+  QMC_EBUSY = -4,      /* handle still referenced by a pending request */
+  QMC_ENOTFOUND = -5,  /* unknown ticket, or no registered lattice */
+  QMC_ECANCELED = -6,  /* request was cancelled */
+  QMC_EUNSUPPORTED = -7 /* no HIP device / library built without it */
+};
+
+/* limits of the device kernels */
+#define QMC_MAX_DIM 16        /* integration variables per integrand */
+#define QMC_MAX_EXP 15        /* exponent of one variable in one monomial */
+#define QMC_MAX_MONOMIALS 1024 /* n_u + n_f */
+#define QMC_MAX_SHIFTS 1024   /* m */
+
+/* Message describing the last error on the calling thread ("" if none). */
+const char* qmc_last_error(void);
+
+/* Library version as 10000*major + 100*minor + patch. */
+int qmc_version(void);
+
+/* ---------------------------------------------------------------- context */
+typedef struct qmc_context qmc_context;
+
+/*
+ * Create a context on HIP device `device`, launching on `hip_stream`
+ * (a hipStream_t; NULL = the library creates its own stream).
+ * workspace/workspace_bytes: optional caller-owned device memory (for
+ * example a torch tensor's data pointer) from which per-call scratch
+ * (shifts, per-block partial sums) is carved; NULL = the library allocates
+ * and grows its own scratch.  The workspace must stay valid until
+ * qmc_context_destroy.  Errors: QMC_EINVAL (bad device), QMC_EDEVICE.
+ */
+int qmc_context_create(int device, void* hip_stream, void* workspace, size_t workspace_bytes,
+                       qmc_context** out);
+
+/* Destroy; QMC_EBUSY while submitted requests are unfinished. */
+int qmc_context_destroy(qmc_context* ctx);
+
+/*
+ * Register the generating vector z[0..dim) for lattice size n in the
+ * context's table, used when an integration grows n (App. A.1,
+ * generatingvectors).  Requires gcd(z_j, n) = 1 and 2 <= n < 2^53.
+ * Re-registering n replaces its vector.
+ */
+int qmc_register_lattice(qmc_context* ctx, uint64_t n, uint32_t dim, const uint64_t* z);
+
+/*
+ * Smallest registered n >= preferred_n whose vector has >= dim components
+ * (App. A.2, get_next_n); the largest such n if none is >= preferred_n.
+ * QMC_ENOTFOUND if no registered vector has dim components.
+ */
+int qmc_next_lattice(qmc_context* ctx, uint64_t preferred_n, uint32_t dim, uint64_t* n_out);
+
+/* ---------------------------------------------------------------- integrand */
+typedef struct qmc_integrand qmc_integrand;
+
+enum {
+  QMC_DEFORM = 1u,    /* complex result: contour deformation with parameter lambda */
+  QMC_EVAL_FP32 = 2u  /* evaluate U, F and the powers in fp32, accumulate in fp64 */
+};
+
+/*
+ * f(x) = prefactor * U(x)^pow_u * F(x)^pow_f, U and F sums of monomials
+ * coef_i * prod_j x_j^expo[i*dim + j].  Monomials 0..n_u-1 form U, the next
+ * n_f form F; n_f = 0 means F == 1.  With QMC_DEFORM every x_j is replaced
+ * by z_j = x_j - i*lambda*x_j*(1-x_j)*dF/dx_j and the determinant of dz/dx
+ * multiplies f; powers take the principal branch with arg = -pi on the
+ * negative real axis.  Without QMC_DEFORM a negative base with a
+ * non-integer power gives NaN, which is reported, never dropped.
+ */
+typedef struct {
+  uint32_t dim;          /* 1..QMC_MAX_DIM */
+  uint32_t n_u, n_f;     /* n_u >= 1, n_u + n_f <= QMC_MAX_MONOMIALS */
+  const double* coef;    /* host [n_u + n_f], finite */
+  const uint8_t* expo;   /* host [(n_u + n_f) * dim], row-major, each <= QMC_MAX_EXP */
+  double pow_u, pow_f, prefactor; /* finite */
+  uint32_t flags;        /* QMC_DEFORM | QMC_EVAL_FP32 */
+  double lambda;         /* deformation parameter, used iff QMC_DEFORM */
+} qmc_integrand_desc;
+
+/* Copy a descriptor to the device (one host-to-device copy). */
+int qmc_create_integrand(qmc_context* ctx, const qmc_integrand_desc* desc, qmc_integrand** out);
+
+/* Free; QMC_EBUSY while a pending request references it. */
+int qmc_destroy_integrand(qmc_integrand* f);
+
+/*
+ * Set the variance-reduction map (Sec. 2.4, eq. ISfit in the PolySingular
+ * form of App. A.5): params[6*j + 0..5] = (p0..p5) for dimension j, with
+ * p0 >= 1.001 and p1 <= -0.001.  NULL switches the map off.
+ */
+int qmc_set_vr(qmc_integrand* f, const double* params);
+
+/* ---------------------------------------------------------------- transforms */
+enum { QMC_T_NONE = 0, QMC_T_KOROBOV = 1, QMC_T_BAKER = 2 };
+
+/* Korobov<r0,r1> (eq. korobov, 0 <= r0, r1 <= 12), baker (eq. baker), none. */
+typedef struct {
+  int32_t kind;
+  int32_t r0, r1;
+} qmc_transform;
+
+/* ---------------------------------------------------------------- results */
+enum {
+  QMC_CONVERGED = 1u,   /* error goal met */
+  QMC_MAXEVAL_HIT = 2u, /* stopped by max_evals or the end of the lattice table */
+  QMC_NONFINITE = 4u,   /* some contributions were not finite */
+  QMC_VR_FALLBACK = 8u, /* a fitted VR map was rejected; identity used */
+  QMC_DEFORM_SIGN = 16u /* some points had Im F(z) > 0 (reported only) */
+};
+
+enum { QMC_ERRMODE_ALL = 0, QMC_ERRMODE_LARGEST = 1 };
+
+/* Mirrors the paper's result struct (App. A.2): integral, error, n, m,
+ * iterations, evaluations; plus status flags and timings. */
+typedef struct {
+  double re, im;          /* estimate; im = 0 for real integrands */
+  double err_re, err_im;  /* sqrt of eq. lattice-error per component; +inf if m = 1 */
+  uint64_t n;             /* lattice size of the returned (last) iteration */
+  uint32_t m;             /* shifts */
+  uint32_t iterations;    /* lattices evaluated (earlier ones discarded) */
+  uint64_t evaluations;   /* total integrand evaluations over all iterations */
+  uint32_t flags;         /* QMC_CONVERGED | ... */
+  uint32_t reserved;
+  uint64_t nonfinite;     /* contributions that were NaN or +-inf (last iteration) */
+  double device_seconds;  /* summed duration of the evaluation kernels (HIP events) */
+  double queue_seconds;   /* submit-to-start wait (serving); 0 otherwise */
+  double wall_seconds;    /* host wall time of the request */
+} qmc_result;
+
+/*
+ * One integration.  dim must equal the integrand's dim; gcd(z_j, n) = 1;
+ * 2 <= n < 2^53; 1 <= m <= QMC_MAX_SHIFTS.  Shifts are drawn from
+ * SplitMix64(seed) (see qmc_shifts).
+ * rel_tol <= 0: exactly this lattice (the paper's "Case 2", Sec. 3.3.2).
+ * rel_tol > 0:  grow n through the registered table until the error goal
+ *               (errormode "largest" for complex results) is met, as in the
+ *               paper's "Case 1" (Sec. 3.3.1); only the last lattice counts.
+ * shift_sums: optional host [m] (real) or [2m] (complex: re[0..m) then
+ * im[0..m)) receiving the raw per-shift sums sum_k w f of the last lattice.
+ */
+int qmc_integrate(qmc_context* ctx, const qmc_integrand* f, uint32_t dim, uint64_t n,
+                  const uint64_t* z, uint32_t m, uint64_t seed, qmc_transform t, double rel_tol,
+                  qmc_result* out, double* shift_sums);
+
+/* Full request: the paper's epsrel/epsabs/maxeval/errormode (App. A.1). */
+typedef struct {
+  const qmc_integrand* f;
+  uint64_t n;            /* first lattice size (minn, rounded up through the table if z == NULL) */
+  const uint64_t* z;     /* host [dim] generating vector for n, or NULL = from the table */
+  uint32_t m;            /* shifts (minm) */
+  uint32_t errormode;    /* QMC_ERRMODE_ALL or QMC_ERRMODE_LARGEST (complex only) */
+  uint64_t seed;
+  qmc_transform t;
+  double rel_tol, abs_tol; /* both <= 0: one lattice only */
+  uint64_t max_evals;      /* 0 = unlimited */
+} qmc_request;
+
+/* Run `count` requests; results in out[count]. shift_sums (optional) gets
+ * each request's per-shift sums back to back ([m] or [2m] each). */
+int qmc_integrate_batch(qmc_context* ctx, const qmc_request* reqs, uint32_t count,
+                        qmc_result* out, double* shift_sums);
+
+/* ---------------------------------------------------------------- debug / parity */
+
+/* The shifts SplitMix64(seed) gives: out[s*dim + j], s < m, j < dim; each
+ * value is (x >> 11) * 2^-53 of the next 64-bit output, shift-major. Host only. */
+int qmc_shifts(uint64_t seed, uint32_t m, uint32_t dim, double* out);
+
+/* Lattice indices (k z_j) mod n for k in [k0, k0+count), computed by the
+ * device index path (start index, then strided increments): out[i*dim + j]. */
+int qmc_lattice_indices(qmc_context* ctx, uint64_t n, uint32_t dim, const uint64_t* z, uint64_t k0,
+                        uint64_t count, uint64_t* out);
+
+/* Raw per-shift sums over points k in [k0, k1) (a parity unit for large n). */
+int qmc_shift_sums_range(qmc_context* ctx, const qmc_integrand* f, uint64_t n, const uint64_t* z,
+                         uint32_t m, uint64_t seed, qmc_transform t, uint64_t k0, uint64_t k1,
+                         double* shift_sums, uint64_t* nonfinite);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QMC_H */

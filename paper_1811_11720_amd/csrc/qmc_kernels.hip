@@ -1,0 +1,110 @@
+// qmc_kernels.hip -- ahead-of-time gfx950 kernels of the lattice integrator.
+//
+// k_eval_real   fused index -> shift -> transform -> [VR] -> U^a F^b -> per-shift
+//               block partials (Sec. 2.1 eq. lattice; Sec. 2.3; Sec. 2.4)
+// k_finalize    fixed-order sum of the block partials of each shift
+// k_indices     the evaluation kernels' index path, exposed for exact checks
+#include "qmc_internal.h"
+
+namespace qmck {
+
+template <int DMAX, int TK, bool IDX32>
+__global__ __launch_bounds__(QMCD_BLOCK) void k_eval_real(qmcd::EvalArgs a) {
+  qmcd::eval_real_body<DMAX, TK, IDX32, S_REAL>(a);
+}
+
+}  // namespace qmck
+
+namespace qmck {
+
+using EvalFn = void (*)(qmcd::EvalArgs);
+
+#define QMC_ROW(D)                                                                               \
+  {                                                                                              \
+    {k_eval_real<D, qmcd::TK_NONE, false>, k_eval_real<D, qmcd::TK_NONE, true>},                 \
+        {k_eval_real<D, qmcd::TK_KOROBOV, false>, k_eval_real<D, qmcd::TK_KOROBOV, true>},       \
+        {k_eval_real<D, qmcd::TK_BAKER, false>, k_eval_real<D, qmcd::TK_BAKER, true>},           \
+        {k_eval_real<D, qmcd::TK_KOROBOV3, false>, k_eval_real<D, qmcd::TK_KOROBOV3, true>},                                 \
+  }
+
+static EvalFn g_real[4][4][2] = {QMC_ROW(4), QMC_ROW(8), QMC_ROW(12), QMC_ROW(16)};
+#undef QMC_ROW
+
+hipError_t launch_eval_real(const qmcd::EvalArgs& a, int dclass, int tsel, bool idx32, dim3 grid,
+                            hipStream_t st) {
+  EvalFn fn = g_real[dclass][tsel][idx32 ? 1 : 0];
+  qmcd::EvalArgs copy = a;
+  void* args[] = {&copy};
+  return hipLaunchKernel((const void*)fn, grid, dim3(QMCD_BLOCK), args, 0, st);
+}
+
+__global__ __launch_bounds__(QMCD_BLOCK) void k_finalize(const double* __restrict__ partial, uint32_t nblocks,
+                                                         double* __restrict__ out) {
+  const double* p = partial + (size_t)blockIdx.x * nblocks;
+  double t = 0.0;
+  for (uint32_t i = threadIdx.x; i < nblocks; i += QMCD_BLOCK) t += p[i];
+  t = qmcd::wave_sum(t);
+  __shared__ double red[QMCD_BLOCK / 64];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < QMCD_BLOCK / 64; ++w) s += red[w];
+    out[blockIdx.x] = s;
+  }
+}
+
+hipError_t launch_finalize(const double* partial, uint32_t nblocks, uint32_t rows, double* out,
+                           hipStream_t st) {
+  if (rows == 0) return hipSuccess;
+  void* args[] = {(void*)&partial, (void*)&nblocks, (void*)&out};
+  return hipLaunchKernel((const void*)k_finalize, dim3(rows), dim3(QMCD_BLOCK), args, 0, st);
+}
+
+struct IndexArgs {
+  uint64_t n, k0, count, stride;
+  uint32_t dim, idx32;
+  uint64_t z[QMCD_MAXD];
+  uint64_t step[QMCD_MAXD];
+  uint64_t* out;
+};
+
+// Same start-then-step index sequence as the evaluation kernels.
+__global__ __launch_bounds__(QMCD_BLOCK) void k_indices(IndexArgs a) {
+  uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.count || t >= a.stride) return;
+  uint64_t r[QMCD_MAXD];
+  for (uint32_t j = 0; j < a.dim; ++j) r[j] = qmcd::start_index(a.k0 + t, a.z[j], a.n);
+  for (uint64_t i = t; i < a.count; i += a.stride) {
+    for (uint32_t j = 0; j < a.dim; ++j) {
+      a.out[i * a.dim + j] = r[j];
+      r[j] = a.idx32 ? qmcd::step_u32((uint32_t)r[j], (uint32_t)a.step[j], (uint32_t)a.n)
+                     : qmcd::step_u64(r[j], a.step[j], a.n);
+    }
+  }
+}
+
+static uint64_t mulmod_host(uint64_t a, uint64_t b, uint64_t n) {
+  return (uint64_t)(((unsigned __int128)a * b) % n);
+}
+
+hipError_t launch_indices(uint64_t n, uint32_t dim, const uint64_t* z_host, uint64_t k0, uint64_t count,
+                          uint32_t threads, uint64_t* out, hipStream_t st) {
+  IndexArgs a{};
+  a.n = n;
+  a.k0 = k0;
+  a.count = count;
+  a.stride = threads;
+  a.dim = dim;
+  a.idx32 = n <= (1ull << 31) ? 1u : 0u;
+  for (uint32_t j = 0; j < dim; ++j) {
+    a.z[j] = z_host[j] % n;
+    a.step[j] = mulmod_host(threads % n, a.z[j], n);
+  }
+  a.out = out;
+  uint32_t blocks = (threads + QMCD_BLOCK - 1) / QMCD_BLOCK;
+  void* args[] = {&a};
+  return hipLaunchKernel((const void*)k_indices, dim3(blocks), dim3(QMCD_BLOCK), args, 0, st);
+}
+
+}  // namespace qmck

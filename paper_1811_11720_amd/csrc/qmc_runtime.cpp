@@ -1,0 +1,653 @@
+// qmc_runtime.cpp -- host runtime behind include/qmc.h.
+//
+// Holds contexts (device, stream, scratch), integrand descriptors resident on
+// the device, the registered lattice table, and the host side of the method:
+// SplitMix64 shifts, launch planning, the estimate and error of eq.
+// lattice-error (Sec. 2.1) from the device's per-shift sums, and the Case-1
+// growth loop of Sec. 3.3.1 (discard and move to a larger lattice until the
+// goal or maxeval is met).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "qmc.h"
+#include "qmc_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(call)                                                                              \
+  do {                                                                                            \
+    hipError_t e_ = (call);                                                                       \
+    if (e_ != hipSuccess) return fail(QMC_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+uint64_t splitmix64_next(uint64_t& s) {
+  uint64_t z = (s += 0x9e3779b97f4a7c15ULL);
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+  return z ^ (z >> 31);
+}
+
+void make_shifts(uint64_t seed, uint32_t m, uint32_t dim, double* out) {
+  uint64_t s = seed;
+  for (uint64_t i = 0; i < (uint64_t)m * dim; ++i) out[i] = (double)(splitmix64_next(s) >> 11) * 0x1.0p-53;
+}
+
+uint64_t gcd_u64(uint64_t a, uint64_t b) {
+  while (b) {
+    uint64_t t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+uint64_t mulmod(uint64_t a, uint64_t b, uint64_t n) { return (uint64_t)(((unsigned __int128)a * b) % n); }
+
+double binom(int a, int b) {
+  double c = 1.0;
+  for (int i = 1; i <= b; ++i) c = c * (double)(a - b + i) / (double)i;
+  return c;
+}
+
+}  // namespace
+
+struct qmc_context {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  // scratch: caller workspace or library-owned
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool own_ws = false;
+  // pinned host staging
+  double* h_stage = nullptr;
+  size_t h_stage_bytes = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  std::map<uint64_t, std::vector<uint64_t>> lattices;
+  std::recursive_mutex mu;
+  int inflight = 0;
+  bool broken = false;
+  int max_blocks = 1024;
+};
+
+struct qmc_integrand {
+  qmc_context* ctx = nullptr;
+  uint32_t dim = 0, n_u = 0, n_f = 0, flags = 0;
+  double pow_u = 1, pow_f = 1, prefactor = 1, lambda = 0;
+  int pu_mode = 0, pu_k = 0, pf_mode = 0, pf_k = 0;
+  std::vector<double> coef;
+  std::vector<uint8_t> expo;
+  bool has_vr = false;
+  std::vector<double> vr;
+  char* dmem = nullptr;  // coef | expo (u32 x 2 per monomial) | vr
+  double* d_coef = nullptr;
+  uint32_t* d_expo = nullptr;
+  double* d_vr = nullptr;
+  int refs = 0;
+};
+
+namespace {
+
+void classify_power(double p, int& mode, int& k) {
+  if (p == 0.0) {
+    mode = qmcd::PW_ONE;
+    k = 0;
+  } else if (p == std::floor(p) && std::fabs(p) <= 64) {
+    mode = qmcd::PW_INT;
+    k = (int)p;
+  } else if (p - 0.5 == std::floor(p - 0.5) && std::fabs(p) <= 64) {
+    mode = qmcd::PW_HALF;
+    k = (int)std::floor(p);
+  } else {
+    mode = qmcd::PW_GEN;
+    k = 0;
+  }
+}
+
+// carve `bytes` (256-aligned) from the context scratch, growing it if owned
+int scratch(qmc_context* c, size_t need, char** out) {
+  need = (need + 255) & ~(size_t)255;
+  if (need > c->ws_bytes) {
+    if (!c->own_ws)
+      return fail(QMC_ENOMEM, "workspace of %zu bytes is smaller than the %zu bytes needed", c->ws_bytes, need);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (c->ws) HIPCHK(hipFree(c->ws));
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+    size_t nb = std::max(need, (size_t)1 << 22);
+    hipError_t e = hipMalloc((void**)&c->ws, nb);
+    if (e != hipSuccess) return fail(QMC_ENOMEM, "hipMalloc(%zu) failed: %s", nb, hipGetErrorString(e));
+    c->ws_bytes = nb;
+  }
+  *out = c->ws;
+  return QMC_OK;
+}
+
+int stage(qmc_context* c, size_t bytes) {
+  if (bytes <= c->h_stage_bytes) return QMC_OK;
+  if (c->h_stage) HIPCHK(hipHostFree(c->h_stage));
+  c->h_stage = nullptr;
+  size_t nb = std::max(bytes, (size_t)1 << 16);
+  HIPCHK(hipHostMalloc((void**)&c->h_stage, nb, hipHostMallocDefault));
+  c->h_stage_bytes = nb;
+  return QMC_OK;
+}
+
+int check_lattice(uint64_t n, uint32_t dim, const uint64_t* z) {
+  if (n < 2 || n >= (1ull << 53)) return fail(QMC_EINVAL, "lattice size n=%llu outside [2, 2^53)", (unsigned long long)n);
+  if (!z) return fail(QMC_EINVAL, "generating vector is NULL");
+  for (uint32_t j = 0; j < dim; ++j) {
+    if (z[j] == 0 || gcd_u64(z[j] % n, n) != 1)
+      return fail(QMC_EINVAL, "z[%u]=%llu is not coprime to n=%llu", j, (unsigned long long)z[j], (unsigned long long)n);
+  }
+  return QMC_OK;
+}
+
+int set_transform(qmcd::EvalArgs& a, const qmc_transform& t, int& tsel) {
+  a.r0 = a.r1 = a.deg_phi = a.deg_om = a.sym = 0;
+  if (t.kind == QMC_T_NONE) {
+    tsel = qmck::TSEL_NONE;
+  } else if (t.kind == QMC_T_BAKER) {
+    tsel = qmck::TSEL_BAKER;
+  } else if (t.kind == QMC_T_KOROBOV) {
+    if (t.r0 < 0 || t.r1 < 0 || t.r0 > 12 || t.r1 > 12)
+      return fail(QMC_EINVAL, "Korobov weights r0=%d r1=%d outside [0, 12]", t.r0, t.r1);
+    tsel = (t.r0 == 3 && t.r1 == 3) ? qmck::TSEL_KOROBOV3 : qmck::TSEL_KOROBOV;
+    // omega(v) = C v^r0 (1-v)^r1, C = (r0+r1+1) binom(r0+r1, r0)   (eq. korobov)
+    double C = (double)(t.r0 + t.r1 + 1) * binom(t.r0 + t.r1, t.r0);
+    a.r0 = t.r0;
+    a.r1 = t.r1;
+    a.deg_om = t.r1;
+    a.deg_phi = t.r1;
+    a.sym = t.r0 == t.r1 ? 1 : 0;
+    for (int i = 0; i <= t.r1; ++i) {
+      double b = C * binom(t.r1, i) * ((i & 1) ? -1.0 : 1.0);
+      a.om_c[i] = b;
+      a.phi_c[i] = b / (double)(t.r0 + 1 + i);  // phi = int_0^v omega
+    }
+  } else {
+    return fail(QMC_EINVAL, "unknown transform kind %d", t.kind);
+  }
+  return QMC_OK;
+}
+
+struct LatticeRun {
+  std::vector<double> sums;  // rows (m or 2m)
+  double kernel_seconds = 0;
+};
+
+// One lattice (n, z), m shifts from `shift_tab`, points [k0, k1): per-shift sums.
+int run_lattice(qmc_context* c, const qmc_integrand* f, uint64_t n, const uint64_t* z, uint32_t m,
+                const double* shift_tab, const qmc_transform& t, uint64_t k0, uint64_t k1, LatticeRun& out) {
+  if (f->flags & QMC_DEFORM) return fail(QMC_EUNSUPPORTED, "complex (deformed) integrands are not enabled");
+  qmcd::EvalArgs a;
+  std::memset(&a, 0, sizeof a);
+  int tsel = 0;
+  int rc = set_transform(a, t, tsel);
+  if (rc) return rc;
+  const uint32_t dim = f->dim;
+  const uint32_t rows = m;
+  uint64_t npts = k1 - k0;
+  uint32_t nb = (uint32_t)std::min<uint64_t>((npts + QMCD_BLOCK - 1) / QMCD_BLOCK, (uint64_t)c->max_blocks);
+  if (nb == 0) nb = 1;
+  const uint32_t groups = (m + qmck::S_REAL - 1) / qmck::S_REAL;
+  size_t off_sh = 0, sz_sh = (size_t)m * dim * sizeof(double);
+  size_t off_part = (sz_sh + 255) & ~(size_t)255, sz_part = (size_t)rows * nb * sizeof(double);
+  size_t off_out = (off_part + sz_part + 255) & ~(size_t)255, sz_out = rows * sizeof(double);
+  char* ws = nullptr;
+  rc = scratch(c, off_out + sz_out, &ws);
+  if (rc) return rc;
+  rc = stage(c, std::max(sz_sh, sz_out));
+  if (rc) return rc;
+  std::memcpy(c->h_stage, shift_tab, sz_sh);
+  HIPCHK(hipMemcpyAsync(ws + off_sh, c->h_stage, sz_sh, hipMemcpyHostToDevice, c->stream));
+
+  a.n = n;
+  a.n_d = (double)n;
+  a.inv_n = 1.0 / (double)n;
+  a.k_begin = k0;
+  a.k_end = k1;
+  a.stride = (uint64_t)nb * QMCD_BLOCK;
+  for (uint32_t j = 0; j < dim; ++j) {
+    a.z[j] = z[j] % n;
+    a.step[j] = mulmod(a.stride % n, a.z[j], n);
+  }
+  a.dim = dim;
+  a.m = m;
+  a.shifts = (const double*)(ws + off_sh);
+  a.partial = (double*)(ws + off_part);
+  a.nblocks = nb;
+  a.coef = f->d_coef;
+  a.expo = f->d_expo;
+  a.n_u = f->n_u;
+  a.n_f = f->n_f;
+  a.pu_mode = f->pu_mode;
+  a.pu_k = f->pu_k;
+  a.pf_mode = f->pf_mode;
+  a.pf_k = f->pf_k;
+  a.pow_u = f->pow_u;
+  a.pow_f = f->pow_f;
+  a.prefactor = f->prefactor;
+  a.lambda = f->lambda;
+  a.vr = f->has_vr ? f->d_vr : nullptr;
+  const bool idx32 = n <= (1ull << 31);
+  HIPCHK(hipEventRecord(c->ev0, c->stream));
+  HIPCHK(qmck::launch_eval_real(a, qmck::dim_class(dim), tsel, idx32, dim3(nb, groups), c->stream));
+  HIPCHK(hipEventRecord(c->ev1, c->stream));
+  HIPCHK(qmck::launch_finalize(a.partial, nb, rows, (double*)(ws + off_out), c->stream));
+  HIPCHK(hipMemcpyAsync(c->h_stage, ws + off_out, sz_out, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  float ms = 0;
+  HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  out.kernel_seconds = ms * 1e-3;
+  out.sums.assign(c->h_stage, c->h_stage + rows);
+  return QMC_OK;
+}
+
+void estimate(const double* q, uint32_t m, double& mean, double& err) {
+  // eq. lattice-error: sigma^2 = sum (Q_s - Qbar)^2 / (m (m-1))
+  double s = 0.0;
+  for (uint32_t i = 0; i < m; ++i) s += q[i];
+  mean = s / m;
+  if (m < 2) {
+    err = INFINITY;
+    return;
+  }
+  double v = 0.0;
+  for (uint32_t i = 0; i < m; ++i) v += (q[i] - mean) * (q[i] - mean);
+  err = std::sqrt(v / ((double)m * (m - 1)));
+}
+
+bool goal_met(const qmc_result& r, double rel, double abs_, uint32_t mode, bool cplx) {
+  if (!cplx) return r.err_re <= std::max(abs_, rel * std::fabs(r.re));
+  if (mode == QMC_ERRMODE_ALL)
+    return r.err_re <= std::max(abs_, rel * std::fabs(r.re)) && r.err_im <= std::max(abs_, rel * std::fabs(r.im));
+  return std::max(r.err_re, r.err_im) <= std::max(abs_, rel * std::max(std::fabs(r.re), std::fabs(r.im)));
+}
+
+int next_registered(qmc_context* c, uint64_t want, uint32_t dim, uint64_t* n_out, bool allow_smaller) {
+  uint64_t best = 0, largest = 0;
+  for (auto& kv : c->lattices) {
+    if (kv.second.size() < dim) continue;
+    largest = std::max(largest, kv.first);
+    if (kv.first >= want && (best == 0 || kv.first < best)) best = kv.first;
+  }
+  if (best) {
+    *n_out = best;
+    return QMC_OK;
+  }
+  if (allow_smaller && largest) {
+    *n_out = largest;
+    return QMC_OK;
+  }
+  return QMC_ENOTFOUND;
+}
+
+int integrate_request(qmc_context* c, const qmc_request& q, qmc_result* out, double* shift_sums) {
+  auto t0 = std::chrono::steady_clock::now();
+  const qmc_integrand* f = q.f;
+  if (!f) return fail(QMC_EINVAL, "request has no integrand");
+  if (f->ctx != c) return fail(QMC_EINVAL, "integrand belongs to another context");
+  const uint32_t dim = f->dim, m = q.m;
+  if (m < 1 || m > QMC_MAX_SHIFTS) return fail(QMC_EINVAL, "m=%u outside [1, %d]", m, QMC_MAX_SHIFTS);
+  const bool cplx = (f->flags & QMC_DEFORM) != 0;
+  const bool grow = q.rel_tol > 0 || q.abs_tol > 0;
+  uint64_t n = q.n;
+  std::vector<uint64_t> z;
+  if (q.z) {
+    int rc = check_lattice(n, dim, q.z);
+    if (rc) return rc;
+    z.assign(q.z, q.z + dim);
+  } else {
+    uint64_t nn = 0;
+    if (next_registered(c, n, dim, &nn, true) != QMC_OK)
+      return fail(QMC_ENOTFOUND, "no registered lattice with %u components", dim);
+    n = nn;
+    z.assign(c->lattices[n].begin(), c->lattices[n].begin() + dim);
+  }
+  std::vector<double> sh((size_t)m * dim);
+  make_shifts(q.seed, m, dim, sh.data());
+  qmc_result r;
+  std::memset(&r, 0, sizeof r);
+  r.m = m;
+  double dev = 0;
+  LatticeRun run;
+  while (true) {
+    int rc = run_lattice(c, f, n, z.data(), m, sh.data(), q.t, 0, n, run);
+    if (rc) return rc;
+    dev += run.kernel_seconds;
+    r.iterations += 1;
+    r.evaluations += n * (uint64_t)m;
+    r.n = n;
+    std::vector<double> qs(m);
+    for (uint32_t s = 0; s < m; ++s) qs[s] = run.sums[s] / (double)n;
+    estimate(qs.data(), m, r.re, r.err_re);
+    r.im = 0;
+    r.err_im = 0;
+    if (cplx) {
+      for (uint32_t s = 0; s < m; ++s) qs[s] = run.sums[m + s] / (double)n;
+      estimate(qs.data(), m, r.im, r.err_im);
+    }
+    r.flags &= ~(uint32_t)QMC_NONFINITE;
+    bool finite = std::isfinite(r.re) && std::isfinite(r.im);
+    if (!finite) r.flags |= QMC_NONFINITE;
+    if (!grow) break;
+    if (finite && goal_met(r, q.rel_tol, q.abs_tol, q.errormode, cplx)) {
+      r.flags |= QMC_CONVERGED;
+      break;
+    }
+    // next size: assume err ~ 1/n (reading of Sec. 3.3.1; see design notes)
+    double goal = std::max(q.abs_tol, q.rel_tol * (cplx ? std::max(std::fabs(r.re), std::fabs(r.im)) : std::fabs(r.re)));
+    double err = cplx ? std::max(r.err_re, r.err_im) : r.err_re;
+    double want = std::max(1.5 * (double)n, goal > 0 && std::isfinite(err) ? (double)n * err / goal : 2.0 * n);
+    uint64_t nn = 0;
+    uint64_t wantu = want >= 9.0e15 ? (uint64_t)9.0e15 : (uint64_t)std::ceil(want);
+    if (next_registered(c, wantu, dim, &nn, false) != QMC_OK ||
+        (q.max_evals && r.evaluations + nn * (uint64_t)m > q.max_evals)) {
+      r.flags |= QMC_MAXEVAL_HIT;
+      break;
+    }
+    n = nn;
+    z.assign(c->lattices[n].begin(), c->lattices[n].begin() + dim);
+  }
+  r.device_seconds = dev;
+  r.wall_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (out) *out = r;
+  if (shift_sums) std::memcpy(shift_sums, run.sums.data(), run.sums.size() * sizeof(double));
+  return QMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* qmc_last_error(void) { return g_err.c_str(); }
+
+int qmc_version(void) { return 100; }
+
+int qmc_context_create(int device, void* hip_stream, void* workspace, size_t workspace_bytes, qmc_context** out) {
+  if (!out) return fail(QMC_EINVAL, "out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return fail(QMC_EUNSUPPORTED, "no HIP device");
+  if (device < 0 || device >= ndev) return fail(QMC_EINVAL, "device %d outside [0, %d)", device, ndev);
+  HIPCHK(hipSetDevice(device));
+  qmc_context* c = new qmc_context();
+  c->device = device;
+  if (hip_stream) {
+    c->stream = (hipStream_t)hip_stream;
+  } else {
+    hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      delete c;
+      return fail(QMC_EDEVICE, "hipStreamCreate failed: %s", hipGetErrorString(e));
+    }
+    c->own_stream = true;
+  }
+  if (workspace) {
+    c->ws = (char*)workspace;
+    c->ws_bytes = workspace_bytes;
+    c->own_ws = false;
+  } else {
+    c->own_ws = true;
+  }
+  if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+    delete c;
+    return fail(QMC_EDEVICE, "hipEventCreate failed");
+  }
+  if (const char* mb = std::getenv("QMC_MAX_BLOCKS")) c->max_blocks = std::max(1, atoi(mb));
+  *out = c;
+  return QMC_OK;
+}
+
+int qmc_context_destroy(qmc_context* c) {
+  if (!c) return QMC_OK;
+  {
+    std::lock_guard<std::recursive_mutex> g(c->mu);
+    if (c->inflight) return fail(QMC_EBUSY, "context has %d requests in flight", c->inflight);
+  }
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  if (c->own_ws && c->ws) (void)hipFree(c->ws);
+  if (c->h_stage) (void)hipHostFree(c->h_stage);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  if (c->own_stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+  return QMC_OK;
+}
+
+int qmc_register_lattice(qmc_context* c, uint64_t n, uint32_t dim, const uint64_t* z) {
+  if (!c) return fail(QMC_EINVAL, "context is NULL");
+  if (dim < 1 || dim > 1024) return fail(QMC_EINVAL, "dim=%u", dim);
+  int rc = check_lattice(n, dim, z);
+  if (rc) return rc;
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  c->lattices[n] = std::vector<uint64_t>(z, z + dim);
+  return QMC_OK;
+}
+
+int qmc_next_lattice(qmc_context* c, uint64_t preferred_n, uint32_t dim, uint64_t* n_out) {
+  if (!c || !n_out) return fail(QMC_EINVAL, "NULL argument");
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  if (next_registered(c, preferred_n, dim, n_out, true) != QMC_OK)
+    return fail(QMC_ENOTFOUND, "no registered lattice with %u components", dim);
+  return QMC_OK;
+}
+
+int qmc_create_integrand(qmc_context* c, const qmc_integrand_desc* d, qmc_integrand** out) {
+  if (!c || !d || !out) return fail(QMC_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (d->dim < 1 || d->dim > QMC_MAX_DIM) return fail(QMC_EINVAL, "dim=%u outside [1, %d]", d->dim, QMC_MAX_DIM);
+  if (d->n_u < 1) return fail(QMC_EINVAL, "U needs at least one monomial");
+  uint32_t nm = d->n_u + d->n_f;
+  if (nm > QMC_MAX_MONOMIALS) return fail(QMC_EINVAL, "%u monomials exceed %d", nm, QMC_MAX_MONOMIALS);
+  if (!d->coef || !d->expo) return fail(QMC_EINVAL, "coef/expo is NULL");
+  for (uint32_t i = 0; i < nm; ++i)
+    if (!std::isfinite(d->coef[i])) return fail(QMC_EINVAL, "coef[%u] is not finite", i);
+  for (size_t i = 0; i < (size_t)nm * d->dim; ++i)
+    if (d->expo[i] > QMC_MAX_EXP) return fail(QMC_EINVAL, "exponent %u exceeds %d", d->expo[i], QMC_MAX_EXP);
+  if (!std::isfinite(d->pow_u) || !std::isfinite(d->pow_f) || !std::isfinite(d->prefactor))
+    return fail(QMC_EINVAL, "powers and prefactor must be finite");
+  if ((d->flags & QMC_DEFORM) && !std::isfinite(d->lambda)) return fail(QMC_EINVAL, "lambda must be finite");
+  if (d->flags & ~(uint32_t)(QMC_DEFORM | QMC_EVAL_FP32)) return fail(QMC_EINVAL, "unknown flags 0x%x", d->flags);
+  qmc_integrand* f = new qmc_integrand();
+  f->ctx = c;
+  f->dim = d->dim;
+  f->n_u = d->n_u;
+  f->n_f = d->n_f;
+  f->flags = d->flags;
+  f->pow_u = d->pow_u;
+  f->pow_f = d->pow_f;
+  f->prefactor = d->prefactor;
+  f->lambda = (d->flags & QMC_DEFORM) ? d->lambda : 0.0;
+  classify_power(f->pow_u, f->pu_mode, f->pu_k);
+  classify_power(f->n_f ? f->pow_f : 0.0, f->pf_mode, f->pf_k);
+  f->coef.assign(d->coef, d->coef + nm);
+  f->expo.assign(d->expo, d->expo + (size_t)nm * d->dim);
+  std::vector<uint32_t> packed((size_t)nm * 2, 0);
+  for (uint32_t i = 0; i < nm; ++i)
+    for (uint32_t j = 0; j < d->dim; ++j)
+      packed[2 * i + j / 8] |= (uint32_t)d->expo[(size_t)i * d->dim + j] << (4 * (j % 8));
+  size_t b_coef = ((size_t)nm * 8 + 255) & ~(size_t)255;
+  size_t b_expo = ((size_t)nm * 8 + 255) & ~(size_t)255;
+  size_t b_vr = ((size_t)d->dim * 6 * 8 + 255) & ~(size_t)255;
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  (void)hipSetDevice(c->device);
+  hipError_t e = hipMalloc((void**)&f->dmem, b_coef + b_expo + b_vr);
+  if (e != hipSuccess) {
+    delete f;
+    return fail(QMC_ENOMEM, "hipMalloc for the descriptor failed: %s", hipGetErrorString(e));
+  }
+  f->d_coef = (double*)f->dmem;
+  f->d_expo = (uint32_t*)(f->dmem + b_coef);
+  f->d_vr = (double*)(f->dmem + b_coef + b_expo);
+  e = hipMemcpy(f->d_coef, f->coef.data(), nm * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(f->d_expo, packed.data(), (size_t)nm * 8, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(f->dmem);
+    delete f;
+    return fail(QMC_EDEVICE, "descriptor upload failed: %s", hipGetErrorString(e));
+  }
+  *out = f;
+  return QMC_OK;
+}
+
+int qmc_destroy_integrand(qmc_integrand* f) {
+  if (!f) return QMC_OK;
+  if (f->refs) return fail(QMC_EBUSY, "integrand referenced by %d pending requests", f->refs);
+  std::lock_guard<std::recursive_mutex> g(f->ctx->mu);
+  (void)hipSetDevice(f->ctx->device);
+  (void)hipStreamSynchronize(f->ctx->stream);
+  if (f->dmem) (void)hipFree(f->dmem);
+  delete f;
+  return QMC_OK;
+}
+
+int qmc_set_vr(qmc_integrand* f, const double* params) {
+  if (!f) return fail(QMC_EINVAL, "integrand is NULL");
+  if (!params) {
+    f->has_vr = false;
+    return QMC_OK;
+  }
+  for (uint32_t j = 0; j < f->dim; ++j) {
+    const double* p = params + 6 * j;
+    for (int i = 0; i < 6; ++i)
+      if (!std::isfinite(p[i])) return fail(QMC_EINVAL, "VR parameter %u.%d not finite", j, i);
+    if (p[0] < 1.001 || p[1] > -0.001)
+      return fail(QMC_EINVAL, "VR poles of dim %u inside (-0.001, 1.001): p0=%g p1=%g", j, p[0], p[1]);
+  }
+  std::lock_guard<std::recursive_mutex> g(f->ctx->mu);
+  f->vr.assign(params, params + 6 * f->dim);
+  (void)hipSetDevice(f->ctx->device);
+  (void)hipStreamSynchronize(f->ctx->stream);
+  HIPCHK(hipMemcpy(f->d_vr, f->vr.data(), f->vr.size() * 8, hipMemcpyHostToDevice));
+  f->has_vr = true;
+  return QMC_OK;
+}
+
+int qmc_integrate(qmc_context* c, const qmc_integrand* f, uint32_t dim, uint64_t n, const uint64_t* z, uint32_t m,
+                  uint64_t seed, qmc_transform t, double rel_tol, qmc_result* out, double* shift_sums) {
+  if (!c || !f) return fail(QMC_EINVAL, "NULL context or integrand");
+  if (dim != f->dim) return fail(QMC_EINVAL, "dim=%u differs from the integrand's %u", dim, f->dim);
+  qmc_request q;
+  std::memset(&q, 0, sizeof q);
+  q.f = f;
+  q.n = n;
+  q.z = z;
+  q.m = m;
+  q.seed = seed;
+  q.t = t;
+  q.rel_tol = rel_tol;
+  q.abs_tol = 0;
+  q.errormode = QMC_ERRMODE_LARGEST;
+  q.max_evals = 0;
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  if (c->broken) return fail(QMC_EDEVICE, "context is unusable after a device error");
+  HIPCHK(hipSetDevice(c->device));
+  int rc = integrate_request(c, q, out, shift_sums);
+  if (rc == QMC_EDEVICE) c->broken = true;
+  return rc;
+}
+
+int qmc_integrate_batch(qmc_context* c, const qmc_request* reqs, uint32_t count, qmc_result* out,
+                        double* shift_sums) {
+  if (!c || (!reqs && count)) return fail(QMC_EINVAL, "NULL argument");
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  if (c->broken) return fail(QMC_EDEVICE, "context is unusable after a device error");
+  HIPCHK(hipSetDevice(c->device));
+  size_t off = 0;
+  for (uint32_t i = 0; i < count; ++i) {
+    int rc = integrate_request(c, reqs[i], out ? out + i : nullptr, shift_sums ? shift_sums + off : nullptr);
+    if (rc) {
+      if (rc == QMC_EDEVICE) c->broken = true;
+      return rc;
+    }
+    off += (size_t)reqs[i].m * ((reqs[i].f->flags & QMC_DEFORM) ? 2 : 1);
+  }
+  return QMC_OK;
+}
+
+int qmc_shifts(uint64_t seed, uint32_t m, uint32_t dim, double* out) {
+  if (!out || m == 0 || dim == 0) return fail(QMC_EINVAL, "bad arguments");
+  make_shifts(seed, m, dim, out);
+  return QMC_OK;
+}
+
+int qmc_lattice_indices(qmc_context* c, uint64_t n, uint32_t dim, const uint64_t* z, uint64_t k0, uint64_t count,
+                        uint64_t* out) {
+  if (!c || !out) return fail(QMC_EINVAL, "NULL argument");
+  if (dim < 1 || dim > QMC_MAX_DIM) return fail(QMC_EINVAL, "dim=%u", dim);
+  int rc = check_lattice(n, dim, z);
+  if (rc) return rc;
+  if (k0 > n || count > n - k0) return fail(QMC_EINVAL, "range [k0, k0+count) exceeds n");
+  if (count == 0) return QMC_OK;
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  HIPCHK(hipSetDevice(c->device));
+  char* ws = nullptr;
+  size_t bytes = (size_t)count * dim * 8;
+  rc = scratch(c, bytes, &ws);
+  if (rc) return rc;
+  // fewer threads than points so that the strided increments are exercised
+  uint32_t threads = (uint32_t)std::min<uint64_t>(count, 4096);
+  HIPCHK(qmck::launch_indices(n, dim, z, k0, count, threads, (uint64_t*)ws, c->stream));
+  HIPCHK(hipMemcpyAsync(out, ws, bytes, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return QMC_OK;
+}
+
+int qmc_shift_sums_range(qmc_context* c, const qmc_integrand* f, uint64_t n, const uint64_t* z, uint32_t m,
+                         uint64_t seed, qmc_transform t, uint64_t k0, uint64_t k1, double* shift_sums,
+                         uint64_t* nonfinite) {
+  if (!c || !f || !shift_sums) return fail(QMC_EINVAL, "NULL argument");
+  if (m < 1 || m > QMC_MAX_SHIFTS) return fail(QMC_EINVAL, "m=%u", m);
+  int rc = check_lattice(n, f->dim, z);
+  if (rc) return rc;
+  if (k0 > k1 || k1 > n) return fail(QMC_EINVAL, "range [%llu, %llu) outside [0, n)", (unsigned long long)k0,
+                                     (unsigned long long)k1);
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  if (c->broken) return fail(QMC_EDEVICE, "context is unusable after a device error");
+  HIPCHK(hipSetDevice(c->device));
+  std::vector<double> sh((size_t)m * f->dim);
+  make_shifts(seed, m, f->dim, sh.data());
+  LatticeRun run;
+  if (k1 == k0) {
+    std::memset(shift_sums, 0, (size_t)m * ((f->flags & QMC_DEFORM) ? 2 : 1) * 8);
+    if (nonfinite) *nonfinite = 0;
+    return QMC_OK;
+  }
+  rc = run_lattice(c, f, n, z, m, sh.data(), t, k0, k1, run);
+  if (rc) return rc;
+  std::memcpy(shift_sums, run.sums.data(), run.sums.size() * 8);
+  if (nonfinite) {
+    uint64_t bad = 0;
+    for (double v : run.sums) bad += std::isfinite(v) ? 0 : 1;
+    *nonfinite = bad;
+  }
+  return QMC_OK;
+}
+
+}  // extern "C"
