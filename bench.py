@@ -64,17 +64,20 @@ def flops_per_eval(desc, transform) -> float:
 
 
 def cpu_baseline(job, target_seconds: float, threads: int):
+    """The oracle, as it stands, on all m shifts of a prefix [0, k) of the same
+    lattice; k grows until one run takes at least half the target time."""
     import oracle
 
     sh = oracle.shifts(job.seed, job.m, job.desc.dim)
-    k = 4096
-    t0 = time.perf_counter()
-    oracle.shift_sums(job.desc, job.n, job.z, job.m, sh, job.transform, k0=0, k1=k, threads=threads)
-    dt = time.perf_counter() - t0
-    k = int(min(job.n, max(k, k * target_seconds / max(dt, 1e-6))))
-    t0 = time.perf_counter()
-    oracle.shift_sums(job.desc, job.n, job.z, job.m, sh, job.transform, k0=0, k1=k, threads=threads)
-    dt = time.perf_counter() - t0
+    k = 8192
+    oracle.shift_sums(job.desc, job.n, job.z, job.m, sh, job.transform, k0=0, k1=k, threads=threads)  # warm
+    while True:
+        t0 = time.perf_counter()
+        oracle.shift_sums(job.desc, job.n, job.z, job.m, sh, job.transform, k0=0, k1=k, threads=threads)
+        dt = time.perf_counter() - t0
+        if dt >= 0.5 * target_seconds or k >= job.n:
+            break
+        k = int(min(job.n, max(2 * k, k * target_seconds / max(dt, 1e-6))))
     return {
         "value": k * job.m / dt,
         "unit": "evals/s",
@@ -89,7 +92,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=100000007)
     ap.add_argument("--m", type=int, default=32)
     ap.add_argument("--no-cpu", action="store_true")

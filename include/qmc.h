@@ -167,7 +167,7 @@ typedef struct {
   uint32_t iterations;    /* lattices evaluated (earlier ones discarded) */
   uint64_t evaluations;   /* total integrand evaluations over all iterations */
   uint32_t flags;         /* QMC_CONVERGED | ... */
-  uint32_t reserved;
+  uint32_t path;          /* kernels used: 0 = descriptor-interpreting, 1 = specialised to this integrand */
   uint64_t nonfinite;     /* contributions that were NaN or +-inf (last iteration) */
   double device_seconds;  /* summed duration of the evaluation kernels (HIP events) */
   double queue_seconds;   /* submit-to-start wait (serving); 0 otherwise */
@@ -222,6 +222,15 @@ int qmc_lattice_indices(qmc_context* ctx, uint64_t n, uint32_t dim, const uint64
 int qmc_shift_sums_range(qmc_context* ctx, const qmc_integrand* f, uint64_t n, const uint64_t* z,
                          uint32_t m, uint64_t seed, qmc_transform t, uint64_t k0, uint64_t k1,
                          double* shift_sums, uint64_t* nonfinite);
+
+/*
+ * Generate and compile (hiprtc, gfx950) the evaluation kernel specialised to
+ * descriptor d and transform t, without loading it; needs no GPU.  Large
+ * integrations use such kernels automatically (qmc_result.path = 1).
+ * code_bytes (optional) receives the code-object size.  QMC_EINVAL with the
+ * compiler log in qmc_last_error() if generation or compilation fails.
+ */
+int qmc_specialize_check(const qmc_integrand_desc* d, qmc_transform t, size_t* code_bytes);
 
 #ifdef __cplusplus
 }

@@ -68,7 +68,7 @@ class Result(C.Structure):
         ("iterations", C.c_uint32),
         ("evaluations", C.c_uint64),
         ("flags", C.c_uint32),
-        ("reserved", C.c_uint32),
+        ("path", C.c_uint32),
         ("nonfinite", C.c_uint64),
         ("device_seconds", C.c_double),
         ("queue_seconds", C.c_double),
@@ -76,7 +76,7 @@ class Result(C.Structure):
     ]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class Request(C.Structure):
@@ -116,6 +116,7 @@ def _declare(L):
         "qmc_lattice_indices": ([vp, C.c_uint64, C.c_uint32, up, C.c_uint64, C.c_uint64, up], C.c_int),
         "qmc_shift_sums_range": ([vp, vp, C.c_uint64, up, C.c_uint32, C.c_uint64, Transform, C.c_uint64,
                                   C.c_uint64, dp, up], C.c_int),
+        "qmc_specialize_check": ([C.POINTER(IntegrandDesc), Transform, C.POINTER(C.c_size_t)], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -167,17 +168,31 @@ def shifts(seed: int, m: int, dim: int) -> np.ndarray:
     return out.reshape(m, dim)
 
 
+def _desc_struct(desc, keep):
+    coef = np.ascontiguousarray(desc.coef, dtype=np.float64)
+    expo = np.ascontiguousarray(desc.expo, dtype=np.uint8)
+    keep.extend([coef, expo])
+    flags = (QMC_DEFORM if getattr(desc, "deform", False) else 0) | (QMC_EVAL_FP32 if getattr(desc, "fp32", False) else 0)
+    return IntegrandDesc(desc.dim, desc.n_u, desc.n_f, _dp(coef), expo.ctypes.data_as(C.POINTER(C.c_uint8)),
+                         desc.pow_u, desc.pow_f, desc.prefactor, flags, float(getattr(desc, "lam", 0.0)))
+
+
+def specialize_check(desc, transform=(T_KOROBOV, 3, 3)) -> int:
+    """Generate and compile the specialised kernel for `desc` (host only); code bytes."""
+    keep = []
+    d = _desc_struct(desc, keep)
+    nb = C.c_size_t()
+    _check(lib().qmc_specialize_check(C.byref(d), _tr(transform), C.byref(nb)))
+    return nb.value
+
+
 class Integrand:
     def __init__(self, ctx: "Context", desc):
         self.ctx = ctx
         self.dim = int(desc.dim)
         self.complex = bool(getattr(desc, "deform", False))
-        self._coef = np.ascontiguousarray(desc.coef, dtype=np.float64)
-        self._expo = np.ascontiguousarray(desc.expo, dtype=np.uint8)
-        flags = (QMC_DEFORM if self.complex else 0) | (QMC_EVAL_FP32 if getattr(desc, "fp32", False) else 0)
-        d = IntegrandDesc(desc.dim, desc.n_u, desc.n_f, _dp(self._coef),
-                          self._expo.ctypes.data_as(C.POINTER(C.c_uint8)), desc.pow_u, desc.pow_f,
-                          desc.prefactor, flags, float(getattr(desc, "lam", 0.0)))
+        self._keep = []
+        d = _desc_struct(desc, self._keep)
         h = C.c_void_p()
         _check(lib().qmc_create_integrand(ctx.handle, C.byref(d), C.byref(h)))
         self.handle = h

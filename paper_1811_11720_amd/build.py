@@ -37,9 +37,24 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
 
+def _embed_device_source(gendir: str) -> None:
+    """qmc_device.h as a C++ raw string literal, compiled into the library so
+    the run-time specialiser can hand it to hiprtc."""
+    src = open(os.path.join(CSRC, "qmc_device.h")).read()
+    assert ")QMCSRC\"" not in src
+    out = os.path.join(gendir, "qmc_device_src.inc")
+    text = 'R"QMCSRC(' + src + ')QMCSRC"\n'
+    if not os.path.exists(out) or open(out).read() != text:
+        with open(out, "w") as fh:
+            fh.write(text)
+
+
 def build(verbose: bool = False, jobs: int = 8) -> str:
     objdir = os.path.join(ROOT, "_build", "obj")
+    gendir = os.path.join(ROOT, "_build", "gen")
     os.makedirs(objdir, exist_ok=True)
+    os.makedirs(gendir, exist_ok=True)
+    _embed_device_source(gendir)
     procs = []
     objs = []
     t0 = time.time()
@@ -47,7 +62,7 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
         obj = os.path.join(objdir, os.path.basename(src) + ".o")
         objs.append(obj)
         lang = ["-x", "hip"]
-        cmd = [HIPCC] + COMMON + lang + ["-c", src, "-o", obj]
+        cmd = [HIPCC] + COMMON + ["-I" + gendir] + lang + ["-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
@@ -64,7 +79,7 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     if failed:
         raise RuntimeError("hipcc failed")
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-lhiprtc", "-lpthread"]
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     if verbose:

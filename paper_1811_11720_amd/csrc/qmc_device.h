@@ -20,11 +20,17 @@
 //   reduction thread accumulator per shift -> wave (cross-lane) -> LDS ->
 //             partial[shift][block], all in a fixed order.
 // The index work is reused for the S shifts of the group.
-#pragma once
+#ifndef QMC_DEVICE_H
+#define QMC_DEVICE_H
 
 #ifndef QMC_RTC
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#else
+typedef unsigned long long uint64_t;
+typedef unsigned int uint32_t;
+typedef int int32_t;
+typedef unsigned char uint8_t;
 #endif
 
 #define QMCD_MAXD 16
@@ -61,6 +67,7 @@ struct EvalArgs {
   double phi_c[26];
   double om_c[26];
   const double* vr;           // [dim][6] or nullptr
+  double wscale;              // Korobov r=3: prod_j omega = wscale * (prod_j u_j (1-u_j))^3, wscale = 140^dim
 };
 
 // ------------------------------------------------------------------ indices
@@ -104,22 +111,42 @@ __device__ __forceinline__ double exact_quotient(double r, double nd, double inv
   return __builtin_fma(e, inv, q);
 }
 
+// {q + Delta} for q, Delta in [0, 1): u - floor(u) is exact on [0, 2), so it equals
+// "subtract 1 when u >= 1"; v_fract_f64 does it in one instruction
 __device__ __forceinline__ double shifted(double q, double delta) {
-  double u = q + delta;
-  return u >= 1.0 ? u - 1.0 : u;
+  return __builtin_amdgcn_fract(q + delta);
+}
+
+// 1/x and 1/sqrt(x) from the hardware estimates refined by Newton steps
+// (a few ulp; IEEE special values are not preserved: 0 and inf give NaN)
+__device__ __forceinline__ double fast_rcp(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, y, 1.0);
+  y = __builtin_fma(y, e, y);
+  e = __builtin_fma(-x, y, 1.0);
+  return __builtin_fma(y, e, y);
+}
+__device__ __forceinline__ double fast_rsqrt(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double h = 0.5 * y;
+  double t = __builtin_fma(-(x * y), h, 0.5);  // 1/2 - x y^2 / 2
+  y = __builtin_fma(y, t, y);
+  h = 0.5 * y;
+  t = __builtin_fma(-(x * y), h, 0.5);
+  return __builtin_fma(y, t, y);
 }
 
 // ------------------------------------------------------------------ transforms
 
 // Korobov r0 = r1 = 3 with the polynomial written out (eq. korobov):
 // phi(v) = v^4 (35 - 84 v + 70 v^2 - 20 v^3), omega(v) = 140 (v (1-v))^3.
-__device__ __forceinline__ double korobov3(double u, double& w) {
-  double s = __builtin_fma(-u, u, u);  // u (1-u)
+// The weight is returned as s = u (1-u); the caller multiplies 140^d (prod s)^3.
+__device__ __forceinline__ double korobov3(double u, double& s) {
+  s = __builtin_fma(-u, u, u);  // u (1-u)
   double t = __builtin_fma(-20.0, u, 70.0);
   t = __builtin_fma(t, u, -84.0);
   t = __builtin_fma(t, u, 35.0);
   double u2 = u * u;
-  w *= 140.0 * (s * s * s);
   return (u2 * u2) * t;
 }
 
@@ -128,7 +155,10 @@ __device__ __forceinline__ double transform(double u, double& w, const EvalArgs&
   if (TK == TK_NONE) {
     return u;
   } else if (TK == TK_KOROBOV3) {
-    return korobov3(u, w);
+    double sv;
+    double x = korobov3(u, sv);
+    w *= sv;  // 140^d applied once per point by the caller
+    return x;
   } else if (TK == TK_BAKER) {
     double v = 1.0 - u;  // exact for u >= 1/2
     return 2.0 * (u < v ? u : v);
@@ -211,7 +241,8 @@ __device__ __forceinline__ T poly_eval(const double* __restrict__ coef, const ui
   return s;
 }
 
-// v^p folded into num/den: integer and half-integer powers need no exp/log
+// v^p folded into num/den: integer and half-integer powers need no exp/log.
+// p = k + 1/2 with k < 0 is v^(k+1) * v^(-1/2): the refined rsqrt multiplies num.
 template <class T>
 __device__ __forceinline__ void apply_pow(T v, int mode, int k, double p, T& num, T& den) {
   if (mode == PW_ONE) return;
@@ -219,7 +250,9 @@ __device__ __forceinline__ void apply_pow(T v, int mode, int k, double p, T& num
     num *= (T)pow((double)v, p);
     return;
   }
-  int ak = k < 0 ? -k : k;
+  int kk = k;
+  if (mode == PW_HALF && k < 0) kk = k + 1;
+  int ak = kk < 0 ? -kk : kk;
   T a = T(1);
   T b = v;
   while (ak) {
@@ -227,27 +260,31 @@ __device__ __forceinline__ void apply_pow(T v, int mode, int k, double p, T& num
     b *= b;
     ak >>= 1;
   }
-  if (k >= 0)
+  if (kk >= 0)
     num *= a;
   else
     den *= a;
-  if (mode == PW_HALF) num *= __builtin_sqrt(v);
+  if (mode == PW_HALF) num *= (k < 0) ? (T)fast_rsqrt((double)v) : (T)__builtin_sqrt((double)v);
 }
 
+// Descriptor-interpreting integrand: prefactor * U^pow_u * F^pow_f with the
+// monomial table read through uniform (scalar) loads.
 template <int DMAX>
-__device__ __forceinline__ double integrand_real(const double (&x)[DMAX], const EvalArgs& a) {
-  double x2[DMAX];
+struct GenericReal {
+  __device__ __forceinline__ double operator()(const double (&x)[DMAX], const EvalArgs& a) const {
+    double x2[DMAX];
 #pragma unroll
-  for (int j = 0; j < DMAX; ++j) x2[j] = x[j] * x[j];
-  double U = poly_eval<DMAX, double>(a.coef, a.expo, 0, a.n_u, x, x2);
-  double num = a.prefactor, den = 1.0;
-  apply_pow<double>(U, a.pu_mode, a.pu_k, a.pow_u, num, den);
-  if (a.n_f) {
-    double F = poly_eval<DMAX, double>(a.coef, a.expo, a.n_u, a.n_f, x, x2);
-    apply_pow<double>(F, a.pf_mode, a.pf_k, a.pow_f, num, den);
+    for (int j = 0; j < DMAX; ++j) x2[j] = x[j] * x[j];
+    double U = poly_eval<DMAX, double>(a.coef, a.expo, 0, a.n_u, x, x2);
+    double num = a.prefactor, den = 1.0;
+    apply_pow<double>(U, a.pu_mode, a.pu_k, a.pow_u, num, den);
+    if (a.n_f) {
+      double F = poly_eval<DMAX, double>(a.coef, a.expo, a.n_u, a.n_f, x, x2);
+      apply_pow<double>(F, a.pf_mode, a.pf_k, a.pow_f, num, den);
+    }
+    return num * fast_rcp(den);
   }
-  return num / den;
-}
+};
 
 // ------------------------------------------------------------------ reduction
 
@@ -280,11 +317,14 @@ __device__ __forceinline__ void block_store(const double (&acc)[S], uint32_t ns,
 // ------------------------------------------------------------------ real evaluation
 
 // Grid: x over points (grid-stride), y over groups of S shifts.
-template <int DMAX, int TK, bool IDX32, int S>
-__device__ __forceinline__ void eval_real_body(const EvalArgs& a) {
+// EXACT: the integrand has exactly DMAX variables (specialised kernels).
+// VRM: variance-reduction map 0 = decided at run time (a.vr), 1 = off, 2 = on.
+enum { VRM_RUNTIME = 0, VRM_OFF = 1, VRM_ON = 2 };
+template <int DMAX, int TK, bool IDX32, int S, bool EXACT, class Fn, int VRM = VRM_RUNTIME>
+__device__ __forceinline__ void eval_real_body(const EvalArgs& a, const Fn& fn) {
   const uint32_t s0 = blockIdx.y * S;
   const uint32_t ns = (a.m - s0) < (uint32_t)S ? (a.m - s0) : (uint32_t)S;
-  const uint32_t dim = a.dim;
+  const uint32_t dim = EXACT ? (uint32_t)DMAX : a.dim;
   double acc[S];
 #pragma unroll
   for (int s = 0; s < S; ++s) acc[s] = 0.0;
@@ -304,19 +344,22 @@ __device__ __forceinline__ void eval_real_body(const EvalArgs& a) {
       if ((uint32_t)s < ns) {
         const double* __restrict__ D = a.shifts + (size_t)(s0 + s) * dim;
         double x[DMAX];
-        double w = 1.0;
+        double wt = 1.0;  // transform weight (Korobov r=3: prod_j u_j (1-u_j))
+        double wv = 1.0;  // VR Jacobian prod_j p'_j
 #pragma unroll
         for (int j = 0; j < DMAX; ++j) {
           if (j < (int)dim) {
             double u = shifted(q[j], D[j]);
-            double y = transform<TK>(u, w, a);
-            if (a.vr) y = vr_map(y, a.vr + 6 * j, w);
+            double y = transform<TK>(u, wt, a);
+            if (VRM == VRM_ON || (VRM == VRM_RUNTIME && a.vr)) y = vr_map(y, a.vr + 6 * j, wv);
             x[j] = y;
           } else {
             x[j] = 0.0;
           }
         }
-        double f = integrand_real<DMAX>(x, a);
+        if (TK == TK_KOROBOV3) wt = a.wscale * (wt * wt * wt);  // 140^d (prod s_j)^3
+        double w = wt * wv;
+        double f = fn(x, a);
         acc[s] += (w == 0.0) ? 0.0 : w * f;
       }
     }
@@ -332,3 +375,5 @@ __device__ __forceinline__ void eval_real_body(const EvalArgs& a) {
 }
 
 }  // namespace qmcd
+
+#endif  // QMC_DEVICE_H

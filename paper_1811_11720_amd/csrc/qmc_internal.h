@@ -23,6 +23,7 @@ enum { TSEL_NONE = 0, TSEL_KOROBOV = 1, TSEL_BAKER = 2, TSEL_KOROBOV3 = 3 };
 
 hipError_t launch_eval_real(const qmcd::EvalArgs& a, int dclass, int tsel, bool idx32, dim3 grid,
                             hipStream_t st);
+int occupancy_eval_real(int dclass, int tsel, bool idx32);
 hipError_t launch_finalize(const double* partial, uint32_t nblocks, uint32_t rows, double* out,
                            hipStream_t st);
 hipError_t launch_indices(uint64_t n, uint32_t dim, const uint64_t* z_host, uint64_t k0, uint64_t count,

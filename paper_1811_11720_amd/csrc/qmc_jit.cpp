@@ -1,0 +1,270 @@
+// qmc_jit.cpp -- descriptor-specialised evaluation kernels compiled at run time.
+//
+// The paper compiles each generated sector integrand into its kernel (Sec. 3.1,
+// Sec. 4).  Here the integrand's monomial table is turned into straight-line
+// HIP code when it is first integrated: U and F become a multivariate Horner
+// scheme (greedy: factor out the variable that occurs in most remaining
+// terms), the power classes become literal constants, and the result is
+// compiled with hiprtc for gfx950 and instantiated into the same evaluation
+// body as the ahead-of-time kernels (qmc_device.h).  Coefficients stay in
+// device memory, so integrands that differ only in coefficients share a
+// module.  Modules are cached per (device, source).
+#include <hip/hip_runtime.h>
+#include <hip/hiprtc.h>
+
+#include <algorithm>
+#include <array>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "qmc_jit.h"
+
+namespace {
+
+const char* kDeviceSrc =
+#include "qmc_device_src.inc"
+    ;
+
+struct Term {
+  uint32_t ci;
+  std::array<uint8_t, QMCD_MAXD> e;
+};
+
+class Emitter {
+ public:
+  explicit Emitter(int dim) : dim_(dim) {}
+  std::string tmp() { return "t" + std::to_string(ntmp_++); }
+  void line(const std::string& s) { body_ << "    " << s << "\n"; }
+  std::string coef(uint32_t i) {
+    std::string n = "c" + std::to_string(i);
+    if (!coefs_.count(i)) coefs_[i] = n;
+    return n;
+  }
+  // x_j^e from previously formed powers (x_j^2 = x_j x_j, x_j^(2k) = (x_j^k)^2, ...)
+  std::string power(int j, int e) {
+    auto key = std::make_pair(j, e);
+    auto it = pows_.find(key);
+    if (it != pows_.end()) return it->second;
+    std::string n = "x" + std::to_string(j) + "_" + std::to_string(e);
+    std::string v;
+    if (e == 1) {
+      v = "x[" + std::to_string(j) + "]";
+    } else if (e % 2 == 0) {
+      std::string h = power(j, e / 2);
+      v = h + " * " + h;
+    } else {
+      v = power(j, e - 1) + " * " + power(j, 1);
+    }
+    pre_ << "    const double " << n << " = " << v << ";\n";
+    pows_[key] = n;
+    return n;
+  }
+  std::string header() const {
+    std::ostringstream o;
+    for (auto& kv : coefs_) o << "    const double " << kv.second << " = a.coef[" << kv.first << "];\n";
+    return o.str();
+  }
+  std::string pre() const { return pre_.str(); }
+  std::string body() const { return body_.str(); }
+  int dim() const { return dim_; }
+
+ private:
+  int dim_;
+  int ntmp_ = 0;
+  std::map<uint32_t, std::string> coefs_;
+  std::map<std::pair<int, int>, std::string> pows_;
+  std::ostringstream pre_, body_;
+};
+
+// Greedy multivariate Horner: returns the name holding sum_i c_i prod_j x_j^e_ij.
+std::string horner(std::vector<Term> terms, Emitter& em) {
+  const int d = em.dim();
+  bool all_const = true;
+  for (auto& t : terms)
+    for (int j = 0; j < d; ++j)
+      if (t.e[j]) all_const = false;
+  if (all_const) {
+    std::string acc = em.coef(terms[0].ci);
+    if (terms.size() == 1) return acc;
+    std::string v = em.tmp();
+    std::string expr = acc;
+    for (size_t i = 1; i < terms.size(); ++i) expr += " + " + em.coef(terms[i].ci);
+    em.line("const double " + v + " = " + expr + ";");
+    return v;
+  }
+  int best = -1, cnt = -1;
+  for (int j = 0; j < d; ++j) {
+    int c = 0;
+    for (auto& t : terms) c += t.e[j] ? 1 : 0;
+    if (c > cnt) {
+      cnt = c;
+      best = j;
+    }
+  }
+  std::vector<Term> A, B;
+  int emin = 255;
+  for (auto& t : terms) {
+    if (t.e[best]) {
+      A.push_back(t);
+      emin = std::min<int>(emin, t.e[best]);
+    } else {
+      B.push_back(t);
+    }
+  }
+  for (auto& t : A) t.e[best] = (uint8_t)(t.e[best] - emin);
+  std::string va = horner(A, em);
+  std::string p = em.power(best, emin);
+  std::string v = em.tmp();
+  if (B.empty()) {
+    em.line("const double " + v + " = " + p + " * " + va + ";");
+  } else {
+    std::string vb = horner(B, em);
+    em.line("const double " + v + " = __builtin_fma(" + p + ", " + va + ", " + vb + ");");
+  }
+  return v;
+}
+
+struct Module {
+  hipModule_t mod = nullptr;
+  hipFunction_t f32 = nullptr, f64 = nullptr;
+  int occ_blocks = 0;
+};
+
+std::mutex g_mu;
+std::map<std::string, std::shared_ptr<Module>> g_cache;
+thread_local std::string g_jit_err;
+
+}  // namespace
+
+namespace qmcj {
+
+const char* last_error() { return g_jit_err.c_str(); }
+
+std::string generate(const Spec& s) {
+  const int d = (int)s.dim;
+  Emitter em(d);
+  std::vector<Term> tu, tf;
+  for (uint32_t i = 0; i < s.n_u + s.n_f; ++i) {
+    Term t;
+    t.ci = i;
+    t.e.fill(0);
+    for (int j = 0; j < d; ++j) t.e[j] = s.expo[(size_t)i * d + j];
+    (i < s.n_u ? tu : tf).push_back(t);
+  }
+  std::string U = horner(tu, em);
+  std::string F = s.n_f ? horner(tf, em) : std::string();
+  std::ostringstream o;
+  o << "#define QMC_RTC 1\n" << kDeviceSrc << "\n";
+  o << "namespace qmcd {\nstruct JitReal {\n";
+  o << "  __device__ __forceinline__ double operator()(const double (&x)[" << d
+    << "], const EvalArgs& a) const {\n";
+  o << em.header() << em.pre() << em.body();
+  o << "    double num = a.prefactor, den = 1.0;\n";
+  o << "    apply_pow<double>(" << U << ", " << s.pu_mode << ", " << s.pu_k << ", a.pow_u, num, den);\n";
+  if (s.n_f) o << "    apply_pow<double>(" << F << ", " << s.pf_mode << ", " << s.pf_k << ", a.pow_f, num, den);\n";
+  o << "    return num * fast_rcp(den);\n  }\n};\n}  // namespace qmcd\n";
+  const char* tk = s.tk == qmcd::TK_KOROBOV3 ? "qmcd::TK_KOROBOV3"
+                   : s.tk == qmcd::TK_KOROBOV ? "qmcd::TK_KOROBOV"
+                   : s.tk == qmcd::TK_BAKER   ? "qmcd::TK_BAKER"
+                                               : "qmcd::TK_NONE";
+  for (int w = 0; w < 2; ++w) {
+    o << "extern \"C\" __global__ __launch_bounds__(QMCD_BLOCK) void qmc_jit_eval" << (w ? "64" : "32")
+      << "(qmcd::EvalArgs a) {\n  qmcd::eval_real_body<" << d << ", " << tk << ", " << (w ? "false" : "true")
+      << ", " << s.S << ", true, qmcd::JitReal, " << (s.vr ? "qmcd::VRM_ON" : "qmcd::VRM_OFF")
+      << ">(a, qmcd::JitReal());\n}\n";
+  }
+  return o.str();
+}
+
+// hiprtc: source -> gfx950 code object
+static int compile(const std::string& src, std::vector<char>& code) {
+  hiprtcProgram prog;
+  if (hiprtcCreateProgram(&prog, src.c_str(), "qmc_jit.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS) {
+    g_jit_err = "hiprtcCreateProgram failed";
+    return -1;
+  }
+  const char* opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-mcode-object-version=5",
+                        "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
+  hiprtcResult rc = hiprtcCompileProgram(prog, (int)(sizeof opts / sizeof opts[0]), opts);
+  if (rc != HIPRTC_SUCCESS) {
+    size_t ls = 0;
+    hiprtcGetProgramLogSize(prog, &ls);
+    std::string log(ls + 1, '\0');
+    hiprtcGetProgramLog(prog, &log[0]);
+    g_jit_err = "hiprtc compile failed: " + log.substr(0, 2000);
+    hiprtcDestroyProgram(&prog);
+    return -1;
+  }
+  size_t cs = 0;
+  hiprtcGetCodeSize(prog, &cs);
+  code.resize(cs);
+  hiprtcGetCode(prog, code.data());
+  hiprtcDestroyProgram(&prog);
+  return 0;
+}
+
+int compile_only(const Spec& s, size_t* code_bytes) {
+  std::vector<char> code;
+  std::string src = generate(s);
+  if (const char* dump = std::getenv("QMC_JIT_DUMP")) {
+    if (FILE* fh = std::fopen(dump, "w")) {
+      std::fputs(src.c_str(), fh);
+      std::fclose(fh);
+    }
+  }
+  int rc = compile(src, code);
+  if (code_bytes) *code_bytes = code.size();
+  return rc;
+}
+
+int get(int device, const Spec& s, Kernel* out) {
+  std::string src = generate(s);
+  std::string key = std::to_string(device) + "|" + src;
+  {
+    std::lock_guard<std::mutex> g(g_mu);
+    auto it = g_cache.find(key);
+    if (it != g_cache.end()) {
+      out->f32 = it->second->f32;
+      out->f64 = it->second->f64;
+      out->occ_blocks = it->second->occ_blocks;
+      return 0;
+    }
+  }
+  std::vector<char> code;
+  if (compile(src, code)) return -1;
+  auto m = std::make_shared<Module>();
+  hipError_t e = hipModuleLoadData(&m->mod, code.data());
+  if (e == hipSuccess) e = hipModuleGetFunction(&m->f32, m->mod, "qmc_jit_eval32");
+  if (e == hipSuccess) e = hipModuleGetFunction(&m->f64, m->mod, "qmc_jit_eval64");
+  if (e != hipSuccess) {
+    g_jit_err = std::string("module load failed: ") + hipGetErrorString(e);
+    return -2;
+  }
+  int occ = 0;
+  if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&occ, m->f32, QMCD_BLOCK, 0) != hipSuccess) occ = 0;
+  m->occ_blocks = occ;
+  {
+    std::lock_guard<std::mutex> g(g_mu);
+    g_cache[key] = m;
+  }
+  out->f32 = m->f32;
+  out->f64 = m->f64;
+  out->occ_blocks = occ;
+  return 0;
+}
+
+hipError_t launch(const Kernel& k, bool idx32, const qmcd::EvalArgs& a, dim3 grid, hipStream_t st) {
+  qmcd::EvalArgs copy = a;
+  void* params[] = {&copy};
+  return hipModuleLaunchKernel(idx32 ? k.f32 : k.f64, grid.x, grid.y, grid.z, QMCD_BLOCK, 1, 1, 0, st, params,
+                               nullptr);
+}
+
+}  // namespace qmcj

@@ -1,0 +1,36 @@
+// qmc_jit.h -- run-time specialisation of the evaluation kernel to one integrand.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "qmc_device.h"
+
+namespace qmcj {
+
+// What the generated code depends on (coefficients are read from memory).
+struct Spec {
+  uint32_t dim, n_u, n_f;
+  const uint8_t* expo;  // [(n_u + n_f) * dim]
+  int pu_mode, pu_k, pf_mode, pf_k;
+  int tk;  // qmcd::TK_*
+  int S;   // shifts per thread group
+  int vr;  // variance-reduction map compiled in (1) or out (0)
+};
+
+struct Kernel {
+  hipFunction_t f32 = nullptr, f64 = nullptr;  // 32-bit / 64-bit index stepping
+  int occ_blocks = 0;                           // resident blocks per CU
+};
+
+std::string generate(const Spec& s);
+// Compile (or fetch from the cache) the specialised kernels for the current device.
+int get(int device, const Spec& s, Kernel* out);
+// Generate and compile only (no device needed); code size in bytes.
+int compile_only(const Spec& s, size_t* code_bytes);
+hipError_t launch(const Kernel& k, bool idx32, const qmcd::EvalArgs& a, dim3 grid, hipStream_t st);
+const char* last_error();
+
+}  // namespace qmcj

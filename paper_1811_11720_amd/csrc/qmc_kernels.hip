@@ -10,7 +10,7 @@ namespace qmck {
 
 template <int DMAX, int TK, bool IDX32>
 __global__ __launch_bounds__(QMCD_BLOCK) void k_eval_real(qmcd::EvalArgs a) {
-  qmcd::eval_real_body<DMAX, TK, IDX32, S_REAL>(a);
+  qmcd::eval_real_body<DMAX, TK, IDX32, S_REAL, false>(a, qmcd::GenericReal<DMAX>());
 }
 
 }  // namespace qmck
@@ -29,6 +29,14 @@ using EvalFn = void (*)(qmcd::EvalArgs);
 
 static EvalFn g_real[4][4][2] = {QMC_ROW(4), QMC_ROW(8), QMC_ROW(12), QMC_ROW(16)};
 #undef QMC_ROW
+
+int occupancy_eval_real(int dclass, int tsel, bool idx32) {
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)g_real[dclass][tsel][idx32 ? 1 : 0],
+                                                   QMCD_BLOCK, 0) != hipSuccess)
+    return 0;
+  return occ;
+}
 
 hipError_t launch_eval_real(const qmcd::EvalArgs& a, int dclass, int tsel, bool idx32, dim3 grid,
                             hipStream_t st) {

@@ -22,6 +22,7 @@
 
 #include "qmc.h"
 #include "qmc_internal.h"
+#include "qmc_jit.h"
 
 namespace {
 
@@ -90,7 +91,12 @@ struct qmc_context {
   std::recursive_mutex mu;
   int inflight = 0;
   bool broken = false;
-  int max_blocks = 1024;
+  int max_blocks = 0;          // 0: from occupancy
+  int cus = 256;               // compute units of the device
+  int grid_rounds = 1;         // resident-block rounds per launch
+  bool jit = true;             // specialise kernels to the integrand
+  uint64_t jit_min_evals = 1ull << 24;
+  int jit_S = 8;
 };
 
 struct qmc_integrand {
@@ -107,6 +113,8 @@ struct qmc_integrand {
   uint32_t* d_expo = nullptr;
   double* d_vr = nullptr;
   int refs = 0;
+  std::map<int, qmcj::Kernel> jit;  // per (transform kind, VR on) key
+  std::map<int, int> jit_failed;
 };
 
 namespace {
@@ -197,10 +205,25 @@ int set_transform(qmcd::EvalArgs& a, const qmc_transform& t, int& tsel) {
 struct LatticeRun {
   std::vector<double> sums;  // rows (m or 2m)
   double kernel_seconds = 0;
+  uint32_t path = 0;
 };
 
+// blocks over points for one shift group, from the kernel's occupancy
+uint32_t plan_blocks(const qmc_context* c, int occ, uint32_t groups, uint64_t npts) {
+  uint64_t cap = (npts + QMCD_BLOCK - 1) / QMCD_BLOCK;
+  uint64_t nb;
+  if (c->max_blocks > 0) {
+    nb = (uint64_t)c->max_blocks;
+  } else {
+    uint64_t total = (uint64_t)std::max(occ, 1) * (uint64_t)c->cus * (uint64_t)c->grid_rounds;
+    nb = std::max<uint64_t>(1, total / groups);
+  }
+  nb = std::min(nb, cap);
+  return (uint32_t)std::max<uint64_t>(nb, 1);
+}
+
 // One lattice (n, z), m shifts from `shift_tab`, points [k0, k1): per-shift sums.
-int run_lattice(qmc_context* c, const qmc_integrand* f, uint64_t n, const uint64_t* z, uint32_t m,
+int run_lattice(qmc_context* c, qmc_integrand* f, uint64_t n, const uint64_t* z, uint32_t m,
                 const double* shift_tab, const qmc_transform& t, uint64_t k0, uint64_t k1, LatticeRun& out) {
   if (f->flags & QMC_DEFORM) return fail(QMC_EUNSUPPORTED, "complex (deformed) integrands are not enabled");
   qmcd::EvalArgs a;
@@ -210,10 +233,37 @@ int run_lattice(qmc_context* c, const qmc_integrand* f, uint64_t n, const uint64
   if (rc) return rc;
   const uint32_t dim = f->dim;
   const uint32_t rows = m;
-  uint64_t npts = k1 - k0;
-  uint32_t nb = (uint32_t)std::min<uint64_t>((npts + QMCD_BLOCK - 1) / QMCD_BLOCK, (uint64_t)c->max_blocks);
-  if (nb == 0) nb = 1;
-  const uint32_t groups = (m + qmck::S_REAL - 1) / qmck::S_REAL;
+  const uint64_t npts = k1 - k0;
+  const bool idx32 = n <= (1ull << 31);
+  const int dclass = qmck::dim_class(dim);
+
+  // specialised kernel for large jobs (compiled once per integrand structure)
+  qmcj::Kernel jk;
+  bool use_jit = false;
+  int S = qmck::S_REAL;
+  const int jkey = tsel * 2 + (f->has_vr ? 1 : 0);
+  if (c->jit && npts * (uint64_t)m >= c->jit_min_evals && !f->jit_failed.count(jkey)) {
+    auto it = f->jit.find(jkey);
+    if (it == f->jit.end()) {
+      qmcj::Spec sp{dim, f->n_u, f->n_f, f->expo.data(), f->pu_mode, f->pu_k, f->pf_mode, f->pf_k, tsel, c->jit_S,
+                    f->has_vr ? 1 : 0};
+      if (qmcj::get(c->device, sp, &jk) == 0) {
+        f->jit[jkey] = jk;
+        use_jit = true;
+      } else {
+        f->jit_failed[jkey] = 1;
+        if (std::getenv("QMC_JIT_VERBOSE")) std::fprintf(stderr, "qmc: specialisation failed: %s\n", qmcj::last_error());
+      }
+    } else {
+      jk = it->second;
+      use_jit = true;
+    }
+    if (use_jit) S = c->jit_S;
+  }
+  const uint32_t groups = (m + S - 1) / S;
+  const int occ = use_jit ? jk.occ_blocks : qmck::occupancy_eval_real(dclass, tsel, idx32);
+  const uint32_t nb = plan_blocks(c, occ, groups, npts);
+
   size_t off_sh = 0, sz_sh = (size_t)m * dim * sizeof(double);
   size_t off_part = (sz_sh + 255) & ~(size_t)255, sz_part = (size_t)rows * nb * sizeof(double);
   size_t off_out = (off_part + sz_part + 255) & ~(size_t)255, sz_out = rows * sizeof(double);
@@ -253,9 +303,13 @@ int run_lattice(qmc_context* c, const qmc_integrand* f, uint64_t n, const uint64
   a.prefactor = f->prefactor;
   a.lambda = f->lambda;
   a.vr = f->has_vr ? f->d_vr : nullptr;
-  const bool idx32 = n <= (1ull << 31);
+  a.wscale = std::pow(140.0, (double)dim);
   HIPCHK(hipEventRecord(c->ev0, c->stream));
-  HIPCHK(qmck::launch_eval_real(a, qmck::dim_class(dim), tsel, idx32, dim3(nb, groups), c->stream));
+  if (use_jit) {
+    HIPCHK(qmcj::launch(jk, idx32, a, dim3(nb, groups), c->stream));
+  } else {
+    HIPCHK(qmck::launch_eval_real(a, dclass, tsel, idx32, dim3(nb, groups), c->stream));
+  }
   HIPCHK(hipEventRecord(c->ev1, c->stream));
   HIPCHK(qmck::launch_finalize(a.partial, nb, rows, (double*)(ws + off_out), c->stream));
   HIPCHK(hipMemcpyAsync(c->h_stage, ws + off_out, sz_out, hipMemcpyDeviceToHost, c->stream));
@@ -264,6 +318,7 @@ int run_lattice(qmc_context* c, const qmc_integrand* f, uint64_t n, const uint64
   HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
   out.kernel_seconds = ms * 1e-3;
   out.sums.assign(c->h_stage, c->h_stage + rows);
+  out.path = use_jit ? 1u : 0u;
   return QMC_OK;
 }
 
@@ -308,7 +363,7 @@ int next_registered(qmc_context* c, uint64_t want, uint32_t dim, uint64_t* n_out
 
 int integrate_request(qmc_context* c, const qmc_request& q, qmc_result* out, double* shift_sums) {
   auto t0 = std::chrono::steady_clock::now();
-  const qmc_integrand* f = q.f;
+  qmc_integrand* f = const_cast<qmc_integrand*>(q.f);
   if (!f) return fail(QMC_EINVAL, "request has no integrand");
   if (f->ctx != c) return fail(QMC_EINVAL, "integrand belongs to another context");
   const uint32_t dim = f->dim, m = q.m;
@@ -374,9 +429,28 @@ int integrate_request(qmc_context* c, const qmc_request& q, qmc_result* out, dou
     z.assign(c->lattices[n].begin(), c->lattices[n].begin() + dim);
   }
   r.device_seconds = dev;
+  r.path = run.path;
   r.wall_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (out) *out = r;
   if (shift_sums) std::memcpy(shift_sums, run.sums.data(), run.sums.size() * sizeof(double));
+  return QMC_OK;
+}
+
+int validate_desc(const qmc_integrand_desc* d) {
+  if (!d) return fail(QMC_EINVAL, "descriptor is NULL");
+  if (d->dim < 1 || d->dim > QMC_MAX_DIM) return fail(QMC_EINVAL, "dim=%u outside [1, %d]", d->dim, QMC_MAX_DIM);
+  if (d->n_u < 1) return fail(QMC_EINVAL, "U needs at least one monomial");
+  uint32_t nm = d->n_u + d->n_f;
+  if (nm > QMC_MAX_MONOMIALS) return fail(QMC_EINVAL, "%u monomials exceed %d", nm, QMC_MAX_MONOMIALS);
+  if (!d->coef || !d->expo) return fail(QMC_EINVAL, "coef/expo is NULL");
+  for (uint32_t i = 0; i < nm; ++i)
+    if (!std::isfinite(d->coef[i])) return fail(QMC_EINVAL, "coef[%u] is not finite", i);
+  for (size_t i = 0; i < (size_t)nm * d->dim; ++i)
+    if (d->expo[i] > QMC_MAX_EXP) return fail(QMC_EINVAL, "exponent %u exceeds %d", d->expo[i], QMC_MAX_EXP);
+  if (!std::isfinite(d->pow_u) || !std::isfinite(d->pow_f) || !std::isfinite(d->prefactor))
+    return fail(QMC_EINVAL, "powers and prefactor must be finite");
+  if ((d->flags & QMC_DEFORM) && !std::isfinite(d->lambda)) return fail(QMC_EINVAL, "lambda must be finite");
+  if (d->flags & ~(uint32_t)(QMC_DEFORM | QMC_EVAL_FP32)) return fail(QMC_EINVAL, "unknown flags 0x%x", d->flags);
   return QMC_OK;
 }
 
@@ -418,7 +492,17 @@ int qmc_context_create(int device, void* hip_stream, void* workspace, size_t wor
     delete c;
     return fail(QMC_EDEVICE, "hipEventCreate failed");
   }
-  if (const char* mb = std::getenv("QMC_MAX_BLOCKS")) c->max_blocks = std::max(1, atoi(mb));
+  if (const char* mb = std::getenv("QMC_MAX_BLOCKS")) c->max_blocks = std::max(0, atoi(mb));
+  if (const char* v = std::getenv("QMC_GRID_ROUNDS")) c->grid_rounds = std::max(1, atoi(v));
+  if (const char* v = std::getenv("QMC_JIT")) c->jit = atoi(v) != 0;
+  if (const char* v = std::getenv("QMC_JIT_MIN_EVALS")) c->jit_min_evals = strtoull(v, nullptr, 10);
+  if (const char* v = std::getenv("QMC_JIT_S")) {
+    int sv = atoi(v);
+    if (sv == 4 || sv == 8 || sv == 16 || sv == 32) c->jit_S = sv;
+  }
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+    c->cus = cus;
   *out = c;
   return QMC_OK;
 }
@@ -461,19 +545,9 @@ int qmc_next_lattice(qmc_context* c, uint64_t preferred_n, uint32_t dim, uint64_
 int qmc_create_integrand(qmc_context* c, const qmc_integrand_desc* d, qmc_integrand** out) {
   if (!c || !d || !out) return fail(QMC_EINVAL, "NULL argument");
   *out = nullptr;
-  if (d->dim < 1 || d->dim > QMC_MAX_DIM) return fail(QMC_EINVAL, "dim=%u outside [1, %d]", d->dim, QMC_MAX_DIM);
-  if (d->n_u < 1) return fail(QMC_EINVAL, "U needs at least one monomial");
+  int vrc = validate_desc(d);
+  if (vrc) return vrc;
   uint32_t nm = d->n_u + d->n_f;
-  if (nm > QMC_MAX_MONOMIALS) return fail(QMC_EINVAL, "%u monomials exceed %d", nm, QMC_MAX_MONOMIALS);
-  if (!d->coef || !d->expo) return fail(QMC_EINVAL, "coef/expo is NULL");
-  for (uint32_t i = 0; i < nm; ++i)
-    if (!std::isfinite(d->coef[i])) return fail(QMC_EINVAL, "coef[%u] is not finite", i);
-  for (size_t i = 0; i < (size_t)nm * d->dim; ++i)
-    if (d->expo[i] > QMC_MAX_EXP) return fail(QMC_EINVAL, "exponent %u exceeds %d", d->expo[i], QMC_MAX_EXP);
-  if (!std::isfinite(d->pow_u) || !std::isfinite(d->pow_f) || !std::isfinite(d->prefactor))
-    return fail(QMC_EINVAL, "powers and prefactor must be finite");
-  if ((d->flags & QMC_DEFORM) && !std::isfinite(d->lambda)) return fail(QMC_EINVAL, "lambda must be finite");
-  if (d->flags & ~(uint32_t)(QMC_DEFORM | QMC_EVAL_FP32)) return fail(QMC_EINVAL, "unknown flags 0x%x", d->flags);
   qmc_integrand* f = new qmc_integrand();
   f->ctx = c;
   f->dim = d->dim;
@@ -639,7 +713,7 @@ int qmc_shift_sums_range(qmc_context* c, const qmc_integrand* f, uint64_t n, con
     if (nonfinite) *nonfinite = 0;
     return QMC_OK;
   }
-  rc = run_lattice(c, f, n, z, m, sh.data(), t, k0, k1, run);
+  rc = run_lattice(c, const_cast<qmc_integrand*>(f), n, z, m, sh.data(), t, k0, k1, run);
   if (rc) return rc;
   std::memcpy(shift_sums, run.sums.data(), run.sums.size() * 8);
   if (nonfinite) {
@@ -647,6 +721,24 @@ int qmc_shift_sums_range(qmc_context* c, const qmc_integrand* f, uint64_t n, con
     for (double v : run.sums) bad += std::isfinite(v) ? 0 : 1;
     *nonfinite = bad;
   }
+  return QMC_OK;
+}
+
+int qmc_specialize_check(const qmc_integrand_desc* d, qmc_transform t, size_t* code_bytes) {
+  int rc = validate_desc(d);
+  if (rc) return rc;
+  qmcd::EvalArgs a;
+  std::memset(&a, 0, sizeof a);
+  int tsel = 0;
+  rc = set_transform(a, t, tsel);
+  if (rc) return rc;
+  int pu_mode, pu_k, pf_mode, pf_k;
+  classify_power(d->pow_u, pu_mode, pu_k);
+  classify_power(d->n_f ? d->pow_f : 0.0, pf_mode, pf_k);
+  int S = 8;
+  if (const char* v = std::getenv("QMC_JIT_S")) S = atoi(v);
+  qmcj::Spec sp{d->dim, d->n_u, d->n_f, d->expo, pu_mode, pu_k, pf_mode, pf_k, tsel, S, 0};
+  if (qmcj::compile_only(sp, code_bytes) != 0) return fail(QMC_EINVAL, "%s", qmcj::last_error());
   return QMC_OK;
 }
 

@@ -22,11 +22,29 @@ KOR3 = (W.T_KOROBOV, 3, 3)
 THREADS = min(16, os.cpu_count() or 1)
 
 
-@pytest.fixture(scope="module")
-def ctx():
+def make_ctx(path):
+    """Context whose integrations use the descriptor-interpreting kernels
+    ("generic") or kernels specialised to each integrand ("specialised")."""
     import paper_1811_11720_amd as Q
 
-    c = Q.Context(0)
+    old = {k: os.environ.get(k) for k in ("QMC_JIT", "QMC_JIT_MIN_EVALS")}
+    os.environ["QMC_JIT"] = "1" if path == "specialised" else "0"
+    os.environ["QMC_JIT_MIN_EVALS"] = "0"
+    try:
+        c = Q.Context(0)
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    c.path = 1 if path == "specialised" else 0
+    return c
+
+
+@pytest.fixture(scope="module", params=["generic", "specialised"])
+def ctx(request):
+    c = make_ctx(request.param)
     yield c
     c.close()
 
@@ -48,6 +66,7 @@ def _run_both(ctx, desc, n, z, m, seed, tr, vr=None, ids=None):
     if vr is not None:
         f.set_vr(vr)
     g = ctx.integrate(f, n, z, m, seed, tr, sums=True)
+    assert g["path"] == ctx.path
     sh = oracle.shifts(seed, m, desc.dim)
     o = oracle.shift_sums(desc, n, z, m, sh, tr, vr, ids=ids, threads=THREADS)
     ids = o.ids
@@ -207,9 +226,7 @@ def test_growth_loop_matches_oracle(ctx):
     desc = W.product_of_linear([1.0, 1.0, 1.0], [0.8, 0.5, 0.3], -1.5)
     table_ns = [cbc.next_prime(v) for v in (1000, 2000, 4000, 8000, 16000, 32000, 64000, 128000)]
     zs = {n: cbc.fast_cbc(n, 3) for n in table_ns}
-    import paper_1811_11720_amd as Q
-
-    c2 = Q.Context(0)
+    c2 = make_ctx("specialised" if ctx.path else "generic")
     c2.register_table(zs)
     f = c2.integrand(desc)
     BAKER = (W.T_BAKER, 0, 0)
