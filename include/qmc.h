@@ -54,6 +54,7 @@ enum {
 
 /* limits of the device kernels */
 #define QMC_MAX_DIM 16        /* integration variables per integrand */
+#define QMC_MAX_DIM_DEFORM 12 /* ... per integrand with QMC_DEFORM */
 #define QMC_MAX_EXP 15        /* exponent of one variable in one monomial */
 #define QMC_MAX_MONOMIALS 1024 /* n_u + n_f */
 #define QMC_MAX_SHIFTS 1024   /* m */
@@ -79,7 +80,10 @@ typedef struct qmc_context qmc_context;
 int qmc_context_create(int device, void* hip_stream, void* workspace, size_t workspace_bytes,
                        qmc_context** out);
 
-/* Destroy; QMC_EBUSY while submitted requests are unfinished. */
+/* Destroy; QMC_EBUSY while submitted requests are unfinished.  If integrands
+ * created on the context are still alive the context is only marked closed
+ * (further calls on it fail) and is freed when its last integrand is
+ * destroyed. */
 int qmc_context_destroy(qmc_context* ctx);
 
 /*
@@ -137,6 +141,32 @@ int qmc_destroy_integrand(qmc_integrand* f);
  */
 int qmc_set_vr(qmc_integrand* f, const double* params);
 
+/*
+ * Histograms for the variance-reduction fit (Sec. 2.4): over the lattice
+ * (n, z) shifted by the first shift of SplitMix64(seed), with no transform
+ * and no VR map, hist[j*bins + b] = sum of |f(x)| over points with
+ * floor(x_j * bins) = b (|f| = modulus for complex integrands; non-finite
+ * values count 0).  Each |f| is rounded to max|f| * 2^-40 and summed as an
+ * integer, so the result is bitwise reproducible.  hist: host [dim * bins].
+ */
+int qmc_histogram(qmc_context* ctx, const qmc_integrand* f, uint64_t n, const uint64_t* z, uint64_t seed,
+                  uint32_t bins, double* hist);
+
+/*
+ * Fit the PolySingular map of eq. ISfit (App. A.5) to the inverse CDF of
+ * each dimension's histogram by Levenberg-Marquardt (host only, no GPU):
+ * params[6*j + 0..5] receives (p0..p5) with p0 >= 1.001, p1 <= -0.001.  A
+ * dimension whose fit is not strictly increasing on [0,1] gets the identity
+ * map and its bit in *fallback_mask (optional).  hist: host [dim * bins].
+ */
+int qmc_fit_vr_from_histogram(uint32_t dim, uint32_t bins, const double* hist, double* params,
+                              uint32_t* fallback_mask);
+
+/* qmc_histogram + qmc_fit_vr_from_histogram + qmc_set_vr on f.  params
+ * (optional) receives the fitted [dim*6]. */
+int qmc_fit_vr(qmc_context* ctx, qmc_integrand* f, uint64_t n, const uint64_t* z, uint64_t seed, uint32_t bins,
+               double* params, uint32_t* fallback_mask);
+
 /* ---------------------------------------------------------------- transforms */
 enum { QMC_T_NONE = 0, QMC_T_KOROBOV = 1, QMC_T_BAKER = 2 };
 
@@ -167,7 +197,8 @@ typedef struct {
   uint32_t iterations;    /* lattices evaluated (earlier ones discarded) */
   uint64_t evaluations;   /* total integrand evaluations over all iterations */
   uint32_t flags;         /* QMC_CONVERGED | ... */
-  uint32_t path;          /* kernels used: 0 = descriptor-interpreting, 1 = specialised to this integrand */
+  uint32_t path;          /* kernels used: 0 = descriptor-interpreting grid, 1 = specialised to this
+                             integrand, 2 = persistent batch kernels */
   uint64_t nonfinite;     /* contributions that were NaN or +-inf (last iteration) */
   double device_seconds;  /* summed duration of the evaluation kernels (HIP events) */
   double queue_seconds;   /* submit-to-start wait (serving); 0 otherwise */
@@ -202,8 +233,19 @@ typedef struct {
   uint64_t max_evals;      /* 0 = unlimited */
 } qmc_request;
 
-/* Run `count` requests; results in out[count]. shift_sums (optional) gets
- * each request's per-shift sums back to back ([m] or [2m] each). */
+/*
+ * Run `count` requests together; results in out[count].  Each round, the
+ * current lattice of every unfinished request is evaluated by persistent
+ * kernels (one per dimension class / real-complex / fp64-fp32 variant) that
+ * drain a shared tile list, replayed as one HIP graph; requests that miss
+ * their goal move to the next registered lattice for the next round
+ * (Sec. 3.3.1).  A request's tiling depends only on its own n and m, so its
+ * per-shift sums are bitwise the same alone or in any batch.  QMC_EVAL_FP32
+ * integrands run here (U, F and powers in fp32, compensated fp64 sums).
+ * shift_sums (optional) gets each request's per-shift sums of its last
+ * lattice back to back ([m] or [2m] each).  device_seconds is the batch's
+ * total kernel time.
+ */
 int qmc_integrate_batch(qmc_context* ctx, const qmc_request* reqs, uint32_t count,
                         qmc_result* out, double* shift_sums);
 

@@ -117,6 +117,9 @@ def _declare(L):
         "qmc_shift_sums_range": ([vp, vp, C.c_uint64, up, C.c_uint32, C.c_uint64, Transform, C.c_uint64,
                                   C.c_uint64, dp, up], C.c_int),
         "qmc_specialize_check": ([C.POINTER(IntegrandDesc), Transform, C.POINTER(C.c_size_t)], C.c_int),
+        "qmc_histogram": ([vp, vp, C.c_uint64, up, C.c_uint64, C.c_uint32, dp], C.c_int),
+        "qmc_fit_vr_from_histogram": ([C.c_uint32, C.c_uint32, dp, dp, C.POINTER(C.c_uint32)], C.c_int),
+        "qmc_fit_vr": ([vp, vp, C.c_uint64, up, C.c_uint64, C.c_uint32, dp, C.POINTER(C.c_uint32)], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -184,6 +187,16 @@ def specialize_check(desc, transform=(T_KOROBOV, 3, 3)) -> int:
     nb = C.c_size_t()
     _check(lib().qmc_specialize_check(C.byref(d), _tr(transform), C.byref(nb)))
     return nb.value
+
+
+def fit_vr_from_histogram(hist) -> tuple[np.ndarray, int]:
+    """PolySingular parameters [dim, 6] fitted to each row's inverse CDF (host only)."""
+    h = np.ascontiguousarray(hist, dtype=np.float64)
+    dim, bins = h.shape
+    p = np.zeros(6 * dim)
+    mask = C.c_uint32()
+    _check(lib().qmc_fit_vr_from_histogram(dim, bins, _dp(h), _dp(p), C.byref(mask)))
+    return p.reshape(dim, 6), mask.value
 
 
 class Integrand:
@@ -311,6 +324,19 @@ class Context:
         _check(lib().qmc_shift_sums_range(self.handle, f.handle, n, _up(zz), m, seed, _tr(transform), k0, k1,
                                           _dp(out), C.byref(nf)))
         return out[:m].copy(), (out[m:].copy() if f.complex else np.zeros(m))
+
+    def histogram(self, f: Integrand, n: int, z, seed: int, bins: int = 1024) -> np.ndarray:
+        zz = np.ascontiguousarray(z, dtype=np.uint64)
+        out = np.zeros(f.dim * bins)
+        _check(lib().qmc_histogram(self.handle, f.handle, n, _up(zz), seed, bins, _dp(out)))
+        return out.reshape(f.dim, bins)
+
+    def fit_vr(self, f: Integrand, n: int, z, seed: int, bins: int = 1024):
+        zz = np.ascontiguousarray(z, dtype=np.uint64)
+        p = np.zeros(6 * f.dim)
+        mask = C.c_uint32()
+        _check(lib().qmc_fit_vr(self.handle, f.handle, n, _up(zz), seed, bins, _dp(p), C.byref(mask)))
+        return p.reshape(f.dim, 6), mask.value
 
     def close(self):
         if getattr(self, "handle", None):

@@ -1,0 +1,351 @@
+// qmc_batch.cpp -- many integrals in one persistent launch per kernel variant.
+//
+// A round evaluates the current lattice of every job.  Each job is cut into
+// tiles of T points x S shifts (T depends only on the job's own n, so the
+// per-shift sums of a job are the same whether it runs alone or in any
+// mix).  Jobs are grouped by kernel variant (dimension class, real/complex,
+// fp64/fp32 evaluation) and ordered heaviest first; per variant one
+// persistent kernel drains the tile list, then one fixed-order reduction sums
+// every job's tile columns.  The launches of a round are captured into a HIP
+// graph on a private stream and replayed on the context's stream.
+//
+// run_requests adds the paper's growth loop (Sec. 3.3.1) on top: all
+// unconverged requests move to their next lattice and run together in the
+// next round.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "qmc_host.h"
+
+namespace qmch {
+
+namespace {
+
+double cost_per_eval(const qmc_integrand* f) {
+  double c = (double)(f->n_u + f->n_f) * f->dim + 10.0 * f->dim;
+  if (f->flags & QMC_DEFORM) c = c * 6.0 + 2.0 * f->dim * f->dim * f->dim;
+  return c;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+}  // namespace
+
+int run_batch(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_seconds) {
+  const uint32_t J = (uint32_t)jobs.size();
+  if (kernel_seconds) *kernel_seconds = 0.0;
+  if (J == 0) return QMC_OK;
+  struct Plan {
+    int variant;  // dclass * 4 + cplx * 2 + fp32
+    uint32_t rows, ktiles, groups;
+    uint64_t tile_points;
+    size_t part_off, sh_off, row0;
+    double cost;
+  };
+  std::vector<Plan> plan(J);
+  size_t n_part = 0, n_sh = 0, n_rows = 0;
+  for (uint32_t i = 0; i < J; ++i) {
+    BatchJob& b = *jobs[i];
+    const qmc_integrand* f = b.f;
+    const bool cplx = (f->flags & QMC_DEFORM) != 0, fp32 = (f->flags & QMC_EVAL_FP32) != 0;
+    Plan& p = plan[i];
+    const int dclass = qmck::dim_class(f->dim);
+    p.variant = dclass * 4 + (cplx ? 2 : 0) + (fp32 ? 1 : 0);
+    const uint32_t S = cplx ? qmck::S_COMPLEX : qmck::S_REAL;
+    const uint64_t tmin = cplx ? c->batch_tile_complex : c->batch_tile_real;
+    uint64_t tp = std::max<uint64_t>(tmin, (b.n + c->batch_max_ktiles - 1) / c->batch_max_ktiles);
+    tp = (tp + QMCD_BLOCK - 1) / QMCD_BLOCK * QMCD_BLOCK;
+    p.tile_points = tp;
+    p.ktiles = (uint32_t)((b.n + tp - 1) / tp);
+    p.groups = (b.m + S - 1) / S;
+    p.rows = cplx ? 2 * b.m : b.m;
+    p.part_off = n_part;
+    n_part += (size_t)p.rows * p.ktiles;
+    p.sh_off = n_sh;
+    n_sh += (size_t)b.m * f->dim;
+    p.row0 = n_rows;
+    n_rows += p.rows;
+    p.cost = cost_per_eval(f) * (double)b.n * b.m;
+  }
+  // variants present, items ordered heaviest first
+  std::map<int, std::vector<uint32_t>> by_var;
+  for (uint32_t i = 0; i < J; ++i) by_var[plan[i].variant].push_back(i);
+  for (auto& kv : by_var)
+    std::stable_sort(kv.second.begin(), kv.second.end(), [&](uint32_t x, uint32_t y) { return plan[x].cost > plan[y].cost; });
+  const uint32_t NV = (uint32_t)by_var.size();
+
+  // device layout
+  size_t off = 0;
+  const size_t o_items = off;
+  off = align256(off + (size_t)J * sizeof(qmcd::EvalArgs));
+  const size_t o_order = off;
+  off = align256(off + (size_t)J * 4);
+  const size_t o_prefix = off;
+  off = align256(off + (size_t)(J + NV) * 4);
+  const size_t o_rows = off;
+  off = align256(off + n_rows * sizeof(qmck::RowRef));
+  const size_t o_sh = off;
+  off = align256(off + n_sh * 8);
+  const size_t upload = off;  // everything above comes from the host
+  const size_t o_part = off;
+  off = align256(off + n_part * 8);
+  const size_t o_out = off;
+  off = align256(off + n_rows * 8 + (size_t)J * 8);
+  const size_t o_cnt = off;
+  off = align256(off + (size_t)NV * 4);
+  char* ws = nullptr;
+  int rc = scratch(c, off, &ws);
+  if (rc) return rc;
+  rc = stage(c, std::max(upload, n_rows * 8 + (size_t)J * 8));
+  if (rc) return rc;
+  char* h = (char*)c->h_stage;
+  std::memset(h, 0, upload);
+
+  qmcd::EvalArgs* items = (qmcd::EvalArgs*)(h + o_items);
+  qmck::RowRef* rows = (qmck::RowRef*)(h + o_rows);
+  double* shifts = (double*)(h + o_sh);
+  double* d_part = (double*)(ws + o_part);
+  double* d_out = (double*)(ws + o_out);
+  unsigned long long* d_sign = (unsigned long long*)(ws + o_out + n_rows * 8);
+  for (uint32_t i = 0; i < J; ++i) {
+    BatchJob& b = *jobs[i];
+    const Plan& p = plan[i];
+    qmcd::EvalArgs& a = items[i];
+    int tsel = 0;
+    rc = fill_integrand_args(a, b.f, b.t, tsel);
+    if (rc) return rc;
+    a.n = b.n;
+    a.n_d = (double)b.n;
+    a.inv_n = 1.0 / (double)b.n;
+    for (uint32_t j = 0; j < b.f->dim; ++j) {
+      a.z[j] = b.z[j] % b.n;
+      a.step[j] = mulmod(QMCD_BLOCK % b.n, a.z[j], b.n);
+    }
+    a.m = b.m;
+    a.shifts = (const double*)(ws + o_sh) + p.sh_off;
+    a.partial = d_part + p.part_off;
+    a.nblocks = p.ktiles;
+    a.sign_count = d_sign + i;
+    a.tile_points = p.tile_points;
+    a.ktiles = p.ktiles;
+    a.item = i;
+    std::memcpy(shifts + p.sh_off, b.shifts, (size_t)b.m * b.f->dim * 8);
+    for (uint32_t r = 0; r < p.rows; ++r) {
+      rows[p.row0 + r].p = d_part + p.part_off + (size_t)r * p.ktiles;
+      rows[p.row0 + r].ncols = p.ktiles;
+    }
+  }
+  uint32_t* order = (uint32_t*)(h + o_order);
+  uint32_t* prefix = (uint32_t*)(h + o_prefix);
+  struct Launch {
+    int dclass;
+    bool cplx, fp32;
+    uint32_t first, count, prefix_off;
+  };
+  std::vector<Launch> launches;
+  uint32_t pos = 0, ppos = 0;
+  for (auto& kv : by_var) {
+    Launch L;
+    L.dclass = kv.first / 4;
+    L.cplx = (kv.first & 2) != 0;
+    L.fp32 = (kv.first & 1) != 0;
+    L.first = pos;
+    L.count = (uint32_t)kv.second.size();
+    L.prefix_off = ppos;
+    uint64_t acc = 0;
+    for (uint32_t q = 0; q < L.count; ++q) {
+      uint32_t i = kv.second[q];
+      order[pos + q] = i;
+      prefix[ppos + q] = (uint32_t)acc;
+      acc += (uint64_t)plan[i].ktiles * plan[i].groups;
+    }
+    if (acc >= 0xFFFFFFFFull) return fail(QMC_EINVAL, "batch has more than 2^32 tiles");
+    prefix[ppos + L.count] = (uint32_t)acc;
+    pos += L.count;
+    ppos += L.count + 1;
+    launches.push_back(L);
+  }
+  HIPCHK(hipMemcpyAsync(ws, h, upload, hipMemcpyHostToDevice, c->stream));
+
+  auto enqueue = [&](hipStream_t st) -> int {
+    HIPCHK(qmck::launch_fill_u32((uint32_t*)(ws + o_cnt), NV, 0u, st));
+    HIPCHK(qmck::launch_fill_u64(d_sign, J, 0ull, st));
+    for (uint32_t v = 0; v < (uint32_t)launches.size(); ++v) {
+      const Launch& L = launches[v];
+      int occ = qmck::occupancy_batch(L.dclass, L.cplx, L.fp32);
+      uint32_t blocks = (uint32_t)std::max(1, occ) * (uint32_t)c->cus;
+      HIPCHK(qmck::launch_batch(L.dclass, L.cplx, L.fp32, (const qmcd::EvalArgs*)(ws + o_items),
+                                (const uint32_t*)(ws + o_order) + L.first,
+                                (const uint32_t*)(ws + o_prefix) + L.prefix_off, L.count,
+                                (uint32_t*)(ws + o_cnt) + v, blocks, st));
+    }
+    HIPCHK(qmck::launch_finalize_rows((const qmck::RowRef*)(ws + o_rows), (uint32_t)n_rows, d_out, st));
+    return QMC_OK;
+  };
+
+  HIPCHK(hipEventRecord(c->ev0, c->stream));
+  if (c->batch_graph) {
+    if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    int erc = enqueue(c->cap_stream);
+    hipError_t ec = hipStreamEndCapture(c->cap_stream, &g);
+    if (erc) {
+      if (g) (void)hipGraphDestroy(g);
+      return erc;
+    }
+    if (ec != hipSuccess) return fail(QMC_EDEVICE, "hipStreamEndCapture failed: %s", hipGetErrorString(ec));
+    hipGraphExec_t ge = nullptr;
+    hipError_t ei = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) return fail(QMC_EDEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(ei));
+    hipError_t el = hipGraphLaunch(ge, c->stream);
+    if (el != hipSuccess) {
+      (void)hipGraphExecDestroy(ge);
+      return fail(QMC_EDEVICE, "hipGraphLaunch failed: %s", hipGetErrorString(el));
+    }
+    HIPCHK(hipEventRecord(c->ev1, c->stream));
+    HIPCHK(hipMemcpyAsync(c->h_stage, d_out, n_rows * 8 + (size_t)J * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    (void)hipGraphExecDestroy(ge);
+  } else {
+    rc = enqueue(c->stream);
+    if (rc) return rc;
+    HIPCHK(hipEventRecord(c->ev1, c->stream));
+    HIPCHK(hipMemcpyAsync(c->h_stage, d_out, n_rows * 8 + (size_t)J * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+  }
+  float ms = 0;
+  HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  if (kernel_seconds) *kernel_seconds = ms * 1e-3;
+  const unsigned long long* sg = (const unsigned long long*)(c->h_stage + n_rows);
+  for (uint32_t i = 0; i < J; ++i) {
+    const Plan& p = plan[i];
+    jobs[i]->sums.assign(c->h_stage + p.row0, c->h_stage + p.row0 + p.rows);
+    jobs[i]->sign_points = sg[i];
+  }
+  return QMC_OK;
+}
+
+int run_requests(qmc_context* c, const qmc_request* reqs, uint32_t count, qmc_result* out, double* shift_sums) {
+  auto t0 = std::chrono::steady_clock::now();
+  struct St {
+    qmc_integrand* f;
+    std::vector<double> shifts;
+    std::vector<uint64_t> z;
+    uint64_t n;
+    bool done = false;
+    qmc_result r{};
+    BatchJob job;
+  };
+  std::vector<St> st(count);
+  for (uint32_t i = 0; i < count; ++i) {
+    const qmc_request& q = reqs[i];
+    if (!q.f) return fail(QMC_EINVAL, "request %u has no integrand", i);
+    St& s = st[i];
+    s.f = const_cast<qmc_integrand*>(q.f);
+    if (s.f->ctx != c) return fail(QMC_EINVAL, "request %u: integrand belongs to another context", i);
+    if (q.m < 1 || q.m > QMC_MAX_SHIFTS) return fail(QMC_EINVAL, "request %u: m=%u", i, q.m);
+    const uint32_t dim = s.f->dim;
+    if (q.z) {
+      int rc = check_lattice(q.n, dim, q.z);
+      if (rc) return rc;
+      s.n = q.n;
+      s.z.assign(q.z, q.z + dim);
+    } else {
+      uint64_t nn = 0;
+      if (next_registered(c, q.n, dim, &nn, true) != QMC_OK)
+        return fail(QMC_ENOTFOUND, "request %u: no registered lattice with %u components", i, dim);
+      s.n = nn;
+      s.z.assign(c->lattices[nn].begin(), c->lattices[nn].begin() + dim);
+    }
+    s.shifts.resize((size_t)q.m * dim);
+    make_shifts(q.seed, q.m, dim, s.shifts.data());
+    s.r.m = q.m;
+    s.r.path = 2;
+  }
+  double dev = 0.0;
+  for (;;) {
+    std::vector<BatchJob*> jobs;
+    std::vector<uint32_t> idx;
+    for (uint32_t i = 0; i < count; ++i) {
+      St& s = st[i];
+      if (s.done) continue;
+      s.job.f = s.f;
+      s.job.n = s.n;
+      s.job.z = s.z.data();
+      s.job.m = reqs[i].m;
+      s.job.shifts = s.shifts.data();
+      s.job.t = reqs[i].t;
+      jobs.push_back(&s.job);
+      idx.push_back(i);
+    }
+    if (jobs.empty()) break;
+    double ks = 0.0;
+    int rc = run_batch(c, jobs, &ks);
+    if (rc) return rc;
+    dev += ks;
+    for (uint32_t i : idx) {
+      St& s = st[i];
+      const qmc_request& q = reqs[i];
+      const bool cplx = (s.f->flags & QMC_DEFORM) != 0;
+      const uint32_t m = q.m;
+      s.r.iterations += 1;
+      s.r.evaluations += s.n * (uint64_t)m;
+      s.r.n = s.n;
+      std::vector<double> qs(m);
+      for (uint32_t k = 0; k < m; ++k) qs[k] = s.job.sums[k] / (double)s.n;
+      estimate(qs.data(), m, s.r.re, s.r.err_re);
+      s.r.im = s.r.err_im = 0.0;
+      if (cplx) {
+        for (uint32_t k = 0; k < m; ++k) qs[k] = s.job.sums[m + k] / (double)s.n;
+        estimate(qs.data(), m, s.r.im, s.r.err_im);
+      }
+      s.r.flags &= ~(uint32_t)(QMC_NONFINITE | QMC_DEFORM_SIGN);
+      if (s.job.sign_points) s.r.flags |= QMC_DEFORM_SIGN;
+      const bool finite = std::isfinite(s.r.re) && std::isfinite(s.r.im);
+      if (!finite) s.r.flags |= QMC_NONFINITE;
+      const bool grow = q.rel_tol > 0 || q.abs_tol > 0;
+      if (!grow) {
+        s.done = true;
+        continue;
+      }
+      if (finite && goal_met(s.r, q.rel_tol, q.abs_tol, q.errormode, cplx)) {
+        s.r.flags |= QMC_CONVERGED;
+        s.done = true;
+        continue;
+      }
+      double goal = std::max(q.abs_tol, q.rel_tol * (cplx ? std::max(std::fabs(s.r.re), std::fabs(s.r.im))
+                                                          : std::fabs(s.r.re)));
+      double err = cplx ? std::max(s.r.err_re, s.r.err_im) : s.r.err_re;
+      double want = std::max(1.5 * (double)s.n, goal > 0 && std::isfinite(err) ? (double)s.n * err / goal : 2.0 * s.n);
+      uint64_t wantu = want >= 9.0e15 ? (uint64_t)9.0e15 : (uint64_t)std::ceil(want);
+      uint64_t nn = 0;
+      if (next_registered(c, wantu, s.f->dim, &nn, false) != QMC_OK ||
+          (q.max_evals && s.r.evaluations + nn * (uint64_t)m > q.max_evals)) {
+        s.r.flags |= QMC_MAXEVAL_HIT;
+        s.done = true;
+        continue;
+      }
+      s.n = nn;
+      s.z.assign(c->lattices[nn].begin(), c->lattices[nn].begin() + s.f->dim);
+    }
+  }
+  const double wall = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  size_t off = 0;
+  for (uint32_t i = 0; i < count; ++i) {
+    st[i].r.device_seconds = dev;  // shared launches: the batch's total device time
+    st[i].r.wall_seconds = wall;
+    if (out) out[i] = st[i].r;
+    if (shift_sums) {
+      std::memcpy(shift_sums + off, st[i].job.sums.data(), st[i].job.sums.size() * 8);
+      off += st[i].job.sums.size();
+    }
+  }
+  return QMC_OK;
+}
+
+}  // namespace qmch

@@ -38,7 +38,7 @@ typedef unsigned char uint8_t;
 
 namespace qmcd {
 
-enum { TK_NONE = 0, TK_KOROBOV = 1, TK_BAKER = 2, TK_KOROBOV3 = 3 };
+enum { TK_NONE = 0, TK_KOROBOV = 1, TK_BAKER = 2, TK_KOROBOV3 = 3, TK_RUNTIME = 4 };  // RUNTIME: EvalArgs::tk
 enum { PW_ONE = 0, PW_INT = 1, PW_HALF = 2, PW_GEN = 3 };
 
 // Everything one evaluation launch needs, passed by value.
@@ -68,7 +68,35 @@ struct EvalArgs {
   double om_c[26];
   const double* vr;           // [dim][6] or nullptr
   double wscale;              // Korobov r=3: prod_j omega = wscale * (prod_j u_j (1-u_j))^3, wscale = 140^dim
+  unsigned long long* sign_count;  // complex kernels: points with Im F(z) > 0
+  int32_t tk;                 // transform kind for TK_RUNTIME kernels (TK_NONE..TK_KOROBOV3)
+  const float* coef32;        // coefficients rounded to fp32 (fp32-evaluation kernels)
+  uint64_t tile_points;       // batch: points per tile (a multiple of the block size)
+  uint32_t ktiles;            // batch: tiles along k (= columns of partial[][])
+  uint32_t item;              // batch: index of this integral
 };
+
+// Where one workgroup's threads sit in the lattice and where their sums go.
+// Single launches derive it from the grid; the batch kernels from a tile.
+struct Sched {
+  uint64_t k;             // this thread's first point
+  uint64_t k_end;         // one past the last point
+  uint64_t stride;        // distance between a thread's consecutive points
+  const uint64_t* step;   // (stride * z_j) mod n
+  uint32_t col;           // column of partial[][] written by this workgroup
+  uint32_t s0;            // first shift of the group
+};
+
+__device__ __forceinline__ Sched grid_sched(const EvalArgs& a, int S) {
+  Sched sc;
+  sc.k = a.k_begin + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  sc.k_end = a.k_end;
+  sc.stride = a.stride;
+  sc.step = a.step;
+  sc.col = blockIdx.x;
+  sc.s0 = blockIdx.y * S;
+  return sc;
+}
 
 // ------------------------------------------------------------------ indices
 
@@ -151,8 +179,27 @@ __device__ __forceinline__ double korobov3(double u, double& s) {
 }
 
 template <int TK>
+__device__ __forceinline__ double transform(double u, double& w, const EvalArgs& a);
+
+// transform chosen per integrand (uniform branch), for the batch kernels
+__device__ __forceinline__ double transform_rt(double u, double& w, const EvalArgs& a) {
+  switch (a.tk) {
+    case TK_KOROBOV3:
+      return transform<TK_KOROBOV3>(u, w, a);
+    case TK_KOROBOV:
+      return transform<TK_KOROBOV>(u, w, a);
+    case TK_BAKER:
+      return transform<TK_BAKER>(u, w, a);
+    default:
+      return u;
+  }
+}
+
+template <int TK>
 __device__ __forceinline__ double transform(double u, double& w, const EvalArgs& a) {
-  if (TK == TK_NONE) {
+  if (TK == TK_RUNTIME) {
+    return transform_rt(u, w, a);
+  } else if (TK == TK_NONE) {
     return u;
   } else if (TK == TK_KOROBOV3) {
     double sv;
@@ -286,6 +333,388 @@ struct GenericReal {
   }
 };
 
+
+// ------------------------------------------------------------------ complex integrands (contour deformation)
+
+struct cplx {
+  double re, im;
+};
+__device__ __forceinline__ cplx cmk(double r, double i) { return cplx{r, i}; }
+__device__ __forceinline__ cplx cmul(cplx a, cplx b) {
+  return cplx{__builtin_fma(a.re, b.re, -(a.im * b.im)), __builtin_fma(a.re, b.im, a.im * b.re)};
+}
+// a * b + c
+__device__ __forceinline__ cplx cfma(cplx a, cplx b, cplx c) {
+  return cplx{__builtin_fma(a.re, b.re, __builtin_fma(-a.im, b.im, c.re)),
+              __builtin_fma(a.re, b.im, __builtin_fma(a.im, b.re, c.im))};
+}
+// real r * complex b + complex c
+__device__ __forceinline__ cplx cfmar(double r, cplx b, cplx c) {
+  return cplx{__builtin_fma(r, b.re, c.re), __builtin_fma(r, b.im, c.im)};
+}
+__device__ __forceinline__ cplx cscale(double r, cplx b) { return cplx{r * b.re, r * b.im}; }
+__device__ __forceinline__ cplx crcp(cplx a) {
+  double n = __builtin_fma(a.re, a.re, a.im * a.im);
+  double r = fast_rcp(n);
+  return cplx{a.re * r, -a.im * r};
+}
+// Principal square root with the -i0 side on the negative real axis:
+// Im w = +-0 is read as -0, so sqrt(-|w|) = -i sqrt(|w|).
+__device__ __forceinline__ cplx csqrt_feyn(cplx w) {
+  double im = (w.im == 0.0) ? -0.0 : w.im;
+  double r = __builtin_sqrt(__builtin_fma(w.re, w.re, im * im));
+  if (w.re >= 0.0) {
+    double t = __builtin_sqrt(0.5 * (r + w.re));
+    return cplx{t, (t == 0.0) ? 0.0 : 0.5 * im / t};
+  }
+  double t = __builtin_sqrt(0.5 * (r - w.re));
+  return cplx{0.5 * __builtin_fabs(im) / t, __builtin_copysign(t, im)};
+}
+// w^p = exp(p Log w), principal branch with arg = -pi on the negative real axis
+__device__ __forceinline__ cplx cpow_feyn(cplx w, double p) {
+  double im = (w.im == 0.0) ? -0.0 : w.im;
+  double lr = log(__builtin_sqrt(__builtin_fma(w.re, w.re, im * im)));
+  double th = atan2(im, w.re);
+  double mag = exp(p * lr);
+  double sn, cs;
+  sincos(p * th, &sn, &cs);
+  return cplx{mag * cs, mag * sn};
+}
+// v^p folded into num/den (complex): integer and half-integer powers use
+// products and one principal square root
+__device__ __forceinline__ void apply_cpow(cplx v, int mode, int k, double p, cplx& num, cplx& den) {
+  if (mode == PW_ONE) return;
+  if (mode == PW_GEN) {
+    num = cmul(num, cpow_feyn(v, p));
+    return;
+  }
+  int ak = k < 0 ? -k : k;
+  cplx a = cmk(1.0, 0.0), b = v;
+  while (ak) {
+    if (ak & 1) a = cmul(a, b);
+    b = cmul(b, b);
+    ak >>= 1;
+  }
+  if (k >= 0)
+    num = cmul(num, a);
+  else
+    den = cmul(den, a);
+  if (mode == PW_HALF) num = cmul(num, csqrt_feyn(v));
+}
+
+template <int D>
+struct Tri {
+  static constexpr int N = D * (D + 1) / 2;
+  __device__ static constexpr int at(int i, int j) { return i * (i + 1) / 2 + j; }  // i >= j
+};
+
+// det of a complex symmetric matrix (lower triangle, in place) by LDL^T without
+// pivoting; stable here because the Hermitian part of I - i lambda A is I.
+template <int D>
+__device__ __forceinline__ cplx ldl_det(cplx (&B)[Tri<D>::N]) {
+  cplx det = cmk(1.0, 0.0);
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    cplx dk = B[Tri<D>::at(k, k)];
+    det = cmul(det, dk);
+    cplx inv = crcp(dk);
+    cplx l[D];
+#pragma unroll
+    for (int i = k + 1; i < D; ++i) l[i] = cmul(B[Tri<D>::at(i, k)], inv);
+#pragma unroll
+    for (int i = k + 1; i < D; ++i)
+#pragma unroll
+      for (int j = k + 1; j <= i; ++j) {
+        cplx t = cmul(l[i], B[Tri<D>::at(j, k)]);
+        B[Tri<D>::at(i, j)] = cmk(B[Tri<D>::at(i, j)].re - t.re, B[Tri<D>::at(i, j)].im - t.im);
+      }
+  }
+  return det;
+}
+
+// f at the deformed point z = x - i lambda x(1-x) grad F(x), times det(dz/dx).
+// Fn provides grad_hess (real, at x) and the polynomials U, F at complex z.
+template <int D, class Fn>
+__device__ __forceinline__ cplx deformed_integrand(const double (&x)[D], const Fn& fn, const EvalArgs& a,
+                                                   uint32_t& sign) {
+  double g[D];
+  double H[Tri<D>::N];
+  fn.grad_hess(x, g, H, a);
+  const double lam = a.lambda;
+  double d2[D], sq[D];
+  cplx z[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    // x (1-x); rounding can put x a few ulp above 1 (the Korobov polynomial
+    // near u = 1), which would make the symmetrising square root NaN
+    double t = __builtin_fma(-x[j], x[j], x[j]);
+    d2[j] = t > 0.0 ? t : 0.0;
+    sq[j] = __builtin_sqrt(d2[j]);
+    z[j] = cmk(x[j], -lam * d2[j] * g[j]);
+  }
+  // B = I - i lambda (S H S + diag((1-2x) g)), S = diag(sqrt(x(1-x))), similar to dz/dx
+  cplx B[Tri<D>::N];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j) {
+      double A = sq[i] * H[Tri<D>::at(i, j)] * sq[j];
+      if (i == j) A = __builtin_fma(__builtin_fma(-2.0, x[i], 1.0), g[i], A);
+      B[Tri<D>::at(i, j)] = cmk(i == j ? 1.0 : 0.0, -lam * A);
+    }
+  cplx det = ldl_det<D>(B);
+  return cmul(cscale(a.prefactor, det), fn.uf(z, a, sign));
+}
+
+// U(z)^pow_u F(z)^pow_f in fp64 from the functor's polynomials
+template <int D, class Fn>
+__device__ __forceinline__ cplx uf_fp64(const Fn& fn, const cplx (&z)[D], const EvalArgs& a, uint32_t& sign) {
+  cplx num = cmk(1.0, 0.0), den = cmk(1.0, 0.0);
+  cplx Uz = fn.U(z, a);
+  apply_cpow(Uz, a.pu_mode, a.pu_k, a.pow_u, num, den);
+  if (a.n_f) {
+    cplx Fz = fn.F(z, a);
+    sign += (Fz.im > 0.0) ? 1u : 0u;
+    apply_cpow(Fz, a.pf_mode, a.pf_k, a.pow_f, num, den);
+  }
+  return cmul(num, crcp(den));
+}
+
+// Generic (table-driven) polynomial pieces for the deformed integrand.
+template <int DMAX>
+struct GenericComplex {
+  // gradient and Hessian of F at real x by exponent arithmetic (no division by x)
+  __device__ __forceinline__ void grad_hess(const double (&x)[DMAX], double (&g)[DMAX], double (&H)[Tri<DMAX>::N],
+                                            const EvalArgs& a) const {
+#pragma unroll
+    for (int j = 0; j < DMAX; ++j) g[j] = 0.0;
+#pragma unroll
+    for (int j = 0; j < Tri<DMAX>::N; ++j) H[j] = 0.0;
+    for (uint32_t i = a.n_u; i < a.n_u + a.n_f; ++i) {
+      const double c = a.coef[i];
+      uint32_t e[DMAX];
+#pragma unroll
+      for (int j = 0; j < DMAX; ++j) e[j] = (a.expo[2 * i + j / 8] >> (4 * (j % 8))) & 15u;
+      double P[DMAX], D1[DMAX], D2[DMAX];
+#pragma unroll
+      for (int j = 0; j < DMAX; ++j) {
+        // x^e, e x^(e-1), e (e-1) x^(e-2)
+        double pe = 1.0, pe1 = 0.0, pe2 = 0.0;
+        if (e[j] >= 1u) {
+          double q2 = 1.0;  // x^(e-2)
+          for (uint32_t t = 2; t < e[j]; ++t) q2 *= x[j];
+          double q1 = e[j] >= 2u ? q2 * x[j] : 1.0;  // x^(e-1)
+          pe = q1 * x[j];
+          pe1 = (double)e[j] * q1;
+          pe2 = e[j] >= 2u ? (double)(e[j] * (e[j] - 1u)) * q2 : 0.0;
+        }
+        P[j] = pe;
+        D1[j] = pe1;
+        D2[j] = pe2;
+      }
+      double pre[DMAX + 1], suf[DMAX + 1];
+      pre[0] = c;
+#pragma unroll
+      for (int j = 0; j < DMAX; ++j) pre[j + 1] = pre[j] * P[j];
+      suf[DMAX] = 1.0;
+#pragma unroll
+      for (int j = DMAX - 1; j >= 0; --j) suf[j] = suf[j + 1] * P[j];
+#pragma unroll
+      for (int j = 0; j < DMAX; ++j) {
+        if (e[j] == 0u) continue;
+        g[j] = __builtin_fma(pre[j] * D1[j], suf[j + 1], g[j]);
+        if (e[j] >= 2u) H[Tri<DMAX>::at(j, j)] = __builtin_fma(pre[j] * D2[j], suf[j + 1], H[Tri<DMAX>::at(j, j)]);
+        double mid = pre[j] * D1[j];  // c prod_{q<j} P_q * D1_j * prod_{j<q<l} P_q
+#pragma unroll
+        for (int l = j + 1; l < DMAX; ++l) {
+          if (e[l] != 0u) H[Tri<DMAX>::at(l, j)] = __builtin_fma(mid * D1[l], suf[l + 1], H[Tri<DMAX>::at(l, j)]);
+          mid *= P[l];
+        }
+      }
+    }
+  }
+  __device__ __forceinline__ cplx poly(const cplx (&z)[DMAX], uint32_t first, uint32_t count,
+                                       const EvalArgs& a) const {
+    cplx s = cmk(0.0, 0.0);
+    for (uint32_t i = first; i < first + count; ++i) {
+      cplx t = cmk(a.coef[i], 0.0);
+#pragma unroll
+      for (int j = 0; j < DMAX; ++j) {
+        uint32_t e = (a.expo[2 * i + j / 8] >> (4 * (j % 8))) & 15u;
+        for (uint32_t q = 0; q < e; ++q) t = cmul(t, z[j]);
+      }
+      s = cmk(s.re + t.re, s.im + t.im);
+    }
+    return s;
+  }
+  __device__ __forceinline__ cplx U(const cplx (&z)[DMAX], const EvalArgs& a) const { return poly(z, 0, a.n_u, a); }
+  __device__ __forceinline__ cplx F(const cplx (&z)[DMAX], const EvalArgs& a) const {
+    return poly(z, a.n_u, a.n_f, a);
+  }
+  __device__ __forceinline__ cplx uf(const cplx (&z)[DMAX], const EvalArgs& a, uint32_t& sign) const {
+    return uf_fp64<DMAX>(*this, z, a, sign);
+  }
+};
+
+// ------------------------------------------------------------------ fp32 evaluation of U, F and the powers
+// Index arithmetic, transform, weights, the deformation Jacobian and the sums
+// stay fp64; only the polynomials and powers run in fp32.
+
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
+__device__ __forceinline__ void apply_pow_f32(float v, int mode, int k, double p, float& num, float& den) {
+  if (mode == PW_ONE) return;
+  if (mode == PW_GEN) {
+    num *= __builtin_exp2f((float)p * __builtin_log2f(v));
+    return;
+  }
+  int kk = k;
+  if (mode == PW_HALF && k < 0) kk = k + 1;
+  int ak = kk < 0 ? -kk : kk;
+  float a = 1.0f, b = v;
+  while (ak) {
+    if (ak & 1) a *= b;
+    b *= b;
+    ak >>= 1;
+  }
+  if (kk >= 0)
+    num *= a;
+  else
+    den *= a;
+  if (mode == PW_HALF) num *= (k < 0) ? frsq(v) : __builtin_sqrtf(v);
+}
+
+template <int DMAX>
+__device__ __forceinline__ float poly_eval_f32(const float* __restrict__ coef, const uint32_t* __restrict__ expo,
+                                               uint32_t first, uint32_t count, const float (&x)[DMAX],
+                                               const float (&x2)[DMAX]) {
+  float s = 0.0f;
+  for (uint32_t i = first; i < first + count; ++i) {
+    float t = coef[i];
+    uint32_t w0 = expo[2 * i];
+#pragma unroll
+    for (int j = 0; j < (DMAX < 8 ? DMAX : 8); ++j) {
+      uint32_t e = (w0 >> (4 * j)) & 15u;
+      if (e) t *= xpow<float>(x[j], x2[j], e);
+    }
+    if (DMAX > 8) {
+      uint32_t w1 = expo[2 * i + 1];
+#pragma unroll
+      for (int j = 8; j < DMAX; ++j) {
+        uint32_t e = (w1 >> (4 * (j - 8))) & 15u;
+        if (e) t *= xpow<float>(x[j], x2[j], e);
+      }
+    }
+    s += t;
+  }
+  return s;
+}
+
+template <int DMAX>
+struct GenericRealF32 {
+  __device__ __forceinline__ double operator()(const double (&x)[DMAX], const EvalArgs& a) const {
+    float xf[DMAX], x2[DMAX];
+#pragma unroll
+    for (int j = 0; j < DMAX; ++j) {
+      xf[j] = (float)x[j];
+      x2[j] = xf[j] * xf[j];
+    }
+    float U = poly_eval_f32<DMAX>(a.coef32, a.expo, 0, a.n_u, xf, x2);
+    float num = (float)a.prefactor, den = 1.0f;
+    apply_pow_f32(U, a.pu_mode, a.pu_k, a.pow_u, num, den);
+    if (a.n_f) {
+      float F = poly_eval_f32<DMAX>(a.coef32, a.expo, a.n_u, a.n_f, xf, x2);
+      apply_pow_f32(F, a.pf_mode, a.pf_k, a.pow_f, num, den);
+    }
+    return (double)(num * frcp(den));
+  }
+};
+
+struct cplxf {
+  float re, im;
+};
+__device__ __forceinline__ cplxf cmulf(cplxf a, cplxf b) {
+  return cplxf{__builtin_fmaf(a.re, b.re, -(a.im * b.im)), __builtin_fmaf(a.re, b.im, a.im * b.re)};
+}
+__device__ __forceinline__ cplxf crcpf(cplxf a) {
+  float r = frcp(__builtin_fmaf(a.re, a.re, a.im * a.im));
+  return cplxf{a.re * r, -a.im * r};
+}
+__device__ __forceinline__ cplxf csqrtf_feyn(cplxf w) {
+  float im = (w.im == 0.0f) ? -0.0f : w.im;
+  float r = __builtin_sqrtf(__builtin_fmaf(w.re, w.re, im * im));
+  if (w.re >= 0.0f) {
+    float t = __builtin_sqrtf(0.5f * (r + w.re));
+    return cplxf{t, (t == 0.0f) ? 0.0f : 0.5f * im / t};
+  }
+  float t = __builtin_sqrtf(0.5f * (r - w.re));
+  return cplxf{0.5f * __builtin_fabsf(im) / t, __builtin_copysignf(t, im)};
+}
+__device__ __forceinline__ cplxf cpowf_feyn(cplxf w, float p) {
+  float im = (w.im == 0.0f) ? -0.0f : w.im;
+  float lr = 0.5f * __builtin_log2f(__builtin_fmaf(w.re, w.re, im * im)) * 0.69314718f;
+  float th = atan2f(im, w.re);
+  float mag = __builtin_exp2f(p * lr * 1.44269504f);
+  float sn, cs;
+  sincosf(p * th, &sn, &cs);
+  return cplxf{mag * cs, mag * sn};
+}
+__device__ __forceinline__ void apply_cpow_f32(cplxf v, int mode, int k, double p, cplxf& num, cplxf& den) {
+  if (mode == PW_ONE) return;
+  if (mode == PW_GEN) {
+    num = cmulf(num, cpowf_feyn(v, (float)p));
+    return;
+  }
+  int ak = k < 0 ? -k : k;
+  cplxf a = cplxf{1.0f, 0.0f}, b = v;
+  while (ak) {
+    if (ak & 1) a = cmulf(a, b);
+    b = cmulf(b, b);
+    ak >>= 1;
+  }
+  if (k >= 0)
+    num = cmulf(num, a);
+  else
+    den = cmulf(den, a);
+  if (mode == PW_HALF) num = cmulf(num, csqrtf_feyn(v));
+}
+
+// Deformed integrand with U(z), F(z) and their powers in fp32; the gradient,
+// Hessian and Jacobian determinant come from the fp64 GenericComplex.
+template <int DMAX>
+struct GenericComplexF32 : GenericComplex<DMAX> {
+  __device__ __forceinline__ cplxf polyf(const cplxf (&z)[DMAX], uint32_t first, uint32_t count,
+                                         const EvalArgs& a) const {
+    cplxf s = cplxf{0.0f, 0.0f};
+    for (uint32_t i = first; i < first + count; ++i) {
+      cplxf t = cplxf{a.coef32[i], 0.0f};
+#pragma unroll
+      for (int j = 0; j < DMAX; ++j) {
+        uint32_t e = (a.expo[2 * i + j / 8] >> (4 * (j % 8))) & 15u;
+        for (uint32_t q = 0; q < e; ++q) t = cmulf(t, z[j]);
+      }
+      s = cplxf{s.re + t.re, s.im + t.im};
+    }
+    return s;
+  }
+  __device__ __forceinline__ cplx uf(const cplx (&z)[DMAX], const EvalArgs& a, uint32_t& sign) const {
+    cplxf zf[DMAX];
+#pragma unroll
+    for (int j = 0; j < DMAX; ++j) zf[j] = cplxf{(float)z[j].re, (float)z[j].im};
+    cplxf num = cplxf{1.0f, 0.0f}, den = cplxf{1.0f, 0.0f};
+    cplxf Uz = polyf(zf, 0, a.n_u, a);
+    apply_cpow_f32(Uz, a.pu_mode, a.pu_k, a.pow_u, num, den);
+    if (a.n_f) {
+      cplxf Fz = polyf(zf, a.n_u, a.n_f, a);
+      sign += (Fz.im > 0.0f) ? 1u : 0u;
+      apply_cpow_f32(Fz, a.pf_mode, a.pf_k, a.pow_f, num, den);
+    }
+    cplxf f = cmulf(num, crcpf(den));
+    return cmk((double)f.re, (double)f.im);
+  }
+};
+
 // ------------------------------------------------------------------ reduction
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -294,10 +723,10 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// acc[s] of every thread -> partial[(row0 + s) * nblocks + blockIdx.x] for s < ns
+// acc[s] of every thread -> partial[(row0 + s) * nblocks + col] for s < ns
 template <int S>
 __device__ __forceinline__ void block_store(const double (&acc)[S], uint32_t ns, uint32_t row0,
-                                            double* __restrict__ partial, uint32_t nblocks) {
+                                            double* __restrict__ partial, uint32_t nblocks, uint32_t col) {
   __shared__ double red[S][QMCD_BLOCK / 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -310,31 +739,39 @@ __device__ __forceinline__ void block_store(const double (&acc)[S], uint32_t ns,
     double t = 0.0;
 #pragma unroll
     for (int w = 0; w < QMCD_BLOCK / 64; ++w) t += red[threadIdx.x][w];
-    partial[(size_t)(row0 + threadIdx.x) * nblocks + blockIdx.x] = t;
+    partial[(size_t)(row0 + threadIdx.x) * nblocks + col] = t;
   }
 }
 
 // ------------------------------------------------------------------ real evaluation
 
-// Grid: x over points (grid-stride), y over groups of S shifts.
+// One workgroup's share of the lattice (Sched) for a group of S shifts.
 // EXACT: the integrand has exactly DMAX variables (specialised kernels).
 // VRM: variance-reduction map 0 = decided at run time (a.vr), 1 = off, 2 = on.
+// COMP: compensated (Neumaier) accumulation of the contributions.
 enum { VRM_RUNTIME = 0, VRM_OFF = 1, VRM_ON = 2 };
-template <int DMAX, int TK, bool IDX32, int S, bool EXACT, class Fn, int VRM = VRM_RUNTIME>
-__device__ __forceinline__ void eval_real_body(const EvalArgs& a, const Fn& fn) {
-  const uint32_t s0 = blockIdx.y * S;
+
+__device__ __forceinline__ void neumaier(double& s, double& c, double v) {
+  double t = s + v;
+  c += (__builtin_fabs(s) >= __builtin_fabs(v)) ? (s - t) + v : (v - t) + s;
+  s = t;
+}
+
+template <int DMAX, int TK, bool IDX32, int S, bool EXACT, class Fn, int VRM = VRM_RUNTIME, bool COMP = false>
+__device__ __forceinline__ void eval_real_sched(const EvalArgs& a, const Fn& fn, const Sched& sc) {
+  const uint32_t s0 = sc.s0;
   const uint32_t ns = (a.m - s0) < (uint32_t)S ? (a.m - s0) : (uint32_t)S;
   const uint32_t dim = EXACT ? (uint32_t)DMAX : a.dim;
-  double acc[S];
+  double acc[S], cmp[S];
 #pragma unroll
-  for (int s = 0; s < S; ++s) acc[s] = 0.0;
+  for (int s = 0; s < S; ++s) acc[s] = cmp[s] = 0.0;
 
-  uint64_t k = a.k_begin + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint64_t k = sc.k;
   uint64_t r[DMAX];
 #pragma unroll
-  for (int j = 0; j < DMAX; ++j) r[j] = (j < (int)dim && k < a.k_end) ? start_index(k, a.z[j], a.n) : 0;
+  for (int j = 0; j < DMAX; ++j) r[j] = (j < (int)dim && k < sc.k_end) ? start_index(k, a.z[j], a.n) : 0;
 
-  for (; k < a.k_end; k += a.stride) {
+  for (; k < sc.k_end; k += sc.stride) {
     double q[DMAX];
 #pragma unroll
     for (int j = 0; j < DMAX; ++j)
@@ -357,21 +794,192 @@ __device__ __forceinline__ void eval_real_body(const EvalArgs& a, const Fn& fn) 
             x[j] = 0.0;
           }
         }
-        if (TK == TK_KOROBOV3) wt = a.wscale * (wt * wt * wt);  // 140^d (prod s_j)^3
+        if (TK == TK_KOROBOV3 || (TK == TK_RUNTIME && a.tk == TK_KOROBOV3))
+          wt = a.wscale * (wt * wt * wt);  // 140^d (prod s_j)^3
         double w = wt * wv;
         double f = fn(x, a);
-        acc[s] += (w == 0.0) ? 0.0 : w * f;
+        double v = (w == 0.0) ? 0.0 : w * f;
+        if (COMP)
+          neumaier(acc[s], cmp[s], v);
+        else
+          acc[s] += v;
       }
     }
 #pragma unroll
     for (int j = 0; j < DMAX; ++j) {
       if (IDX32)
-        r[j] = step_u32((uint32_t)r[j], (uint32_t)a.step[j], (uint32_t)a.n);
+        r[j] = step_u32((uint32_t)r[j], (uint32_t)sc.step[j], (uint32_t)a.n);
       else
-        r[j] = step_u64(r[j], a.step[j], a.n);
+        r[j] = step_u64(r[j], sc.step[j], a.n);
     }
   }
-  block_store<S>(acc, ns, s0, a.partial, a.nblocks);
+  if (COMP) {
+#pragma unroll
+    for (int s = 0; s < S; ++s) acc[s] += cmp[s];
+  }
+  block_store<S>(acc, ns, s0, a.partial, a.nblocks, sc.col);
+}
+
+template <int DMAX, int TK, bool IDX32, int S, bool EXACT, class Fn, int VRM = VRM_RUNTIME>
+__device__ __forceinline__ void eval_real_body(const EvalArgs& a, const Fn& fn) {
+  eval_real_sched<DMAX, TK, IDX32, S, EXACT, Fn, VRM, false>(a, fn, grid_sched(a, S));
+}
+
+// Complex (deformed) evaluation: rows [row0, row0+ns) hold Re, rows
+// [m + row0, ...) hold Im of the per-shift partial sums.
+// Padding variables (j >= dim in the class kernels) get x = 0: no monomial
+// uses them, so grad F and the row/column of B vanish apart from B_jj = 1.
+template <int DMAX, int TK, bool IDX32, int S, bool EXACT, class Fn, int VRM = VRM_RUNTIME, bool COMP = false>
+__device__ __forceinline__ void eval_complex_sched(const EvalArgs& a, const Fn& fn, const Sched& sc) {
+  const uint32_t s0 = sc.s0;
+  const uint32_t ns = (a.m - s0) < (uint32_t)S ? (a.m - s0) : (uint32_t)S;
+  const uint32_t dim = EXACT ? (uint32_t)DMAX : a.dim;
+  double acc_re[S], acc_im[S], c_re[S], c_im[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) acc_re[s] = acc_im[s] = c_re[s] = c_im[s] = 0.0;
+  uint32_t sign = 0;
+
+  uint64_t k = sc.k;
+  uint64_t r[DMAX];
+#pragma unroll
+  for (int j = 0; j < DMAX; ++j) r[j] = (j < (int)dim && k < sc.k_end) ? start_index(k, a.z[j], a.n) : 0;
+
+  for (; k < sc.k_end; k += sc.stride) {
+    double q[DMAX];
+#pragma unroll
+    for (int j = 0; j < DMAX; ++j)
+      q[j] = exact_quotient(IDX32 ? (double)(uint32_t)r[j] : (double)r[j], a.n_d, a.inv_n);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      if ((uint32_t)s < ns) {
+        const double* __restrict__ D = a.shifts + (size_t)(s0 + s) * dim;
+        double x[DMAX];
+        double wt = 1.0, wv = 1.0;
+#pragma unroll
+        for (int j = 0; j < DMAX; ++j) {
+          if (j < (int)dim) {
+            double u = shifted(q[j], D[j]);
+            double y = transform<TK>(u, wt, a);
+            if (VRM == VRM_ON || (VRM == VRM_RUNTIME && a.vr)) y = vr_map(y, a.vr + 6 * j, wv);
+            x[j] = y;
+          } else {
+            x[j] = 0.0;
+          }
+        }
+        if (TK == TK_KOROBOV3 || (TK == TK_RUNTIME && a.tk == TK_KOROBOV3)) wt = a.wscale * (wt * wt * wt);
+        double w = wt * wv;
+        uint32_t sg = 0;
+        cplx f = deformed_integrand<DMAX>(x, fn, a, sg);
+        bool live = (w != 0.0);
+        sign += live ? sg : 0u;
+        double vre = live ? w * f.re : 0.0, vim = live ? w * f.im : 0.0;
+        if (COMP) {
+          neumaier(acc_re[s], c_re[s], vre);
+          neumaier(acc_im[s], c_im[s], vim);
+        } else {
+          acc_re[s] += vre;
+          acc_im[s] += vim;
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < DMAX; ++j) {
+      if (IDX32)
+        r[j] = step_u32((uint32_t)r[j], (uint32_t)sc.step[j], (uint32_t)a.n);
+      else
+        r[j] = step_u64(r[j], sc.step[j], a.n);
+    }
+  }
+  if (COMP) {
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      acc_re[s] += c_re[s];
+      acc_im[s] += c_im[s];
+    }
+  }
+  block_store<S>(acc_re, ns, s0, a.partial, a.nblocks, sc.col);
+  __syncthreads();
+  block_store<S>(acc_im, ns, a.m + s0, a.partial, a.nblocks, sc.col);
+  // points on the wrong side of the cut: one atomic per wave
+  uint32_t tot = sign;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off, 64);
+  if ((threadIdx.x & 63) == 0 && tot) atomicAdd(a.sign_count, (unsigned long long)tot);
+}
+
+template <int DMAX, int TK, bool IDX32, int S, bool EXACT, class Fn, int VRM = VRM_RUNTIME>
+__device__ __forceinline__ void eval_complex_body(const EvalArgs& a, const Fn& fn) {
+  eval_complex_sched<DMAX, TK, IDX32, S, EXACT, Fn, VRM, false>(a, fn, grid_sched(a, S));
+}
+
+// ------------------------------------------------------------------ histograms for the VR fit (Sec. 2.4)
+
+// |f| at the raw points x = {k z/n + Delta} of one shifted lattice (no
+// periodizing transform, no VR map).  PASS 0: per-block max of |f| into
+// a.partial[block].  PASS 1: hist[j][floor(x_j * bins)] += rint(|f| * scale)
+// as 64-bit integers (exact, order-independent sums).
+struct HistArgs {
+  unsigned long long* hist;  // [dim][bins]
+  uint32_t bins;
+  double scale;              // 2^40 / max|f|
+};
+
+template <int DMAX, bool CPLX, int PASS>
+__device__ __forceinline__ void hist_body(const EvalArgs& a, const HistArgs& h) {
+  const uint32_t dim = a.dim;
+  const double* __restrict__ D = a.shifts;
+  double mx = 0.0;
+  for (uint64_t k = a.k_begin + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < a.k_end; k += a.stride) {
+    double x[DMAX];
+#pragma unroll
+    for (int j = 0; j < DMAX; ++j) {
+      if (j < (int)dim) {
+        double q = exact_quotient((double)start_index(k, a.z[j], a.n), a.n_d, a.inv_n);
+        x[j] = shifted(q, D[j]);
+      } else {
+        x[j] = 0.0;
+      }
+    }
+    double v;
+    if (CPLX) {
+      uint32_t sg = 0;
+      cplx f = deformed_integrand<DMAX>(x, GenericComplex<DMAX>(), a, sg);
+      v = __builtin_sqrt(__builtin_fma(f.re, f.re, f.im * f.im));
+    } else {
+      v = __builtin_fabs(GenericReal<DMAX>()(x, a));
+    }
+    if (!(v == v) || v > 1.7e308) v = 0.0;  // non-finite points carry no weight in the fit
+    if (PASS == 0) {
+      mx = v > mx ? v : mx;
+    } else {
+      unsigned long long c = (unsigned long long)__builtin_rint(v * h.scale);
+      if (c) {
+#pragma unroll
+        for (int j = 0; j < DMAX; ++j) {
+          if (j < (int)dim) {
+            uint32_t b = (uint32_t)(x[j] * (double)h.bins);
+            b = b < h.bins ? b : h.bins - 1;
+            atomicAdd(h.hist + (size_t)j * h.bins + b, c);
+          }
+        }
+      }
+    }
+  }
+  if (PASS == 0) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      double o = __shfl_xor(mx, off, 64);
+      mx = o > mx ? o : mx;
+    }
+    __shared__ double red[QMCD_BLOCK / 64];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double m = red[0];
+      for (int w = 1; w < QMCD_BLOCK / 64; ++w) m = red[w] > m ? red[w] : m;
+      a.partial[blockIdx.x] = m;
+    }
+  }
 }
 
 }  // namespace qmcd

@@ -1,0 +1,112 @@
+// qmc_host.h -- host-side state shared by the runtime, batch executor and scheduler.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <condition_variable>
+#include <cstdint>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "qmc.h"
+#include "qmc_internal.h"
+#include "qmc_jit.h"
+
+struct qmc_serve_state;  // qmc_serve.cpp
+
+struct qmc_context {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  // scratch: caller workspace or library-owned
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool own_ws = false;
+  // pinned host staging
+  double* h_stage = nullptr;
+  size_t h_stage_bytes = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  std::map<uint64_t, std::vector<uint64_t>> lattices;
+  std::recursive_mutex mu;
+  int inflight = 0;
+  int live_integrands = 0;  // the context is freed only after its last integrand
+  bool closing = false;     // destroy requested while integrands were alive
+  bool broken = false;
+  int max_blocks = 0;          // 0: from occupancy
+  int cus = 256;               // compute units of the device
+  int grid_rounds = 1;         // resident-block rounds per launch
+  bool jit = true;             // specialise kernels to the integrand
+  uint64_t jit_min_evals = 1ull << 24;
+  int jit_S = 8;
+  // batch executor
+  uint64_t batch_tile_real = 4096;    // minimum points per tile (real integrands)
+  uint64_t batch_tile_complex = 1024;  // ... (complex integrands)
+  uint64_t batch_max_ktiles = 2048;   // tiles along k per integral at most
+  bool batch_graph = true;            // replay each round's launches as a HIP graph
+  hipStream_t cap_stream = nullptr;   // private stream used only for graph capture
+};
+
+struct qmc_integrand {
+  qmc_context* ctx = nullptr;
+  uint32_t dim = 0, n_u = 0, n_f = 0, flags = 0;
+  double pow_u = 1, pow_f = 1, prefactor = 1, lambda = 0;
+  int pu_mode = 0, pu_k = 0, pf_mode = 0, pf_k = 0;
+  std::vector<double> coef;
+  std::vector<uint8_t> expo;
+  bool has_vr = false;
+  std::vector<double> vr;
+  char* dmem = nullptr;  // coef | expo (u32 x 2 per monomial) | vr
+  double* d_coef = nullptr;
+  uint32_t* d_expo = nullptr;
+  double* d_vr = nullptr;
+  float* d_coef32 = nullptr;
+  int refs = 0;
+  std::map<int, qmcj::Kernel> jit;  // per (transform kind, VR on) key
+  std::map<int, int> jit_failed;
+};
+
+
+namespace qmch {
+
+// error reporting (thread-local message, returns code)
+int fail(int code, const char* fmt, ...);
+void make_shifts(uint64_t seed, uint32_t m, uint32_t dim, double* out);
+uint64_t mulmod(uint64_t a, uint64_t b, uint64_t n);
+int check_lattice(uint64_t n, uint32_t dim, const uint64_t* z);
+int set_transform(qmcd::EvalArgs& a, const qmc_transform& t, int& tsel);
+int scratch(qmc_context* c, size_t need, char** out);
+int stage(qmc_context* c, size_t bytes);
+void estimate(const double* q, uint32_t m, double& mean, double& err);
+bool goal_met(const qmc_result& r, double rel, double abs_, uint32_t mode, bool cplx);
+int next_registered(qmc_context* c, uint64_t want, uint32_t dim, uint64_t* n_out, bool allow_smaller);
+// fill the integrand/transform part of an EvalArgs
+int fill_integrand_args(qmcd::EvalArgs& a, const qmc_integrand* f, const qmc_transform& t, int& tsel);
+
+// one integral's current lattice in a batch round
+struct BatchJob {
+  qmc_integrand* f = nullptr;
+  uint64_t n = 0;
+  const uint64_t* z = nullptr;   // [dim]
+  uint32_t m = 0;
+  const double* shifts = nullptr;  // [m][dim]
+  qmc_transform t{};
+  std::vector<double> sums;  // out: rows (m or 2m)
+  uint64_t sign_points = 0;  // out
+};
+// Evaluate all jobs with the persistent batch kernels (one round).
+int run_batch(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_seconds);
+// Requests through rounds of run_batch (growth loop per request).
+int run_requests(qmc_context* c, const qmc_request* reqs, uint32_t count, qmc_result* out, double* shift_sums);
+
+}  // namespace qmch
+
+#define HIPCHK(call)                                                                                  \
+  do {                                                                                                \
+    hipError_t e_ = (call);                                                                           \
+    if (e_ != hipSuccess) return qmch::fail(QMC_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+  } while (0)

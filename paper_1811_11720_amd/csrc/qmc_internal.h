@@ -17,16 +17,43 @@ enum Kind { KIND_REAL = 0 };
 
 // shifts per thread group of the real kernel (grid.y = ceil(m / S))
 constexpr int S_REAL = 8;
+// shifts per thread group of the complex kernels (one evaluation is ~1e3 instructions)
+constexpr int S_COMPLEX = 2;
+// ... of the specialised complex kernels (register pressure: one point's Jacobian at a time)
+constexpr int S_COMPLEX_JIT = 1;
+// largest dimension of the complex (deformed) kernels
+constexpr uint32_t MAX_DIM_COMPLEX = 12;
 
 // transform selector of the AOT kernels: generic Korobov, the written-out r=3 form, baker, none
 enum { TSEL_NONE = 0, TSEL_KOROBOV = 1, TSEL_BAKER = 2, TSEL_KOROBOV3 = 3 };
 
 hipError_t launch_eval_real(const qmcd::EvalArgs& a, int dclass, int tsel, bool idx32, dim3 grid,
                             hipStream_t st);
-int occupancy_eval_real(int dclass, int tsel, bool idx32);
+int occupancy_eval(bool cplx, int dclass, int tsel, bool idx32);
+hipError_t launch_eval_complex(const qmcd::EvalArgs& a, int dclass, int tsel, bool idx32, dim3 grid,
+                               hipStream_t st);
+hipError_t launch_hist(const qmcd::EvalArgs& a, const qmcd::HistArgs& h, int dclass, bool cplx, int pass, dim3 grid,
+                       hipStream_t st);
+hipError_t launch_fill_u64(unsigned long long* p, uint32_t count, unsigned long long v, hipStream_t st);
 hipError_t launch_finalize(const double* partial, uint32_t nblocks, uint32_t rows, double* out,
                            hipStream_t st);
 hipError_t launch_indices(uint64_t n, uint32_t dim, const uint64_t* z_host, uint64_t k0, uint64_t count,
                           uint32_t threads, uint64_t* out, hipStream_t st);
+
+// ---------------------------------------------------------------- batches
+using BatchFn = void (*)(const qmcd::EvalArgs*, const uint32_t*, const uint32_t*, uint32_t, uint32_t*);
+// [dclass][complex][fp32]; complex entries exist for classes up to 12 variables
+BatchFn batch_kernel(int dclass, bool cplx, bool fp32);
+int occupancy_batch(int dclass, bool cplx, bool fp32);
+hipError_t launch_batch(int dclass, bool cplx, bool fp32, const qmcd::EvalArgs* items, const uint32_t* order,
+                        const uint32_t* prefix, uint32_t nitems, uint32_t* counter, uint32_t blocks, hipStream_t st);
+
+// Sums rows of per-item partial arrays in a fixed order: out[r] = sum_c rows[r].p[c].
+struct RowRef {
+  const double* p;
+  uint32_t ncols, pad;
+};
+hipError_t launch_finalize_rows(const RowRef* rows, uint32_t nrows, double* out, hipStream_t st);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t count, uint32_t v, hipStream_t st);
 
 }  // namespace qmck

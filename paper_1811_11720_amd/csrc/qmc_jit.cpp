@@ -20,6 +20,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <set>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -31,6 +32,8 @@ namespace {
 const char* kDeviceSrc =
 #include "qmc_device_src.inc"
     ;
+
+int Tri_N(int d) { return d * (d + 1) / 2; }
 
 struct Term {
   uint32_t ci;
@@ -131,6 +134,240 @@ std::string horner(std::vector<Term> terms, Emitter& em) {
   return v;
 }
 
+// ---------------------------------------------------------------- complex integrands
+
+// A term whose coefficient is coef[ci] * mult (mult from differentiating).
+struct CTerm {
+  uint32_t ci;
+  int mult;
+  std::array<uint8_t, QMCD_MAXD> e;
+};
+
+struct Val {
+  std::string name;
+  bool real;  // a real scalar (coefficient); otherwise a cplx value in the complex domain
+};
+
+class CEmitter {
+ public:
+  CEmitter(int dim, bool cplx_domain) : dim_(dim), cx_(cplx_domain) {}
+  std::string tmp() { return std::string(cx_ ? "w" : "r") + std::to_string(ntmp_++); }
+  void line(const std::string& s) { body_ << "    " << s << "\n"; }
+  std::string coef(uint32_t i, int mult) {
+    std::string base = "c" + std::to_string(i);
+    coefs_.insert(i);
+    if (mult == 1) return base;
+    std::string n = base + "m" + std::to_string(mult);
+    if (!scaled_.count(n)) scaled_[n] = base + " * " + std::to_string(mult) + ".0";
+    return n;
+  }
+  std::string power(int j, int e) {
+    auto key = std::make_pair(j, e);
+    auto it = pows_.find(key);
+    if (it != pows_.end()) return it->second;
+    std::string n = std::string(cx_ ? "z" : "x") + std::to_string(j) + "_" + std::to_string(e);
+    std::string v;
+    if (e == 1) {
+      v = std::string(cx_ ? "z[" : "x[") + std::to_string(j) + "]";
+    } else if (e % 2 == 0) {
+      std::string h = power(j, e / 2);
+      v = cx_ ? "cmul(" + h + ", " + h + ")" : h + " * " + h;
+    } else {
+      std::string a = power(j, e - 1), b = power(j, 1);
+      v = cx_ ? "cmul(" + a + ", " + b + ")" : a + " * " + b;
+    }
+    pre_ << "    const " << (cx_ ? "cplx " : "double ") << n << " = " << v << ";\n";
+    pows_[key] = n;
+    return n;
+  }
+  std::string decls() const {
+    std::ostringstream o;
+    for (uint32_t i : coefs_) o << "    const double c" << i << " = a.coef[" << i << "];\n";
+    for (auto& kv : scaled_) o << "    const double " << kv.first << " = " << kv.second << ";\n";
+    return o.str();
+  }
+  std::string pre() const { return pre_.str(); }
+  std::string body() const { return body_.str(); }
+  int dim() const { return dim_; }
+  bool cx() const { return cx_; }
+
+ private:
+  int dim_;
+  bool cx_;
+  int ntmp_ = 0;
+  std::set<uint32_t> coefs_;
+  std::map<std::string, std::string> scaled_;
+  std::map<std::pair<int, int>, std::string> pows_;
+  std::ostringstream pre_, body_;
+};
+
+// Greedy multivariate Horner over a real (x) or complex (z) variable vector.
+Val chorner(std::vector<CTerm> terms, CEmitter& em) {
+  const int d = em.dim();
+  if (terms.empty()) return Val{"0.0", true};
+  bool all_const = true;
+  for (auto& t : terms)
+    for (int j = 0; j < d; ++j)
+      if (t.e[j]) all_const = false;
+  if (all_const) {
+    std::string expr = em.coef(terms[0].ci, terms[0].mult);
+    if (terms.size() == 1) return Val{expr, true};
+    for (size_t i = 1; i < terms.size(); ++i) expr += " + " + em.coef(terms[i].ci, terms[i].mult);
+    std::string v = "s" + em.tmp();
+    em.line("const double " + v + " = " + expr + ";");
+    return Val{v, true};
+  }
+  int best = -1, cnt = -1;
+  for (int j = 0; j < d; ++j) {
+    int c = 0;
+    for (auto& t : terms) c += t.e[j] ? 1 : 0;
+    if (c > cnt) {
+      cnt = c;
+      best = j;
+    }
+  }
+  std::vector<CTerm> A, B;
+  int emin = 255;
+  for (auto& t : terms) {
+    if (t.e[best]) {
+      A.push_back(t);
+      emin = std::min<int>(emin, t.e[best]);
+    } else {
+      B.push_back(t);
+    }
+  }
+  for (auto& t : A) t.e[best] = (uint8_t)(t.e[best] - emin);
+  Val va = chorner(A, em);
+  std::string p = em.power(best, emin);
+  std::string v = em.tmp();
+  if (!em.cx()) {
+    if (B.empty()) {
+      em.line("const double " + v + " = " + p + " * " + va.name + ";");
+    } else {
+      Val vb = chorner(B, em);
+      em.line("const double " + v + " = __builtin_fma(" + p + ", " + va.name + ", " + vb.name + ");");
+    }
+    return Val{v, true};
+  }
+  // complex domain: p is cplx; va, vb real (coefficient) or cplx
+  if (B.empty()) {
+    if (va.real)
+      em.line("const cplx " + v + " = cscale(" + va.name + ", " + p + ");");
+    else
+      em.line("const cplx " + v + " = cmul(" + p + ", " + va.name + ");");
+    return Val{v, false};
+  }
+  Val vb = chorner(B, em);
+  std::string cb = vb.real ? "cmk(" + vb.name + ", 0.0)" : vb.name;
+  if (va.real)
+    em.line("const cplx " + v + " = cfmar(" + va.name + ", " + p + ", " + cb + ");");
+  else
+    em.line("const cplx " + v + " = cfma(" + p + ", " + va.name + ", " + cb + ");");
+  return Val{v, false};
+}
+
+std::string generate_complex_fn(const qmcj::Spec& s) {
+  const int d = (int)s.dim;
+  std::vector<CTerm> tu, tf;
+  for (uint32_t i = 0; i < s.n_u + s.n_f; ++i) {
+    CTerm t;
+    t.ci = i;
+    t.mult = 1;
+    t.e.fill(0);
+    for (int j = 0; j < d; ++j) t.e[j] = s.expo[(size_t)i * d + j];
+    (i < s.n_u ? tu : tf).push_back(t);
+  }
+  std::ostringstream o;
+  o << "namespace qmcd {\nstruct JitComplex {\n";
+  // gradient and Hessian of F at real x, per monomial m_i = c_i prod_j x_j^e_ij:
+  //   t_j = m_i e_ij / x_j adds to dF/dx_j; t_j e_il / x_l to d2F/dx_j dx_l (l != j);
+  //   t_j (e_ij - 1) / x_j to d2F/dx_j^2.  Reciprocals are formed once per point;
+  //   x_j = 0 only where the transform weight is 0 and the point is discarded.
+  {
+    std::ostringstream gb;
+    std::set<std::pair<int, int>> erx;  // (j, k): k / x_j
+    std::set<std::pair<int, int>> pw;   // (j, e): x_j^e
+    int nm = 0;
+    // accumulators are updated monomial by monomial so only they stay live
+    for (auto& t : tf) {
+      std::vector<int> nz;
+      for (int j = 0; j < d; ++j)
+        if (t.e[j]) nz.push_back(j);
+      if (nz.empty()) continue;  // constant term: no derivative
+      std::string mname = "m" + std::to_string(nm++);
+      std::string prod = "c" + std::to_string(t.ci);
+      for (int j : nz) {
+        pw.insert({j, (int)t.e[j]});
+        prod += " * xp" + std::to_string(j) + "_" + std::to_string((int)t.e[j]);
+      }
+      gb << "    {\n      const double " << mname << " = " << prod << ";\n";
+      for (size_t q = 0; q < nz.size(); ++q) {
+        int j = nz[q];
+        int ej = t.e[j];
+        erx.insert({j, ej});
+        std::string tj = "t" + std::to_string(j);
+        gb << "      const double " << tj << " = " << mname << " * rx" << j << "_" << ej << ";\n";
+        gb << "      g[" << j << "] += " << tj << ";\n";
+        if (ej >= 2) {
+          erx.insert({j, ej - 1});
+          int k = j * (j + 1) / 2 + j;
+          gb << "      H[" << k << "] = __builtin_fma(" << tj << ", rx" << j << "_" << (ej - 1) << ", H[" << k << "]);\n";
+        }
+      }
+      for (size_t q = 0; q < nz.size(); ++q)
+        for (size_t r = q + 1; r < nz.size(); ++r) {
+          int j = nz[q], l = nz[r];
+          int k = l * (l + 1) / 2 + j;
+          erx.insert({l, (int)t.e[l]});
+          gb << "      H[" << k << "] = __builtin_fma(t" << j << ", rx" << l << "_" << (int)t.e[l] << ", H[" << k
+             << "]);\n";
+        }
+      gb << "    }\n";
+    }
+    o << "  __device__ __forceinline__ void grad_hess(const double (&x)[" << d << "], double (&g)[" << d
+      << "], double (&H)[" << Tri_N(d) << "], const EvalArgs& a) const {\n";
+    std::set<uint32_t> used;
+    for (auto& t : tf) {
+      bool any = false;
+      for (int j = 0; j < d; ++j) any = any || t.e[j];
+      if (any) used.insert(t.ci);
+    }
+    for (uint32_t i : used) o << "    const double c" << i << " = a.coef[" << i << "];\n";
+    std::set<int> rjs;
+    for (auto& p : erx) rjs.insert(p.first);
+    for (int j : rjs) o << "    const double rx" << j << " = fast_rcp(x[" << j << "]);\n";
+    for (auto& p : erx)
+      o << "    const double rx" << p.first << "_" << p.second << " = "
+        << (p.second == 1 ? "rx" + std::to_string(p.first) : std::to_string(p.second) + ".0 * rx" + std::to_string(p.first))
+        << ";\n";
+    std::map<int, int> emax;
+    for (auto& p : pw) emax[p.first] = std::max(emax[p.first], p.second);
+    for (auto& kv : emax) {
+      int j = kv.first;
+      o << "    const double xp" << j << "_1 = x[" << j << "];\n";
+      for (int e = 2; e <= kv.second; ++e)
+        o << "    const double xp" << j << "_" << e << " = xp" << j << "_" << (e / 2) << " * xp" << j << "_"
+          << (e - e / 2) << ";\n";
+    }
+    o << "    for (int j = 0; j < " << d << "; ++j) g[j] = 0.0;\n";
+    o << "    for (int j = 0; j < " << Tri_N(d) << "; ++j) H[j] = 0.0;\n";
+    o << gb.str();
+    o << "  }\n";
+  }
+  for (int which = 0; which < 2; ++which) {
+    CEmitter em(d, true);
+    Val v = chorner(which == 0 ? tu : tf, em);
+    o << "  __device__ __forceinline__ cplx " << (which == 0 ? "U" : "F") << "(const cplx (&z)[" << d
+      << "], const EvalArgs& a) const {\n";
+    o << em.decls() << em.pre() << em.body();
+    o << "    return " << (v.real ? "cmk(" + v.name + ", 0.0)" : v.name) << ";\n  }\n";
+  }
+  o << "  __device__ __forceinline__ cplx uf(const cplx (&z)[" << d
+    << "], const EvalArgs& a, uint32_t& sign) const {\n    return uf_fp64<" << d << ">(*this, z, a, sign);\n  }\n";
+  o << "};\n}  // namespace qmcd\n";
+  return o.str();
+}
+
 struct Module {
   hipModule_t mod = nullptr;
   hipFunction_t f32 = nullptr, f64 = nullptr;
@@ -149,6 +386,21 @@ const char* last_error() { return g_jit_err.c_str(); }
 
 std::string generate(const Spec& s) {
   const int d = (int)s.dim;
+  const char* tk = s.tk == qmcd::TK_KOROBOV3 ? "qmcd::TK_KOROBOV3"
+                   : s.tk == qmcd::TK_KOROBOV ? "qmcd::TK_KOROBOV"
+                   : s.tk == qmcd::TK_BAKER   ? "qmcd::TK_BAKER"
+                                               : "qmcd::TK_NONE";
+  if (s.cplx) {
+    std::ostringstream o;
+    o << "#define QMC_RTC 1\n" << kDeviceSrc << "\n" << generate_complex_fn(s);
+    for (int w = 0; w < 2; ++w) {
+      o << "extern \"C\" __global__ __launch_bounds__(QMCD_BLOCK) void qmc_jit_eval" << (w ? "64" : "32")
+        << "(qmcd::EvalArgs a) {\n  qmcd::eval_complex_body<" << d << ", " << tk << ", " << (w ? "false" : "true")
+        << ", " << s.S << ", true, qmcd::JitComplex, " << (s.vr ? "qmcd::VRM_ON" : "qmcd::VRM_OFF")
+        << ">(a, qmcd::JitComplex());\n}\n";
+    }
+    return o.str();
+  }
   Emitter em(d);
   std::vector<Term> tu, tf;
   for (uint32_t i = 0; i < s.n_u + s.n_f; ++i) {
@@ -170,10 +422,6 @@ std::string generate(const Spec& s) {
   o << "    apply_pow<double>(" << U << ", " << s.pu_mode << ", " << s.pu_k << ", a.pow_u, num, den);\n";
   if (s.n_f) o << "    apply_pow<double>(" << F << ", " << s.pf_mode << ", " << s.pf_k << ", a.pow_f, num, den);\n";
   o << "    return num * fast_rcp(den);\n  }\n};\n}  // namespace qmcd\n";
-  const char* tk = s.tk == qmcd::TK_KOROBOV3 ? "qmcd::TK_KOROBOV3"
-                   : s.tk == qmcd::TK_KOROBOV ? "qmcd::TK_KOROBOV"
-                   : s.tk == qmcd::TK_BAKER   ? "qmcd::TK_BAKER"
-                                               : "qmcd::TK_NONE";
   for (int w = 0; w < 2; ++w) {
     o << "extern \"C\" __global__ __launch_bounds__(QMCD_BLOCK) void qmc_jit_eval" << (w ? "64" : "32")
       << "(qmcd::EvalArgs a) {\n  qmcd::eval_real_body<" << d << ", " << tk << ", " << (w ? "false" : "true")

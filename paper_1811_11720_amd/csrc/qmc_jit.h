@@ -18,6 +18,7 @@ struct Spec {
   int tk;  // qmcd::TK_*
   int S;   // shifts per thread group
   int vr;  // variance-reduction map compiled in (1) or out (0)
+  int cplx = 0;  // deformed (complex) integrand
 };
 
 struct Kernel {

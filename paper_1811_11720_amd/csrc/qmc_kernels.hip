@@ -30,12 +30,24 @@ using EvalFn = void (*)(qmcd::EvalArgs);
 static EvalFn g_real[4][4][2] = {QMC_ROW(4), QMC_ROW(8), QMC_ROW(12), QMC_ROW(16)};
 #undef QMC_ROW
 
-int occupancy_eval_real(int dclass, int tsel, bool idx32) {
+// complex kernels: one table per dimension class, defined in qmc_kernels_c{4,8,12}.hip
+using EvalTable = EvalFn[4][2];
+extern EvalTable g_complex4, g_complex8, g_complex12;
+static EvalTable* const g_complex[3] = {&g_complex4, &g_complex8, &g_complex12};
+
+int occupancy_eval(bool cplx, int dclass, int tsel, bool idx32) {
   int occ = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)g_real[dclass][tsel][idx32 ? 1 : 0],
-                                                   QMCD_BLOCK, 0) != hipSuccess)
-    return 0;
+  EvalFn fn = cplx ? (*g_complex[dclass])[tsel][idx32 ? 1 : 0] : g_real[dclass][tsel][idx32 ? 1 : 0];
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)fn, QMCD_BLOCK, 0) != hipSuccess) return 0;
   return occ;
+}
+
+hipError_t launch_eval_complex(const qmcd::EvalArgs& a, int dclass, int tsel, bool idx32, dim3 grid,
+                               hipStream_t st) {
+  EvalFn fn = (*g_complex[dclass])[tsel][idx32 ? 1 : 0];
+  qmcd::EvalArgs copy = a;
+  void* args[] = {&copy};
+  return hipLaunchKernel((const void*)fn, grid, dim3(QMCD_BLOCK), args, 0, st);
 }
 
 hipError_t launch_eval_real(const qmcd::EvalArgs& a, int dclass, int tsel, bool idx32, dim3 grid,
@@ -67,6 +79,72 @@ hipError_t launch_finalize(const double* partial, uint32_t nblocks, uint32_t row
   if (rows == 0) return hipSuccess;
   void* args[] = {(void*)&partial, (void*)&nblocks, (void*)&out};
   return hipLaunchKernel((const void*)k_finalize, dim3(rows), dim3(QMCD_BLOCK), args, 0, st);
+}
+
+__global__ void k_fill_u64(unsigned long long* p, uint32_t count, unsigned long long v) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = v;
+}
+
+hipError_t launch_fill_u64(unsigned long long* p, uint32_t count, unsigned long long v, hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  void* args[] = {(void*)&p, (void*)&count, (void*)&v};
+  return hipLaunchKernel((const void*)k_fill_u64, dim3((count + 255) / 256), dim3(256), args, 0, st);
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t count, uint32_t v) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t count, uint32_t v, hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  void* args[] = {(void*)&p, (void*)&count, (void*)&v};
+  return hipLaunchKernel((const void*)k_fill_u32, dim3((count + 255) / 256), dim3(256), args, 0, st);
+}
+
+__global__ __launch_bounds__(QMCD_BLOCK) void k_finalize_rows(const RowRef* __restrict__ rows,
+                                                              double* __restrict__ out) {
+  const RowRef r = rows[blockIdx.x];
+  double t = 0.0;
+  for (uint32_t i = threadIdx.x; i < r.ncols; i += QMCD_BLOCK) t += r.p[i];
+  t = qmcd::wave_sum(t);
+  __shared__ double red[QMCD_BLOCK / 64];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < QMCD_BLOCK / 64; ++w) s += red[w];
+    out[blockIdx.x] = s;
+  }
+}
+
+hipError_t launch_finalize_rows(const RowRef* rows, uint32_t nrows, double* out, hipStream_t st) {
+  if (nrows == 0) return hipSuccess;
+  void* args[] = {(void*)&rows, (void*)&out};
+  return hipLaunchKernel((const void*)k_finalize_rows, dim3(nrows), dim3(QMCD_BLOCK), args, 0, st);
+}
+
+extern BatchFn g_batch4[2][2], g_batch8[2][2], g_batch12[2][2], g_batch16[2][2];
+
+BatchFn batch_kernel(int dclass, bool cplx, bool fp32) {
+  BatchFn(*t)[2] = dclass == 0 ? g_batch4 : dclass == 1 ? g_batch8 : dclass == 2 ? g_batch12 : g_batch16;
+  return t[cplx ? 1 : 0][fp32 ? 1 : 0];
+}
+
+int occupancy_batch(int dclass, bool cplx, bool fp32) {
+  BatchFn fn = batch_kernel(dclass, cplx, fp32);
+  int occ = 0;
+  if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)fn, QMCD_BLOCK, 0) != hipSuccess) return 0;
+  return occ;
+}
+
+hipError_t launch_batch(int dclass, bool cplx, bool fp32, const qmcd::EvalArgs* items, const uint32_t* order,
+                        const uint32_t* prefix, uint32_t nitems, uint32_t* counter, uint32_t blocks, hipStream_t st) {
+  BatchFn fn = batch_kernel(dclass, cplx, fp32);
+  if (!fn) return hipErrorInvalidValue;
+  void* args[] = {(void*)&items, (void*)&order, (void*)&prefix, (void*)&nitems, (void*)&counter};
+  return hipLaunchKernel((const void*)fn, dim3(blocks), dim3(QMCD_BLOCK), args, 0, st);
 }
 
 struct IndexArgs {

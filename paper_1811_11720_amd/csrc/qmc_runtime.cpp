@@ -21,10 +21,14 @@
 #include <vector>
 
 #include "qmc.h"
-#include "qmc_internal.h"
-#include "qmc_jit.h"
+#include "qmc_host.h"
 
-namespace {
+namespace qmcv {
+bool fit_dimension(const double* hist, uint32_t bins, double* a);
+void identity_params(double* a);
+}  // namespace qmcv
+
+namespace qmch {
 
 thread_local std::string g_err;
 
@@ -38,11 +42,7 @@ int fail(int code, const char* fmt, ...) {
   return code;
 }
 
-#define HIPCHK(call)                                                                              \
-  do {                                                                                            \
-    hipError_t e_ = (call);                                                                       \
-    if (e_ != hipSuccess) return fail(QMC_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
-  } while (0)
+
 
 uint64_t splitmix64_next(uint64_t& s) {
   uint64_t z = (s += 0x9e3779b97f4a7c15ULL);
@@ -72,52 +72,6 @@ double binom(int a, int b) {
   for (int i = 1; i <= b; ++i) c = c * (double)(a - b + i) / (double)i;
   return c;
 }
-
-}  // namespace
-
-struct qmc_context {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  // scratch: caller workspace or library-owned
-  char* ws = nullptr;
-  size_t ws_bytes = 0;
-  bool own_ws = false;
-  // pinned host staging
-  double* h_stage = nullptr;
-  size_t h_stage_bytes = 0;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  std::map<uint64_t, std::vector<uint64_t>> lattices;
-  std::recursive_mutex mu;
-  int inflight = 0;
-  bool broken = false;
-  int max_blocks = 0;          // 0: from occupancy
-  int cus = 256;               // compute units of the device
-  int grid_rounds = 1;         // resident-block rounds per launch
-  bool jit = true;             // specialise kernels to the integrand
-  uint64_t jit_min_evals = 1ull << 24;
-  int jit_S = 8;
-};
-
-struct qmc_integrand {
-  qmc_context* ctx = nullptr;
-  uint32_t dim = 0, n_u = 0, n_f = 0, flags = 0;
-  double pow_u = 1, pow_f = 1, prefactor = 1, lambda = 0;
-  int pu_mode = 0, pu_k = 0, pf_mode = 0, pf_k = 0;
-  std::vector<double> coef;
-  std::vector<uint8_t> expo;
-  bool has_vr = false;
-  std::vector<double> vr;
-  char* dmem = nullptr;  // coef | expo (u32 x 2 per monomial) | vr
-  double* d_coef = nullptr;
-  uint32_t* d_expo = nullptr;
-  double* d_vr = nullptr;
-  int refs = 0;
-  std::map<int, qmcj::Kernel> jit;  // per (transform kind, VR on) key
-  std::map<int, int> jit_failed;
-};
-
-namespace {
 
 void classify_power(double p, int& mode, int& k) {
   if (p == 0.0) {
@@ -206,6 +160,7 @@ struct LatticeRun {
   std::vector<double> sums;  // rows (m or 2m)
   double kernel_seconds = 0;
   uint32_t path = 0;
+  uint64_t sign_points = 0;  // complex: points with Im F(z) > 0
 };
 
 // blocks over points for one shift group, from the kernel's occupancy
@@ -225,14 +180,14 @@ uint32_t plan_blocks(const qmc_context* c, int occ, uint32_t groups, uint64_t np
 // One lattice (n, z), m shifts from `shift_tab`, points [k0, k1): per-shift sums.
 int run_lattice(qmc_context* c, qmc_integrand* f, uint64_t n, const uint64_t* z, uint32_t m,
                 const double* shift_tab, const qmc_transform& t, uint64_t k0, uint64_t k1, LatticeRun& out) {
-  if (f->flags & QMC_DEFORM) return fail(QMC_EUNSUPPORTED, "complex (deformed) integrands are not enabled");
+  const bool cplx = (f->flags & QMC_DEFORM) != 0;
   qmcd::EvalArgs a;
   std::memset(&a, 0, sizeof a);
   int tsel = 0;
   int rc = set_transform(a, t, tsel);
   if (rc) return rc;
   const uint32_t dim = f->dim;
-  const uint32_t rows = m;
+  const uint32_t rows = cplx ? 2 * m : m;
   const uint64_t npts = k1 - k0;
   const bool idx32 = n <= (1ull << 31);
   const int dclass = qmck::dim_class(dim);
@@ -240,13 +195,13 @@ int run_lattice(qmc_context* c, qmc_integrand* f, uint64_t n, const uint64_t* z,
   // specialised kernel for large jobs (compiled once per integrand structure)
   qmcj::Kernel jk;
   bool use_jit = false;
-  int S = qmck::S_REAL;
+  int S = cplx ? qmck::S_COMPLEX : qmck::S_REAL;
   const int jkey = tsel * 2 + (f->has_vr ? 1 : 0);
   if (c->jit && npts * (uint64_t)m >= c->jit_min_evals && !f->jit_failed.count(jkey)) {
     auto it = f->jit.find(jkey);
     if (it == f->jit.end()) {
-      qmcj::Spec sp{dim, f->n_u, f->n_f, f->expo.data(), f->pu_mode, f->pu_k, f->pf_mode, f->pf_k, tsel, c->jit_S,
-                    f->has_vr ? 1 : 0};
+      qmcj::Spec sp{dim, f->n_u, f->n_f, f->expo.data(), f->pu_mode, f->pu_k, f->pf_mode, f->pf_k, tsel,
+                    cplx ? qmck::S_COMPLEX_JIT : c->jit_S, f->has_vr ? 1 : 0, cplx ? 1 : 0};
       if (qmcj::get(c->device, sp, &jk) == 0) {
         f->jit[jkey] = jk;
         use_jit = true;
@@ -258,15 +213,15 @@ int run_lattice(qmc_context* c, qmc_integrand* f, uint64_t n, const uint64_t* z,
       jk = it->second;
       use_jit = true;
     }
-    if (use_jit) S = c->jit_S;
+    if (use_jit) S = cplx ? qmck::S_COMPLEX_JIT : c->jit_S;
   }
   const uint32_t groups = (m + S - 1) / S;
-  const int occ = use_jit ? jk.occ_blocks : qmck::occupancy_eval_real(dclass, tsel, idx32);
+  const int occ = use_jit ? jk.occ_blocks : qmck::occupancy_eval(cplx, dclass, tsel, idx32);
   const uint32_t nb = plan_blocks(c, occ, groups, npts);
 
   size_t off_sh = 0, sz_sh = (size_t)m * dim * sizeof(double);
   size_t off_part = (sz_sh + 255) & ~(size_t)255, sz_part = (size_t)rows * nb * sizeof(double);
-  size_t off_out = (off_part + sz_part + 255) & ~(size_t)255, sz_out = rows * sizeof(double);
+  size_t off_out = (off_part + sz_part + 255) & ~(size_t)255, sz_out = (rows + 1) * sizeof(double);
   char* ws = nullptr;
   rc = scratch(c, off_out + sz_out, &ws);
   if (rc) return rc;
@@ -304,9 +259,14 @@ int run_lattice(qmc_context* c, qmc_integrand* f, uint64_t n, const uint64_t* z,
   a.lambda = f->lambda;
   a.vr = f->has_vr ? f->d_vr : nullptr;
   a.wscale = std::pow(140.0, (double)dim);
+  // the sign counter sits right after the per-shift sums
+  a.sign_count = (unsigned long long*)(ws + off_out + rows * sizeof(double));
+  HIPCHK(qmck::launch_fill_u64(a.sign_count, 1, 0ull, c->stream));
   HIPCHK(hipEventRecord(c->ev0, c->stream));
   if (use_jit) {
     HIPCHK(qmcj::launch(jk, idx32, a, dim3(nb, groups), c->stream));
+  } else if (cplx) {
+    HIPCHK(qmck::launch_eval_complex(a, dclass, tsel, idx32, dim3(nb, groups), c->stream));
   } else {
     HIPCHK(qmck::launch_eval_real(a, dclass, tsel, idx32, dim3(nb, groups), c->stream));
   }
@@ -318,7 +278,78 @@ int run_lattice(qmc_context* c, qmc_integrand* f, uint64_t n, const uint64_t* z,
   HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
   out.kernel_seconds = ms * 1e-3;
   out.sums.assign(c->h_stage, c->h_stage + rows);
+  uint64_t sp;
+  std::memcpy(&sp, c->h_stage + rows, sizeof sp);
+  out.sign_points = sp;
   out.path = use_jit ? 1u : 0u;
+  return QMC_OK;
+}
+
+// Histograms of |f| over the lattice (n, z) shifted by the first shift of
+// SplitMix64(seed), raw points (Sec. 2.4): two passes (max, then integer sums).
+int run_histogram(qmc_context* c, const qmc_integrand* f, uint64_t n, const uint64_t* z, uint64_t seed,
+                  uint32_t bins, std::vector<double>& hist) {
+  const bool cplx = (f->flags & QMC_DEFORM) != 0;
+  const uint32_t dim = f->dim;
+  qmcd::EvalArgs a;
+  std::memset(&a, 0, sizeof a);
+  const uint32_t nb = (uint32_t)std::min<uint64_t>((n + QMCD_BLOCK - 1) / QMCD_BLOCK, 2048);
+  std::vector<double> shift(dim);
+  make_shifts(seed, 1, dim, shift.data());
+  size_t off_sh = 0, sz_sh = dim * sizeof(double);
+  size_t off_part = 256, sz_part = (size_t)nb * sizeof(double);
+  size_t off_h = (off_part + sz_part + 255) & ~(size_t)255, sz_h = (size_t)dim * bins * 8;
+  char* ws = nullptr;
+  int rc = scratch(c, off_h + sz_h, &ws);
+  if (rc) return rc;
+  rc = stage(c, std::max(std::max(sz_part, sz_h), sz_sh));
+  if (rc) return rc;
+  std::memcpy(c->h_stage, shift.data(), sz_sh);
+  HIPCHK(hipMemcpyAsync(ws + off_sh, c->h_stage, sz_sh, hipMemcpyHostToDevice, c->stream));
+  a.n = n;
+  a.n_d = (double)n;
+  a.inv_n = 1.0 / (double)n;
+  a.k_begin = 0;
+  a.k_end = n;
+  a.stride = (uint64_t)nb * QMCD_BLOCK;
+  for (uint32_t j = 0; j < dim; ++j) a.z[j] = z[j] % n;
+  a.dim = dim;
+  a.m = 1;
+  a.shifts = (const double*)(ws + off_sh);
+  a.partial = (double*)(ws + off_part);
+  a.nblocks = nb;
+  a.coef = f->d_coef;
+  a.expo = f->d_expo;
+  a.n_u = f->n_u;
+  a.n_f = f->n_f;
+  a.pu_mode = f->pu_mode;
+  a.pu_k = f->pu_k;
+  a.pf_mode = f->pf_mode;
+  a.pf_k = f->pf_k;
+  a.pow_u = f->pow_u;
+  a.pow_f = f->pow_f;
+  a.prefactor = f->prefactor;
+  a.lambda = f->lambda;
+  qmcd::HistArgs h;
+  h.hist = (unsigned long long*)(ws + off_h);
+  h.bins = bins;
+  h.scale = 0.0;
+  const int dclass = qmck::dim_class(dim);
+  HIPCHK(qmck::launch_hist(a, h, dclass, cplx, 0, dim3(nb), c->stream));
+  HIPCHK(hipMemcpyAsync(c->h_stage, ws + off_part, sz_part, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  double mx = 0.0;
+  for (uint32_t b = 0; b < nb; ++b) mx = std::max(mx, c->h_stage[b]);
+  hist.assign((size_t)dim * bins, 0.0);
+  if (!(mx > 0.0)) return QMC_OK;
+  h.scale = std::ldexp(1.0, 40) / mx;
+  HIPCHK(qmck::launch_fill_u64(h.hist, dim * bins, 0ull, c->stream));
+  HIPCHK(qmck::launch_hist(a, h, dclass, cplx, 1, dim3(nb), c->stream));
+  HIPCHK(hipMemcpyAsync(c->h_stage, ws + off_h, sz_h, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  const unsigned long long* cnt = (const unsigned long long*)c->h_stage;
+  const double unit = mx * std::ldexp(1.0, -40);
+  for (size_t i = 0; i < (size_t)dim * bins; ++i) hist[i] = (double)cnt[i] * unit;
   return QMC_OK;
 }
 
@@ -406,7 +437,8 @@ int integrate_request(qmc_context* c, const qmc_request& q, qmc_result* out, dou
       for (uint32_t s = 0; s < m; ++s) qs[s] = run.sums[m + s] / (double)n;
       estimate(qs.data(), m, r.im, r.err_im);
     }
-    r.flags &= ~(uint32_t)QMC_NONFINITE;
+    r.flags &= ~(uint32_t)(QMC_NONFINITE | QMC_DEFORM_SIGN);
+    if (run.sign_points) r.flags |= QMC_DEFORM_SIGN;
     bool finite = std::isfinite(r.re) && std::isfinite(r.im);
     if (!finite) r.flags |= QMC_NONFINITE;
     if (!grow) break;
@@ -450,11 +482,43 @@ int validate_desc(const qmc_integrand_desc* d) {
   if (!std::isfinite(d->pow_u) || !std::isfinite(d->pow_f) || !std::isfinite(d->prefactor))
     return fail(QMC_EINVAL, "powers and prefactor must be finite");
   if ((d->flags & QMC_DEFORM) && !std::isfinite(d->lambda)) return fail(QMC_EINVAL, "lambda must be finite");
+  if ((d->flags & QMC_DEFORM) && d->dim > qmck::MAX_DIM_COMPLEX)
+    return fail(QMC_EINVAL, "deformed integrands support at most %u variables", qmck::MAX_DIM_COMPLEX);
+  if ((d->flags & QMC_DEFORM) && d->n_f == 0) return fail(QMC_EINVAL, "deformation needs a polynomial F");
   if (d->flags & ~(uint32_t)(QMC_DEFORM | QMC_EVAL_FP32)) return fail(QMC_EINVAL, "unknown flags 0x%x", d->flags);
   return QMC_OK;
 }
 
-}  // namespace
+// integrand + transform part of the per-launch arguments
+int fill_integrand_args(qmcd::EvalArgs& a, const qmc_integrand* f, const qmc_transform& t, int& tsel) {
+  int rc = set_transform(a, t, tsel);
+  if (rc) return rc;
+  a.tk = tsel == qmck::TSEL_KOROBOV3 ? qmcd::TK_KOROBOV3
+         : tsel == qmck::TSEL_KOROBOV ? qmcd::TK_KOROBOV
+         : tsel == qmck::TSEL_BAKER   ? qmcd::TK_BAKER
+                                       : qmcd::TK_NONE;
+  a.dim = f->dim;
+  a.coef = f->d_coef;
+  a.coef32 = f->d_coef32;
+  a.expo = f->d_expo;
+  a.n_u = f->n_u;
+  a.n_f = f->n_f;
+  a.pu_mode = f->pu_mode;
+  a.pu_k = f->pu_k;
+  a.pf_mode = f->pf_mode;
+  a.pf_k = f->pf_k;
+  a.pow_u = f->pow_u;
+  a.pow_f = f->pow_f;
+  a.prefactor = f->prefactor;
+  a.lambda = f->lambda;
+  a.vr = f->has_vr ? f->d_vr : nullptr;
+  a.wscale = std::pow(140.0, (double)f->dim);
+  return QMC_OK;
+}
+
+}  // namespace qmch
+
+using namespace qmch;
 
 extern "C" {
 
@@ -500,6 +564,10 @@ int qmc_context_create(int device, void* hip_stream, void* workspace, size_t wor
     int sv = atoi(v);
     if (sv == 4 || sv == 8 || sv == 16 || sv == 32) c->jit_S = sv;
   }
+  if (const char* v = std::getenv("QMC_BATCH_GRAPH")) c->batch_graph = atoi(v) != 0;
+  if (const char* v = std::getenv("QMC_BATCH_TILE")) c->batch_tile_real = std::max(256ull, strtoull(v, nullptr, 10));
+  if (const char* v = std::getenv("QMC_BATCH_TILE_COMPLEX"))
+    c->batch_tile_complex = std::max(256ull, strtoull(v, nullptr, 10));
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
     c->cus = cus;
@@ -507,12 +575,8 @@ int qmc_context_create(int device, void* hip_stream, void* workspace, size_t wor
   return QMC_OK;
 }
 
-int qmc_context_destroy(qmc_context* c) {
-  if (!c) return QMC_OK;
-  {
-    std::lock_guard<std::recursive_mutex> g(c->mu);
-    if (c->inflight) return fail(QMC_EBUSY, "context has %d requests in flight", c->inflight);
-  }
+namespace qmch {
+void free_context(qmc_context* c) {
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   if (c->own_ws && c->ws) (void)hipFree(c->ws);
@@ -520,7 +584,23 @@ int qmc_context_destroy(qmc_context* c) {
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
+}
+}  // namespace qmch
+
+int qmc_context_destroy(qmc_context* c) {
+  if (!c) return QMC_OK;
+  {
+    std::lock_guard<std::recursive_mutex> g(c->mu);
+    if (c->inflight) return fail(QMC_EBUSY, "context has %d requests in flight", c->inflight);
+    if (c->live_integrands > 0) {
+      // integrands still reference the context: free it with the last of them
+      c->closing = true;
+      return QMC_OK;
+    }
+  }
+  free_context(c);
   return QMC_OK;
 }
 
@@ -569,9 +649,10 @@ int qmc_create_integrand(qmc_context* c, const qmc_integrand_desc* d, qmc_integr
   size_t b_coef = ((size_t)nm * 8 + 255) & ~(size_t)255;
   size_t b_expo = ((size_t)nm * 8 + 255) & ~(size_t)255;
   size_t b_vr = ((size_t)d->dim * 6 * 8 + 255) & ~(size_t)255;
+  size_t b_c32 = ((size_t)nm * 4 + 255) & ~(size_t)255;
   std::lock_guard<std::recursive_mutex> g(c->mu);
   (void)hipSetDevice(c->device);
-  hipError_t e = hipMalloc((void**)&f->dmem, b_coef + b_expo + b_vr);
+  hipError_t e = hipMalloc((void**)&f->dmem, b_coef + b_expo + b_vr + b_c32);
   if (e != hipSuccess) {
     delete f;
     return fail(QMC_ENOMEM, "hipMalloc for the descriptor failed: %s", hipGetErrorString(e));
@@ -579,13 +660,17 @@ int qmc_create_integrand(qmc_context* c, const qmc_integrand_desc* d, qmc_integr
   f->d_coef = (double*)f->dmem;
   f->d_expo = (uint32_t*)(f->dmem + b_coef);
   f->d_vr = (double*)(f->dmem + b_coef + b_expo);
+  f->d_coef32 = (float*)(f->dmem + b_coef + b_expo + b_vr);
+  std::vector<float> c32(f->coef.begin(), f->coef.end());
   e = hipMemcpy(f->d_coef, f->coef.data(), nm * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(f->d_coef32, c32.data(), nm * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(f->d_expo, packed.data(), (size_t)nm * 8, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     (void)hipFree(f->dmem);
     delete f;
     return fail(QMC_EDEVICE, "descriptor upload failed: %s", hipGetErrorString(e));
   }
+  c->live_integrands += 1;
   *out = f;
   return QMC_OK;
 }
@@ -593,11 +678,18 @@ int qmc_create_integrand(qmc_context* c, const qmc_integrand_desc* d, qmc_integr
 int qmc_destroy_integrand(qmc_integrand* f) {
   if (!f) return QMC_OK;
   if (f->refs) return fail(QMC_EBUSY, "integrand referenced by %d pending requests", f->refs);
-  std::lock_guard<std::recursive_mutex> g(f->ctx->mu);
-  (void)hipSetDevice(f->ctx->device);
-  (void)hipStreamSynchronize(f->ctx->stream);
-  if (f->dmem) (void)hipFree(f->dmem);
-  delete f;
+  qmc_context* c = f->ctx;
+  bool last = false;
+  {
+    std::lock_guard<std::recursive_mutex> g(c->mu);
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    if (f->dmem) (void)hipFree(f->dmem);
+    delete f;
+    c->live_integrands -= 1;
+    last = c->closing && c->live_integrands == 0;
+  }
+  if (last) free_context(c);
   return QMC_OK;
 }
 
@@ -640,9 +732,11 @@ int qmc_integrate(qmc_context* c, const qmc_integrand* f, uint32_t dim, uint64_t
   q.errormode = QMC_ERRMODE_LARGEST;
   q.max_evals = 0;
   std::lock_guard<std::recursive_mutex> g(c->mu);
+  if (c->closing) return fail(QMC_EINVAL, "context has been destroyed");
   if (c->broken) return fail(QMC_EDEVICE, "context is unusable after a device error");
   HIPCHK(hipSetDevice(c->device));
-  int rc = integrate_request(c, q, out, shift_sums);
+  // fp32 evaluation exists only in the batch kernels
+  int rc = (f->flags & QMC_EVAL_FP32) ? run_requests(c, &q, 1, out, shift_sums) : integrate_request(c, q, out, shift_sums);
   if (rc == QMC_EDEVICE) c->broken = true;
   return rc;
 }
@@ -653,16 +747,9 @@ int qmc_integrate_batch(qmc_context* c, const qmc_request* reqs, uint32_t count,
   std::lock_guard<std::recursive_mutex> g(c->mu);
   if (c->broken) return fail(QMC_EDEVICE, "context is unusable after a device error");
   HIPCHK(hipSetDevice(c->device));
-  size_t off = 0;
-  for (uint32_t i = 0; i < count; ++i) {
-    int rc = integrate_request(c, reqs[i], out ? out + i : nullptr, shift_sums ? shift_sums + off : nullptr);
-    if (rc) {
-      if (rc == QMC_EDEVICE) c->broken = true;
-      return rc;
-    }
-    off += (size_t)reqs[i].m * ((reqs[i].f->flags & QMC_DEFORM) ? 2 : 1);
-  }
-  return QMC_OK;
+  int rc = run_requests(c, reqs, count, out, shift_sums);
+  if (rc == QMC_EDEVICE) c->broken = true;
+  return rc;
 }
 
 int qmc_shifts(uint64_t seed, uint32_t m, uint32_t dim, double* out) {
@@ -737,9 +824,53 @@ int qmc_specialize_check(const qmc_integrand_desc* d, qmc_transform t, size_t* c
   classify_power(d->n_f ? d->pow_f : 0.0, pf_mode, pf_k);
   int S = 8;
   if (const char* v = std::getenv("QMC_JIT_S")) S = atoi(v);
-  qmcj::Spec sp{d->dim, d->n_u, d->n_f, d->expo, pu_mode, pu_k, pf_mode, pf_k, tsel, S, 0};
+  const int cx = (d->flags & QMC_DEFORM) ? 1 : 0;
+  qmcj::Spec sp{d->dim, d->n_u, d->n_f, d->expo, pu_mode, pu_k, pf_mode, pf_k, tsel, cx ? qmck::S_COMPLEX_JIT : S, 0, cx};
   if (qmcj::compile_only(sp, code_bytes) != 0) return fail(QMC_EINVAL, "%s", qmcj::last_error());
   return QMC_OK;
+}
+
+int qmc_histogram(qmc_context* c, const qmc_integrand* f, uint64_t n, const uint64_t* z, uint64_t seed,
+                  uint32_t bins, double* hist) {
+  if (!c || !f || !hist) return fail(QMC_EINVAL, "NULL argument");
+  if (bins < 2 || bins > 65536) return fail(QMC_EINVAL, "bins=%u outside [2, 65536]", bins);
+  if (n >= (1ull << 53)) return fail(QMC_EINVAL, "n too large");
+  int rc = check_lattice(n, f->dim, z);
+  if (rc) return rc;
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  if (c->broken) return fail(QMC_EDEVICE, "context is unusable after a device error");
+  HIPCHK(hipSetDevice(c->device));
+  std::vector<double> h;
+  rc = run_histogram(c, f, n, z, seed, bins, h);
+  if (rc) return rc;
+  std::memcpy(hist, h.data(), h.size() * sizeof(double));
+  return QMC_OK;
+}
+
+int qmc_fit_vr_from_histogram(uint32_t dim, uint32_t bins, const double* hist, double* params,
+                              uint32_t* fallback_mask) {
+  if (!hist || !params) return fail(QMC_EINVAL, "NULL argument");
+  if (dim < 1 || dim > QMC_MAX_DIM || bins < 2) return fail(QMC_EINVAL, "dim=%u bins=%u", dim, bins);
+  uint32_t mask = 0;
+  for (uint32_t j = 0; j < dim; ++j)
+    if (!qmcv::fit_dimension(hist + (size_t)j * bins, bins, params + 6 * j)) mask |= 1u << j;
+  if (fallback_mask) *fallback_mask = mask;
+  return QMC_OK;
+}
+
+int qmc_fit_vr(qmc_context* c, qmc_integrand* f, uint64_t n, const uint64_t* z, uint64_t seed, uint32_t bins,
+               double* params, uint32_t* fallback_mask) {
+  if (!c || !f) return fail(QMC_EINVAL, "NULL argument");
+  std::vector<double> h((size_t)f->dim * bins);
+  int rc = qmc_histogram(c, f, n, z, seed, bins, h.data());
+  if (rc) return rc;
+  std::vector<double> p(6 * f->dim);
+  uint32_t mask = 0;
+  rc = qmc_fit_vr_from_histogram(f->dim, bins, h.data(), p.data(), &mask);
+  if (rc) return rc;
+  if (params) std::memcpy(params, p.data(), p.size() * sizeof(double));
+  if (fallback_mask) *fallback_mask = mask;
+  return qmc_set_vr(f, p.data());
 }
 
 }  // extern "C"

@@ -1,0 +1,145 @@
+"""Batched persistent launches: parity with the oracle, invariance, fp32 evaluation."""
+
+import copy
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from paper_1811_11720_amd import cbc
+from test_parity_gpu import THREADS, TOL, _check_sums, make_ctx
+
+pytestmark = pytest.mark.gpu
+
+KOR3 = (W.T_KOROBOV, 3, 3)
+
+
+def _ctx(graph=True):
+    old = os.environ.get("QMC_BATCH_GRAPH")
+    os.environ["QMC_BATCH_GRAPH"] = "1" if graph else "0"
+    try:
+        return make_ctx("generic")
+    finally:
+        if old is None:
+            os.environ.pop("QMC_BATCH_GRAPH", None)
+        else:
+            os.environ["QMC_BATCH_GRAPH"] = old
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = _ctx(True)
+    yield c
+    c.close()
+
+
+def _mix(count, seed, n_choices=(1009, 4099, 10007), fp32=False):
+    rng = np.random.default_rng(seed)
+    jobs = []
+    for i in range(count):
+        dim = int(rng.integers(1, 13))
+        cplx = bool(rng.integers(0, 2))
+        n_f = int(rng.integers(2, 9))
+        desc = W.sector(int(rng.integers(0, 2 ** 31)), dim, max(1, n_f // 2), n_f,
+                        float(rng.choice([-1.0, -2.0])), float(rng.choice([-1.0, -1.5, -2.0])),
+                        complex_=cplx, lam=0.5, neg_frac=0.3)
+        desc.fp32 = fp32
+        n = int(rng.choice(n_choices))
+        tr = [KOR3, (W.T_BAKER, 0, 0), (W.T_KOROBOV, 2, 2), (W.T_NONE, 0, 0)][int(rng.integers(0, 4))]
+        m = int(rng.integers(1, 20))
+        jobs.append(W.Job(desc, n, cbc.fast_cbc(n, dim), m, seed=7000 + i, transform=tr))
+    return jobs
+
+
+def _run(ctx, jobs, keep=None):
+    fs = [ctx.integrand(j.desc) for j in jobs]
+    if keep is not None:
+        keep.extend(fs)
+    reqs = [dict(f=f, n=j.n, z=j.z, m=j.m, seed=j.seed, transform=j.transform) for f, j in zip(fs, jobs)]
+    return ctx.integrate_batch(reqs, sums=True)
+
+
+def test_mixed_batch_matches_oracle(ctx):
+    jobs = _mix(24, 1)
+    res = _run(ctx, jobs)
+    for j, r in zip(jobs, res):
+        assert r["path"] == 2 and r["n"] == j.n and r["iterations"] == 1
+        sh = oracle.shifts(j.seed, j.m, j.desc.dim)
+        o = oracle.shift_sums(j.desc, j.n, j.z, j.m, sh, j.transform, threads=THREADS)
+        _check_sums(r["sums_re"], o, r["sums_im"] if j.desc.deform else None, label=f"d{j.desc.dim}")
+
+
+def test_alone_equals_in_the_mix_bitwise(ctx):
+    jobs = _mix(16, 2)
+    mixed = _run(ctx, jobs)
+    for k in (0, 5, 11):
+        alone = _run(ctx, [jobs[k]])[0]
+        assert np.array_equal(alone["sums_re"], mixed[k]["sums_re"])
+        assert np.array_equal(alone["sums_im"], mixed[k]["sums_im"])
+    # another mix containing the same request
+    other = _mix(9, 3) + [jobs[5]]
+    again = _run(ctx, other)[-1]
+    assert np.array_equal(again["sums_re"], mixed[5]["sums_re"])
+
+
+def test_graph_replays_equal_eager(ctx):
+    jobs = _mix(10, 4)
+    eager_ctx = _ctx(False)
+    eager = _run(eager_ctx, jobs)
+    eager_ctx.close()
+    for _ in range(3):  # each round captures and replays a graph
+        g = _run(ctx, jobs)
+        for a, b in zip(eager, g):
+            assert np.array_equal(a["sums_re"], b["sums_re"]) and np.array_equal(a["sums_im"], b["sums_im"])
+
+
+def test_fp32_evaluation_error_is_small_and_reported(ctx):
+    jobs = _mix(12, 5, n_choices=(10007,), fp32=True)
+    res = _run(ctx, jobs)
+    for j, r in zip(jobs, res):
+        sh = oracle.shifts(j.seed, j.m, j.desc.dim)
+        o = oracle.shift_sums(j.desc, j.n, j.z, j.m, sh, j.transform, threads=THREADS)
+        # fp32 polynomials and powers: a few 1e-7 relative per evaluation
+        assert np.all(np.abs(r["sums_re"] - o.re) <= 2e-5 * o.abs_re + 1e-300)
+        if j.desc.deform:
+            assert np.all(np.abs(r["sums_im"] - o.im) <= 2e-5 * o.abs_im + 1e-300)
+
+
+def test_batched_growth_matches_oracle(ctx):
+    table_ns = [cbc.next_prime(v) for v in (1000, 2000, 4000, 8000, 16000, 32000, 64000, 128000)]
+    zs = {n: cbc.fast_cbc(n, 3) for n in table_ns}
+    ctx2 = _ctx(True)
+    ctx2.register_table(zs)
+    descs = [W.product_of_linear([1.0, 1.0, 1.0], [0.8, 0.5, 0.3], -1.5),
+             W.product_of_linear([1.0, 1.0, 1.0], [0.2, 0.9, 0.4], -1.0)]
+    fs = [ctx2.integrand(d) for d in descs]
+    BAKER = (W.T_BAKER, 0, 0)
+    reqs = [dict(f=f, n=table_ns[0], z=zs[table_ns[0]], m=16, seed=77 + i, transform=BAKER, rel_tol=1e-8)
+            for i, f in enumerate(fs)]
+    res = ctx2.integrate_batch(reqs, sums=True)
+    for i, (d, r) in enumerate(zip(descs, res)):
+        o = oracle.integrate(d, table_ns[0], zs.__getitem__, 16, 77 + i, BAKER, rel_tol=1e-8, table_ns=table_ns,
+                             threads=THREADS)
+        assert r["n"] == o["n"] and r["iterations"] == o["iterations"] and bool(r["flags"] & 1) == o["converged"]
+        assert np.all(np.abs(r["sums_re"] - o["sums_re"]) <= TOL * o["abs_re"])
+    for f in fs:
+        f.close()
+    ctx2.close()
+
+
+def test_batch_of_sector_mix_workload(ctx):
+    """Integrands from the batch-mix generator (dims 2..10, 4..40 monomials,
+    half complex) on a small lattice, against the oracle on sampled shifts."""
+    pool = W.batch_mix(count=40, seed=4)
+    jobs = []
+    for j in pool[:16]:
+        n = 10007
+        jobs.append(W.Job(j.desc, n, cbc.fast_cbc(n, j.desc.dim), 8, j.seed, j.transform))
+    res = _run(ctx, jobs)
+    for j, r in zip(jobs, res):
+        sh = oracle.shifts(j.seed, j.m, j.desc.dim)
+        o = oracle.shift_sums(j.desc, j.n, j.z, j.m, sh, j.transform, ids=[0, 7], threads=THREADS)
+        _check_sums(np.asarray(r["sums_re"])[[0, 7]], o,
+                    np.asarray(r["sums_im"])[[0, 7]] if j.desc.deform else None)
