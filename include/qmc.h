@@ -249,6 +249,37 @@ typedef struct {
 int qmc_integrate_batch(qmc_context* ctx, const qmc_request* reqs, uint32_t count,
                         qmc_result* out, double* shift_sums);
 
+/* ---------------------------------------------------------------- serving */
+
+/*
+ * Continuous batching.  qmc_submit queues `count` requests as one ticket and
+ * returns at once (arrays are copied).  A scheduler thread of the context
+ * admits tickets in arrival order while their device memory (estimated at the
+ * largest lattice they may reach) fits the budget (QMC_SERVE_MEM, default
+ * 8 GiB), and runs rounds of the batch kernels over every admitted request's
+ * current lattice; each request applies its own goal and growth rule
+ * (Sec. 3.3.1) between rounds, so requests arriving while others run join the
+ * next round.  Results equal qmc_integrate_batch's for the same request.
+ * QMC_ENOMEM if the ticket alone exceeds the budget.  Integrands of a
+ * pending ticket cannot be destroyed (QMC_EBUSY).  result.queue_seconds is
+ * submit-to-admission, result.wall_seconds submit-to-completion.
+ */
+int qmc_submit(qmc_context* ctx, const qmc_request* reqs, uint32_t count, uint64_t* ticket);
+
+/* QMC_OK and the ticket's results in out[count] (the ticket is then
+ * released), QMC_PENDING, QMC_ECANCELED, QMC_EDEVICE, or QMC_ENOTFOUND. */
+int qmc_poll(qmc_context* ctx, uint64_t ticket, qmc_result* out);
+
+/* As qmc_poll, blocking up to timeout_s seconds (< 0: no limit). */
+int qmc_wait(qmc_context* ctx, uint64_t ticket, double timeout_s, qmc_result* out);
+
+/* Cancel a ticket: removed before admission or at the next round boundary. */
+int qmc_cancel(qmc_context* ctx, uint64_t ticket);
+
+/* Scheduler counters: rounds run, tickets queued and active, bytes admitted. */
+int qmc_serve_stats(qmc_context* ctx, uint64_t* rounds, uint64_t* queued, uint64_t* active,
+                    uint64_t* bytes_in_use);
+
 /* ---------------------------------------------------------------- debug / parity */
 
 /* The shifts SplitMix64(seed) gives: out[s*dim + j], s < m, j < dim; each

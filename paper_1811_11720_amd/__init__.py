@@ -117,6 +117,11 @@ def _declare(L):
         "qmc_shift_sums_range": ([vp, vp, C.c_uint64, up, C.c_uint32, C.c_uint64, Transform, C.c_uint64,
                                   C.c_uint64, dp, up], C.c_int),
         "qmc_specialize_check": ([C.POINTER(IntegrandDesc), Transform, C.POINTER(C.c_size_t)], C.c_int),
+        "qmc_submit": ([vp, C.POINTER(Request), C.c_uint32, up], C.c_int),
+        "qmc_poll": ([vp, C.c_uint64, C.POINTER(Result)], C.c_int),
+        "qmc_wait": ([vp, C.c_uint64, C.c_double, C.POINTER(Result)], C.c_int),
+        "qmc_cancel": ([vp, C.c_uint64], C.c_int),
+        "qmc_serve_stats": ([vp, up, up, up, up], C.c_int),
         "qmc_histogram": ([vp, vp, C.c_uint64, up, C.c_uint64, C.c_uint32, dp], C.c_int),
         "qmc_fit_vr_from_histogram": ([C.c_uint32, C.c_uint32, dp, dp, C.POINTER(C.c_uint32)], C.c_int),
         "qmc_fit_vr": ([vp, vp, C.c_uint64, up, C.c_uint64, C.c_uint32, dp, C.POINTER(C.c_uint32)], C.c_int),
@@ -280,6 +285,51 @@ class Context:
             d["sums_re"] = out[:m].copy()
             d["sums_im"] = out[m:].copy() if f.complex else np.zeros(m)
         return d
+
+    def _requests(self, reqs):
+        arr = (Request * len(reqs))()
+        keep = []
+        for i, r in enumerate(reqs):
+            z = r.get("z")
+            zp = None
+            if z is not None:
+                zz = np.ascontiguousarray(z, dtype=np.uint64)
+                keep.append(zz)
+                zp = _up(zz)
+            arr[i] = Request(r["f"].handle, r["n"], zp, r["m"], r.get("errormode", ERRMODE_LARGEST), r["seed"],
+                             _tr(r.get("transform", (T_KOROBOV, 3, 3))), r.get("rel_tol", 0.0),
+                             r.get("abs_tol", 0.0), r.get("max_evals", 0))
+        return arr, keep
+
+    def submit(self, reqs) -> int:
+        """Queue a ticket of requests (dicts as in integrate_batch); returns the ticket."""
+        arr, keep = self._requests(reqs)
+        t = C.c_uint64()
+        _check(lib().qmc_submit(self.handle, arr, len(reqs), C.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int, count: int):
+        """None while pending, else the list of result dicts."""
+        res = (Result * count)()
+        rc = _check(lib().qmc_poll(self.handle, ticket, res))
+        if rc == QMC_PENDING:
+            return None
+        return [x.as_dict() for x in res]
+
+    def wait(self, ticket: int, count: int, timeout: float = -1.0):
+        res = (Result * count)()
+        rc = _check(lib().qmc_wait(self.handle, ticket, timeout, res))
+        if rc == QMC_PENDING:
+            return None
+        return [x.as_dict() for x in res]
+
+    def cancel(self, ticket: int):
+        _check(lib().qmc_cancel(self.handle, ticket))
+
+    def serve_stats(self):
+        v = [C.c_uint64() for _ in range(4)]
+        _check(lib().qmc_serve_stats(self.handle, *[C.byref(x) for x in v]))
+        return dict(zip(("rounds", "queued", "active", "bytes_in_use"), (x.value for x in v)))
 
     def integrate_batch(self, reqs, sums: bool = False):
         """reqs: list of dicts with keys f, n, z (or None), m, seed, transform,

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <condition_variable>
 #include <cstdint>
 #include <deque>
@@ -49,6 +50,10 @@ struct qmc_context {
   uint64_t batch_max_ktiles = 2048;   // tiles along k per integral at most
   bool batch_graph = true;            // replay each round's launches as a HIP graph
   hipStream_t cap_stream = nullptr;   // private stream used only for graph capture
+  // serving
+  qmc_serve_state* serve = nullptr;     // scheduler, created by the first qmc_submit
+  size_t serve_mem_limit = (size_t)8 << 30;  // device bytes admitted requests may use
+  uint64_t serve_max_n = (1ull << 31) - 1;   // growth stops above this lattice size
 };
 
 struct qmc_integrand {
@@ -65,7 +70,7 @@ struct qmc_integrand {
   uint32_t* d_expo = nullptr;
   double* d_vr = nullptr;
   float* d_coef32 = nullptr;
-  int refs = 0;
+  std::atomic<int> refs{0};  // pending serving requests that use this integrand
   std::map<int, qmcj::Kernel> jit;  // per (transform kind, VR on) key
   std::map<int, int> jit_failed;
 };
@@ -102,6 +107,10 @@ struct BatchJob {
 int run_batch(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_seconds);
 // Requests through rounds of run_batch (growth loop per request).
 int run_requests(qmc_context* c, const qmc_request* reqs, uint32_t count, qmc_result* out, double* shift_sums);
+// serving scheduler (qmc_serve.cpp)
+void serve_shutdown(qmc_context* c);
+int serve_inflight(qmc_context* c);
+void free_context(qmc_context* c);
 
 }  // namespace qmch
 

@@ -516,6 +516,19 @@ int fill_integrand_args(qmcd::EvalArgs& a, const qmc_integrand* f, const qmc_tra
   return QMC_OK;
 }
 
+void free_context(qmc_context* c) {
+  serve_shutdown(c);
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  if (c->own_ws && c->ws) (void)hipFree(c->ws);
+  if (c->h_stage) (void)hipHostFree(c->h_stage);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  if (c->own_stream) (void)hipStreamDestroy(c->stream);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  delete c;
+}
+
 }  // namespace qmch
 
 using namespace qmch;
@@ -565,6 +578,7 @@ int qmc_context_create(int device, void* hip_stream, void* workspace, size_t wor
     if (sv == 4 || sv == 8 || sv == 16 || sv == 32) c->jit_S = sv;
   }
   if (const char* v = std::getenv("QMC_BATCH_GRAPH")) c->batch_graph = atoi(v) != 0;
+  if (const char* v = std::getenv("QMC_SERVE_MEM")) c->serve_mem_limit = (size_t)strtoull(v, nullptr, 10);
   if (const char* v = std::getenv("QMC_BATCH_TILE")) c->batch_tile_real = std::max(256ull, strtoull(v, nullptr, 10));
   if (const char* v = std::getenv("QMC_BATCH_TILE_COMPLEX"))
     c->batch_tile_complex = std::max(256ull, strtoull(v, nullptr, 10));
@@ -575,25 +589,13 @@ int qmc_context_create(int device, void* hip_stream, void* workspace, size_t wor
   return QMC_OK;
 }
 
-namespace qmch {
-void free_context(qmc_context* c) {
-  (void)hipSetDevice(c->device);
-  if (c->stream) (void)hipStreamSynchronize(c->stream);
-  if (c->own_ws && c->ws) (void)hipFree(c->ws);
-  if (c->h_stage) (void)hipHostFree(c->h_stage);
-  if (c->ev0) (void)hipEventDestroy(c->ev0);
-  if (c->ev1) (void)hipEventDestroy(c->ev1);
-  if (c->own_stream) (void)hipStreamDestroy(c->stream);
-  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-  delete c;
-}
-}  // namespace qmch
 
 int qmc_context_destroy(qmc_context* c) {
   if (!c) return QMC_OK;
   {
     std::lock_guard<std::recursive_mutex> g(c->mu);
-    if (c->inflight) return fail(QMC_EBUSY, "context has %d requests in flight", c->inflight);
+    int inflight = serve_inflight(c);
+    if (inflight) return fail(QMC_EBUSY, "context has %d submitted tickets in flight", inflight);
     if (c->live_integrands > 0) {
       // integrands still reference the context: free it with the last of them
       c->closing = true;
@@ -677,7 +679,7 @@ int qmc_create_integrand(qmc_context* c, const qmc_integrand_desc* d, qmc_integr
 
 int qmc_destroy_integrand(qmc_integrand* f) {
   if (!f) return QMC_OK;
-  if (f->refs) return fail(QMC_EBUSY, "integrand referenced by %d pending requests", f->refs);
+  if (f->refs.load()) return fail(QMC_EBUSY, "integrand referenced by %d pending requests", f->refs.load());
   qmc_context* c = f->ctx;
   bool last = false;
   {

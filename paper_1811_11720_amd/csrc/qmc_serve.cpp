@@ -1,0 +1,369 @@
+// qmc_serve.cpp -- continuous batching of integration requests on one context.
+//
+// qmc_submit queues a ticket (a group of requests) and returns at once.  A
+// scheduler thread per context runs rounds: before each round it admits
+// queued tickets in arrival order while their estimated device memory fits
+// the context's budget; one round evaluates the current lattice of every
+// admitted, unfinished request with the persistent batch kernels
+// (run_batch), then applies each request's own error goal and growth rule
+// (Sec. 3.3.1).  Requests that finish free their memory at once, so tickets
+// that arrive while others are on the GPU join the next round.  A request's
+// results do not depend on what it was batched with (its tiling depends only
+// on its own n and m).  Descriptors stay resident on the device between
+// rounds; a request's state between rounds is (n, z, shifts, round count).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <list>
+
+#include "qmc_host.h"
+
+namespace {
+
+using clk = std::chrono::steady_clock;
+
+struct Req {
+  qmc_request q;
+  qmc_integrand* f;
+  std::vector<double> shifts;
+  std::vector<uint64_t> z;
+  uint64_t n = 0;
+  bool done = false;
+  qmc_result r{};
+  qmch::BatchJob job;
+  size_t bytes = 0;
+};
+
+struct Ticket {
+  uint64_t id;
+  std::vector<Req> reqs;
+  clk::time_point t_submit, t_admit;
+  bool admitted = false, finished = false, cancelled = false;
+  int status = QMC_OK;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct qmc_serve_state {
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::thread thr;
+  bool stop = false;
+  uint64_t next_id = 1;
+  std::list<std::shared_ptr<Ticket>> queue;   // submitted, not admitted
+  std::list<std::shared_ptr<Ticket>> active;  // admitted, running
+  std::map<uint64_t, std::shared_ptr<Ticket>> all;
+  size_t in_use = 0;
+  uint64_t rounds = 0;
+};
+
+namespace qmch {
+
+size_t serve_budget(const qmc_context* c) { return c->serve_mem_limit; }
+
+// device bytes one request needs during a round at its largest lattice
+static size_t request_bytes(const qmc_integrand* f, uint64_t n, uint32_t m, const qmc_context* c) {
+  const bool cplx = (f->flags & QMC_DEFORM) != 0;
+  uint64_t tmin = cplx ? c->batch_tile_complex : c->batch_tile_real;
+  uint64_t tp = std::max<uint64_t>(tmin, (n + c->batch_max_ktiles - 1) / c->batch_max_ktiles);
+  uint64_t kt = (n + tp - 1) / tp;
+  size_t rows = cplx ? 2 * m : m;
+  return sizeof(qmcd::EvalArgs) + rows * (kt * 8 + sizeof(qmck::RowRef) + 8) + (size_t)m * f->dim * 8 + 64;
+}
+
+static void finish_ticket(qmc_serve_state* s, Ticket& t, int status) {
+  t.finished = true;
+  t.status = status;
+  for (auto& r : t.reqs) r.f->refs -= 1;
+  s->in_use -= t.bytes;
+  s->cv_done.notify_all();
+}
+
+static void scheduler(qmc_context* c) {
+  qmc_serve_state* s = c->serve;
+  std::unique_lock<std::mutex> lk(s->mu);
+  for (;;) {
+    // admission: arrival order, while the memory budget allows
+    while (!s->queue.empty()) {
+      auto& t = s->queue.front();
+      if (t->cancelled) {
+        finish_ticket(s, *t, QMC_ECANCELED);
+        s->queue.pop_front();
+        continue;
+      }
+      if (s->in_use + t->bytes > serve_budget(c) && !s->active.empty()) break;
+      t->admitted = true;
+      t->t_admit = clk::now();
+      s->in_use += t->bytes;
+      s->active.push_back(t);
+      s->queue.pop_front();
+    }
+    // drop cancelled tickets at the round boundary
+    for (auto it = s->active.begin(); it != s->active.end();) {
+      if ((*it)->cancelled) {
+        finish_ticket(s, **it, QMC_ECANCELED);
+        it = s->active.erase(it);
+      } else {
+        ++it;
+      }
+    }
+    if (s->active.empty()) {
+      if (s->stop) return;
+      s->cv_work.wait(lk);
+      continue;
+    }
+    // one round over every unfinished request of the admitted tickets
+    std::vector<BatchJob*> jobs;
+    std::vector<std::pair<Ticket*, Req*>> refs;
+    for (auto& t : s->active)
+      for (auto& r : t->reqs)
+        if (!r.done) {
+          r.job.f = r.f;
+          r.job.n = r.n;
+          r.job.z = r.z.data();
+          r.job.m = r.q.m;
+          r.job.shifts = r.shifts.data();
+          r.job.t = r.q.t;
+          jobs.push_back(&r.job);
+          refs.push_back({t.get(), &r});
+        }
+    lk.unlock();
+    double ks = 0.0;
+    int rc;
+    {
+      std::lock_guard<std::recursive_mutex> g(c->mu);
+      rc = c->broken ? QMC_EDEVICE : run_batch(c, jobs, &ks);
+      if (rc == QMC_EDEVICE) c->broken = true;
+    }
+    lk.lock();
+    s->rounds += 1;
+    if (rc != QMC_OK) {
+      for (auto& t : s->active) finish_ticket(s, *t, rc);
+      s->active.clear();
+      continue;
+    }
+    for (auto& pr : refs) {
+      Req& r = *pr.second;
+      const bool cplx = (r.f->flags & QMC_DEFORM) != 0;
+      const uint32_t m = r.q.m;
+      r.r.iterations += 1;
+      r.r.evaluations += r.n * (uint64_t)m;
+      r.r.n = r.n;
+      r.r.device_seconds += ks;
+      std::vector<double> qs(m);
+      for (uint32_t k = 0; k < m; ++k) qs[k] = r.job.sums[k] / (double)r.n;
+      estimate(qs.data(), m, r.r.re, r.r.err_re);
+      r.r.im = r.r.err_im = 0.0;
+      if (cplx) {
+        for (uint32_t k = 0; k < m; ++k) qs[k] = r.job.sums[m + k] / (double)r.n;
+        estimate(qs.data(), m, r.r.im, r.r.err_im);
+      }
+      r.r.flags &= ~(uint32_t)(QMC_NONFINITE | QMC_DEFORM_SIGN);
+      if (r.job.sign_points) r.r.flags |= QMC_DEFORM_SIGN;
+      const bool finite = std::isfinite(r.r.re) && std::isfinite(r.r.im);
+      if (!finite) r.r.flags |= QMC_NONFINITE;
+      const bool grow = r.q.rel_tol > 0 || r.q.abs_tol > 0;
+      if (!grow) {
+        r.done = true;
+        continue;
+      }
+      if (finite && goal_met(r.r, r.q.rel_tol, r.q.abs_tol, r.q.errormode, cplx)) {
+        r.r.flags |= QMC_CONVERGED;
+        r.done = true;
+        continue;
+      }
+      double goal = std::max(r.q.abs_tol, r.q.rel_tol * (cplx ? std::max(std::fabs(r.r.re), std::fabs(r.r.im))
+                                                              : std::fabs(r.r.re)));
+      double err = cplx ? std::max(r.r.err_re, r.r.err_im) : r.r.err_re;
+      double want = std::max(1.5 * (double)r.n, goal > 0 && std::isfinite(err) ? (double)r.n * err / goal : 2.0 * r.n);
+      uint64_t wantu = want >= 9.0e15 ? (uint64_t)9.0e15 : (uint64_t)std::ceil(want);
+      uint64_t nn = 0;
+      if (next_registered(c, wantu, r.f->dim, &nn, false) != QMC_OK || nn > c->serve_max_n ||
+          (r.q.max_evals && r.r.evaluations + nn * (uint64_t)m > r.q.max_evals)) {
+        r.r.flags |= QMC_MAXEVAL_HIT;
+        r.done = true;
+        continue;
+      }
+      r.n = nn;
+      r.z.assign(c->lattices[nn].begin(), c->lattices[nn].begin() + r.f->dim);
+    }
+    for (auto it = s->active.begin(); it != s->active.end();) {
+      Ticket& t = **it;
+      bool all_done = true;
+      for (auto& r : t.reqs) all_done = all_done && r.done;
+      if (all_done) {
+        const double wall = std::chrono::duration<double>(clk::now() - t.t_submit).count();
+        const double queue = std::chrono::duration<double>(t.t_admit - t.t_submit).count();
+        for (auto& r : t.reqs) {
+          r.r.wall_seconds = wall;
+          r.r.queue_seconds = queue;
+          r.r.path = 2;
+        }
+        finish_ticket(s, t, QMC_OK);
+        it = s->active.erase(it);
+      } else {
+        ++it;
+      }
+    }
+  }
+}
+
+void serve_shutdown(qmc_context* c) {
+  if (!c->serve) return;
+  {
+    std::lock_guard<std::mutex> g(c->serve->mu);
+    c->serve->stop = true;
+  }
+  c->serve->cv_work.notify_all();
+  if (c->serve->thr.joinable()) c->serve->thr.join();
+  delete c->serve;
+  c->serve = nullptr;
+}
+
+int serve_inflight(qmc_context* c) {
+  if (!c->serve) return 0;
+  std::lock_guard<std::mutex> g(c->serve->mu);
+  return (int)(c->serve->queue.size() + c->serve->active.size());
+}
+
+}  // namespace qmch
+
+using namespace qmch;
+
+extern "C" {
+
+int qmc_submit(qmc_context* c, const qmc_request* reqs, uint32_t count, uint64_t* ticket) {
+  if (!c || !reqs || !ticket || count == 0) return fail(QMC_EINVAL, "bad arguments");
+  auto t = std::make_shared<Ticket>();
+  t->reqs.resize(count);
+  {
+    std::lock_guard<std::recursive_mutex> g(c->mu);
+    if (c->closing) return fail(QMC_EINVAL, "context has been destroyed");
+    if (c->broken) return fail(QMC_EDEVICE, "context is unusable after a device error");
+    for (uint32_t i = 0; i < count; ++i) {
+      const qmc_request& q = reqs[i];
+      Req& r = t->reqs[i];
+      if (!q.f) return fail(QMC_EINVAL, "request %u has no integrand", i);
+      r.q = q;
+      r.f = const_cast<qmc_integrand*>(q.f);
+      if (r.f->ctx != c) return fail(QMC_EINVAL, "request %u: integrand belongs to another context", i);
+      if (q.m < 1 || q.m > QMC_MAX_SHIFTS) return fail(QMC_EINVAL, "request %u: m=%u", i, q.m);
+      const uint32_t dim = r.f->dim;
+      if (q.z) {
+        int rc = check_lattice(q.n, dim, q.z);
+        if (rc) return rc;
+        r.n = q.n;
+        r.z.assign(q.z, q.z + dim);
+      } else {
+        uint64_t nn = 0;
+        if (next_registered(c, q.n, dim, &nn, true) != QMC_OK)
+          return fail(QMC_ENOTFOUND, "request %u: no registered lattice with %u components", i, dim);
+        r.n = nn;
+        r.z.assign(c->lattices[nn].begin(), c->lattices[nn].begin() + dim);
+      }
+      r.q.z = nullptr;  // the caller's array may be freed after return
+      r.shifts.resize((size_t)q.m * dim);
+      make_shifts(q.seed, q.m, dim, r.shifts.data());
+      r.r.m = q.m;
+      // memory at the largest lattice the request may reach
+      const bool grow = q.rel_tol > 0 || q.abs_tol > 0;
+      uint64_t nmax = r.n;
+      if (grow) nmax = std::max<uint64_t>(r.n, std::min<uint64_t>(c->serve_max_n, c->lattices.empty() ? r.n : c->lattices.rbegin()->first));
+      r.bytes = request_bytes(r.f, nmax, q.m, c);
+      t->bytes += r.bytes;
+    }
+    if (t->bytes > serve_budget(c))
+      return fail(QMC_ENOMEM, "ticket needs %zu bytes, the serving budget is %zu", t->bytes, serve_budget(c));
+    if (!c->serve) {
+      c->serve = new qmc_serve_state();
+      c->serve->thr = std::thread(scheduler, c);
+    }
+  }
+  qmc_serve_state* s = c->serve;
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    t->id = s->next_id++;
+    t->t_submit = clk::now();
+    for (auto& r : t->reqs) r.f->refs += 1;
+    s->queue.push_back(t);
+    s->all[t->id] = t;
+    *ticket = t->id;
+  }
+  s->cv_work.notify_all();
+  return QMC_OK;
+}
+
+static int collect(qmc_serve_state* s, uint64_t ticket, qmc_result* out) {
+  auto it = s->all.find(ticket);
+  if (it == s->all.end()) return fail(QMC_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
+  Ticket& t = *it->second;
+  if (!t.finished) return QMC_PENDING;
+  int st = t.status;
+  if (out && st == QMC_OK)
+    for (size_t i = 0; i < t.reqs.size(); ++i) out[i] = t.reqs[i].r;
+  s->all.erase(it);
+  if (st != QMC_OK) return fail(st, "ticket %llu %s", (unsigned long long)ticket,
+                                st == QMC_ECANCELED ? "was cancelled" : "failed on the device");
+  return QMC_OK;
+}
+
+int qmc_poll(qmc_context* c, uint64_t ticket, qmc_result* out) {
+  if (!c) return fail(QMC_EINVAL, "context is NULL");
+  if (!c->serve) return fail(QMC_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
+  std::lock_guard<std::mutex> g(c->serve->mu);
+  return collect(c->serve, ticket, out);
+}
+
+int qmc_wait(qmc_context* c, uint64_t ticket, double timeout_s, qmc_result* out) {
+  if (!c) return fail(QMC_EINVAL, "context is NULL");
+  if (!c->serve) return fail(QMC_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
+  qmc_serve_state* s = c->serve;
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto deadline = clk::now() + std::chrono::duration_cast<clk::duration>(std::chrono::duration<double>(
+                                   timeout_s < 0 ? 1e9 : timeout_s));
+  for (;;) {
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return fail(QMC_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
+    if (it->second->finished) return collect(s, ticket, out);
+    if (s->cv_done.wait_until(lk, deadline) == std::cv_status::timeout) {
+      it = s->all.find(ticket);
+      if (it != s->all.end() && it->second->finished) return collect(s, ticket, out);
+      return QMC_PENDING;
+    }
+  }
+}
+
+int qmc_cancel(qmc_context* c, uint64_t ticket) {
+  if (!c || !c->serve) return fail(QMC_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
+  qmc_serve_state* s = c->serve;
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return fail(QMC_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
+    if (it->second->finished) return QMC_OK;
+    it->second->cancelled = true;
+  }
+  s->cv_work.notify_all();
+  return QMC_OK;
+}
+
+int qmc_serve_stats(qmc_context* c, uint64_t* rounds, uint64_t* queued, uint64_t* active, uint64_t* bytes_in_use) {
+  if (!c) return fail(QMC_EINVAL, "context is NULL");
+  uint64_t r = 0, q = 0, a = 0, b = 0;
+  if (c->serve) {
+    std::lock_guard<std::mutex> g(c->serve->mu);
+    r = c->serve->rounds;
+    q = c->serve->queue.size();
+    a = c->serve->active.size();
+    b = c->serve->in_use;
+  }
+  if (rounds) *rounds = r;
+  if (queued) *queued = q;
+  if (active) *active = a;
+  if (bytes_in_use) *bytes_in_use = b;
+  return QMC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,162 @@
+"""Serving: continuous batching through qmc_submit / qmc_poll / qmc_wait."""
+
+import os
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from paper_1811_11720_amd import cbc
+from test_parity_gpu import THREADS, make_ctx
+
+pytestmark = pytest.mark.gpu
+
+KOR3 = (W.T_KOROBOV, 3, 3)
+
+
+def _serve_ctx(mem=None):
+    old = os.environ.get("QMC_SERVE_MEM")
+    if mem is not None:
+        os.environ["QMC_SERVE_MEM"] = str(mem)
+    try:
+        c = make_ctx("generic")
+    finally:
+        if old is None:
+            os.environ.pop("QMC_SERVE_MEM", None)
+        else:
+            os.environ["QMC_SERVE_MEM"] = old
+    c.register_table({n: z for n, z in W.lattice_table().items() if n <= 2_000_000})
+    return c
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = _serve_ctx()
+    yield c
+    c.close()
+
+
+def _requests(ctx, count, seed, rel=None, keep=None):
+    pool = W.batch_mix(count=count, seed=seed, n_lo=1e4, n_hi=1e5, m=16)
+    reqs = []
+    for j in pool:
+        f = ctx.integrand(j.desc)
+        if keep is not None:
+            keep.append(f)
+        r = dict(f=f, n=j.n, z=j.z, m=j.m, seed=j.seed, transform=j.transform)
+        if rel is not None:
+            r.update(z=None, rel_tol=rel, max_evals=10 ** 9)
+        reqs.append(r)
+    return reqs
+
+
+def test_served_results_equal_the_batch_path(ctx):
+    keep = []
+    reqs = _requests(ctx, 12, 31, keep=keep)
+    t = ctx.submit(reqs)
+    served = ctx.wait(t, len(reqs), timeout=120)
+    direct = ctx.integrate_batch(reqs)
+    for a, b in zip(served, direct):
+        assert a["re"] == b["re"] and a["im"] == b["im"] and a["err_re"] == b["err_re"]
+        assert a["path"] == 2 and a["wall_seconds"] >= a["queue_seconds"] >= 0
+
+
+def test_each_result_is_the_same_alone_and_in_the_mix(ctx):
+    keep = []
+    reqs = _requests(ctx, 20, 32, keep=keep)
+    alone = []
+    for r in reqs[:4]:
+        t = ctx.submit([r])
+        alone.append(ctx.wait(t, 1, timeout=120)[0])
+    # the same four requests again, each in its own ticket, while many others run
+    tickets = [ctx.submit(reqs[4:12]), ctx.submit(reqs[:2]), ctx.submit(reqs[12:]), ctx.submit(reqs[2:4])]
+    mixed = ctx.wait(tickets[1], 2, timeout=300) + ctx.wait(tickets[3], 2, timeout=300)
+    ctx.wait(tickets[0], 8, timeout=300)
+    ctx.wait(tickets[2], 8, timeout=300)
+    for a, b in zip(alone, mixed):
+        assert a["re"] == b["re"] and a["im"] == b["im"] and a["err_re"] == b["err_re"] and a["err_im"] == b["err_im"]
+
+
+def test_growth_requests_meet_their_goals_and_match_the_oracle(ctx):
+    keep = []
+    reqs = _requests(ctx, 6, 33, rel=1e-6, keep=keep)
+    t = ctx.submit(reqs)
+    res = ctx.wait(t, len(reqs), timeout=300)
+    for r, q in zip(res, reqs):
+        assert r["iterations"] >= 1
+        if r["flags"] & 1:
+            err = max(r["err_re"], r["err_im"])
+            assert err <= 1e-6 * max(abs(r["re"]), abs(r["im"]))
+    # one of them against the oracle at its final lattice
+    j = 0
+    desc = W.batch_mix(count=6, seed=33, n_lo=1e4, n_hi=1e5, m=16)[j]
+    n = res[j]["n"]
+    z = W.z_for(n, desc.desc.dim)
+    sh = oracle.shifts(desc.seed, 16, desc.desc.dim)
+    o = oracle.shift_sums(desc.desc, n, z, 16, sh, desc.transform, threads=THREADS)
+    q, e = oracle.estimate(o.re / n)
+    assert abs(q - res[j]["re"]) <= 1e-12 * np.mean(o.abs_re) / n * 16 + 1e-15
+
+
+def test_late_arrivals_join_while_others_run(ctx):
+    keep = []
+    big = W.batch_mix(count=6, seed=34, n_lo=1e6, n_hi=2e6, m=32)
+    big_reqs = []
+    for j in big:
+        f = ctx.integrand(j.desc)
+        keep.append(f)
+        big_reqs.append(dict(f=f, n=j.n, z=j.z, m=j.m, seed=j.seed, transform=j.transform))
+    t_big = ctx.submit(big_reqs)
+    time.sleep(0.01)
+    small = _requests(ctx, 3, 35, keep=keep)
+    t_small = ctx.submit(small)
+    r_small = ctx.wait(t_small, len(small), timeout=300)
+    r_big = ctx.wait(t_big, len(big_reqs), timeout=300)
+    assert r_small is not None and r_big is not None
+    st = ctx.serve_stats()
+    assert st["queued"] == 0 and st["active"] == 0 and st["bytes_in_use"] == 0 and st["rounds"] >= 1
+
+
+def test_memory_admission_queues_and_rejects():
+    c = _serve_ctx(mem=600_000)
+    keep = []
+    reqs = _requests(c, 8, 36, keep=keep)
+    tickets = [c.submit([r]) for r in reqs]
+    res = [c.wait(t, 1, timeout=120)[0] for t in tickets]
+    assert all(r is not None for r in res)
+    # a ticket larger than the whole budget is refused at submission
+    import paper_1811_11720_amd as Q
+
+    with pytest.raises(Q.QmcError) as e:
+        c.submit(reqs * 40)
+    assert e.value.code == Q.QMC_ENOMEM
+    for f in keep:
+        f.close()
+    c.close()
+
+
+def test_cancel_and_busy_integrand(ctx):
+    import paper_1811_11720_amd as Q
+
+    keep = []
+    big = W.batch_mix(count=4, seed=37, n_lo=1.5e6, n_hi=2.5e6, m=32)
+    reqs = []
+    for j in big:
+        f = ctx.integrand(j.desc)
+        keep.append(f)
+        reqs.append(dict(f=f, n=j.n, z=j.z, m=j.m, seed=j.seed, transform=j.transform))
+    t1 = ctx.submit(reqs)
+    t2 = ctx.submit(reqs)
+    ctx.cancel(t2)
+    with pytest.raises(Q.QmcError) as e:
+        keep[0].close()  # still referenced by pending tickets
+    assert e.value.code == Q.QMC_EBUSY
+    assert ctx.wait(t1, 4, timeout=300) is not None
+    with pytest.raises(Q.QmcError) as e:
+        ctx.wait(t2, 4, timeout=300)
+    assert e.value.code == Q.QMC_ECANCELED
+    with pytest.raises(Q.QmcError) as e:
+        ctx.poll(t2, 4)
+    assert e.value.code == Q.QMC_ENOTFOUND
