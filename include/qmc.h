@@ -249,6 +249,18 @@ typedef struct {
 int qmc_integrate_batch(qmc_context* ctx, const qmc_request* reqs, uint32_t count,
                         qmc_result* out, double* shift_sums);
 
+/*
+ * Autotune the batch kernels on a sample of requests: for every kernel variant
+ * (dimension class, real/complex, fp64/fp32) present in the sample, time each
+ * compiled points-per-decode variant and candidate tile size on one round and
+ * keep the fastest for this context (and append it to the file named by the
+ * environment variable QMC_TUNE_CACHE, read at context creation).  The
+ * points-per-decode choice never changes results; the tile size fixes the
+ * summation order, so tune before integrating, not between calls whose sums
+ * must match bitwise.  *configs_tried (optional) counts timed schedules.
+ */
+int qmc_autotune_batch(qmc_context* ctx, const qmc_request* reqs, uint32_t count, uint32_t* configs_tried);
+
 /* ---------------------------------------------------------------- serving */
 
 /*

@@ -117,6 +117,7 @@ def _declare(L):
         "qmc_shift_sums_range": ([vp, vp, C.c_uint64, up, C.c_uint32, C.c_uint64, Transform, C.c_uint64,
                                   C.c_uint64, dp, up], C.c_int),
         "qmc_specialize_check": ([C.POINTER(IntegrandDesc), Transform, C.POINTER(C.c_size_t)], C.c_int),
+        "qmc_autotune_batch": ([vp, C.POINTER(Request), C.c_uint32, C.POINTER(C.c_uint32)], C.c_int),
         "qmc_submit": ([vp, C.POINTER(Request), C.c_uint32, up], C.c_int),
         "qmc_poll": ([vp, C.c_uint64, C.POINTER(Result)], C.c_int),
         "qmc_wait": ([vp, C.c_uint64, C.c_double, C.POINTER(Result)], C.c_int),
@@ -300,6 +301,12 @@ class Context:
                              _tr(r.get("transform", (T_KOROBOV, 3, 3))), r.get("rel_tol", 0.0),
                              r.get("abs_tol", 0.0), r.get("max_evals", 0))
         return arr, keep
+
+    def autotune_batch(self, reqs) -> int:
+        arr, keep = self._requests(reqs)
+        n = C.c_uint32()
+        _check(lib().qmc_autotune_batch(self.handle, arr, len(reqs), C.byref(n)))
+        return n.value
 
     def submit(self, reqs) -> int:
         """Queue a ticket of requests (dicts as in integrate_batch); returns the ticket."""

@@ -16,6 +16,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <cstdio>
 #include <numeric>
 
 #include "qmc_host.h"
@@ -55,7 +56,8 @@ int run_batch(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_secon
     const int dclass = qmck::dim_class(f->dim);
     p.variant = dclass * 4 + (cplx ? 2 : 0) + (fp32 ? 1 : 0);
     const uint32_t S = cplx ? qmck::S_COMPLEX : qmck::S_REAL;
-    const uint64_t tmin = cplx ? c->batch_tile_complex : c->batch_tile_real;
+    const uint64_t tuned = c->batch_tile[dclass][cplx ? 1 : 0][fp32 ? 1 : 0];
+    const uint64_t tmin = tuned ? tuned : (cplx ? c->batch_tile_complex : c->batch_tile_real);
     uint64_t tp = std::max<uint64_t>(tmin, (b.n + c->batch_max_ktiles - 1) / c->batch_max_ktiles);
     tp = (tp + QMCD_BLOCK - 1) / QMCD_BLOCK * QMCD_BLOCK;
     p.tile_points = tp;
@@ -175,9 +177,10 @@ int run_batch(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_secon
     HIPCHK(qmck::launch_fill_u64(d_sign, J, 0ull, st));
     for (uint32_t v = 0; v < (uint32_t)launches.size(); ++v) {
       const Launch& L = launches[v];
-      int occ = qmck::occupancy_batch(L.dclass, L.cplx, L.fp32);
+      const int sv = L.cplx ? 0 : c->batch_sv[L.dclass][0][L.fp32 ? 1 : 0];
+      int occ = qmck::occupancy_batch(L.dclass, L.cplx, L.fp32, sv);
       uint32_t blocks = (uint32_t)std::max(1, occ) * (uint32_t)c->cus;
-      HIPCHK(qmck::launch_batch(L.dclass, L.cplx, L.fp32, (const qmcd::EvalArgs*)(ws + o_items),
+      HIPCHK(qmck::launch_batch(L.dclass, L.cplx, L.fp32, sv, (const qmcd::EvalArgs*)(ws + o_items),
                                 (const uint32_t*)(ws + o_order) + L.first,
                                 (const uint32_t*)(ws + o_prefix) + L.prefix_off, L.count,
                                 (uint32_t*)(ws + o_cnt) + v, blocks, st));
@@ -348,4 +351,94 @@ int run_requests(qmc_context* c, const qmc_request* reqs, uint32_t count, qmc_re
   return QMC_OK;
 }
 
+// ---------------------------------------------------------------- autotuning
+
+// Variant key of an integrand: dimension class, complex, fp32.
+static void variant_of(const qmc_integrand* f, int& dc, int& cx, int& f32) {
+  dc = qmck::dim_class(f->dim);
+  cx = (f->flags & QMC_DEFORM) ? 1 : 0;
+  f32 = (f->flags & QMC_EVAL_FP32) ? 1 : 0;
+}
+
+void load_tune_cache(qmc_context* c) {
+  if (c->tune_cache.empty()) return;
+  FILE* fh = std::fopen(c->tune_cache.c_str(), "r");
+  if (!fh) return;
+  int dc, cx, f32, sv;
+  unsigned long long tile;
+  char arch[64];
+  while (std::fscanf(fh, "%63s %d %d %d %d %llu", arch, &dc, &cx, &f32, &sv, &tile) == 6) {
+    if (std::strcmp(arch, "gfx950") != 0 || dc < 0 || dc > 3 || cx < 0 || cx > 1 || f32 < 0 || f32 > 1) continue;
+    if (sv >= 0 && sv < qmck::BATCH_SV_VARIANTS) c->batch_sv[dc][cx][f32] = sv;
+    if (tile >= 256 && tile <= (1ull << 24)) c->batch_tile[dc][cx][f32] = tile;
+  }
+  std::fclose(fh);
+}
+
+// Time each candidate schedule of every variant present in the sample
+// (one round, first lattice of each request) and keep the fastest.
+int autotune(qmc_context* c, const qmc_request* reqs, uint32_t count, uint32_t* configs_tried) {
+  std::map<int, std::vector<uint32_t>> by_var;
+  for (uint32_t i = 0; i < count; ++i) {
+    if (!reqs[i].f || reqs[i].f->ctx != c) return fail(QMC_EINVAL, "request %u: bad integrand", i);
+    int dc, cx, f32;
+    variant_of(reqs[i].f, dc, cx, f32);
+    by_var[dc * 4 + cx * 2 + f32].push_back(i);
+  }
+  uint32_t tried = 0;
+  for (auto& kv : by_var) {
+    const int dc = kv.first / 4, cx = (kv.first >> 1) & 1, f32 = kv.first & 1;
+    std::vector<qmc_request> sub;
+    for (uint32_t i : kv.second) {
+      qmc_request q = reqs[i];
+      q.rel_tol = q.abs_tol = 0.0;  // one lattice
+      sub.push_back(q);
+    }
+    const std::vector<uint64_t> tiles = cx ? std::vector<uint64_t>{512, 1024, 4096}
+                                           : std::vector<uint64_t>{1024, 4096, 16384};
+    const int nsv = cx ? 1 : qmck::BATCH_SV_VARIANTS;
+    double best = 1e300;
+    int best_sv = 0;
+    uint64_t best_tile = tiles[0];
+    for (int sv = 0; sv < nsv; ++sv) {
+      if (!qmck::batch_kernel(dc, cx, f32, sv)) continue;
+      for (uint64_t tile : tiles) {
+        c->batch_sv[dc][cx][f32] = sv;
+        c->batch_tile[dc][cx][f32] = tile;
+        double t_best = 1e300;
+        for (int rep = 0; rep < 2; ++rep) {
+          std::vector<qmc_result> out(sub.size());
+          int rc = run_requests(c, sub.data(), (uint32_t)sub.size(), out.data(), nullptr);
+          if (rc) return rc;
+          t_best = std::min(t_best, out[0].device_seconds);
+        }
+        ++tried;
+        if (t_best < best) {
+          best = t_best;
+          best_sv = sv;
+          best_tile = tile;
+        }
+      }
+    }
+    c->batch_sv[dc][cx][f32] = best_sv;
+    c->batch_tile[dc][cx][f32] = best_tile;
+    if (!c->tune_cache.empty()) {
+      if (FILE* fh = std::fopen(c->tune_cache.c_str(), "a")) {
+        std::fprintf(fh, "gfx950 %d %d %d %d %llu\n", dc, cx, f32, best_sv, (unsigned long long)best_tile);
+        std::fclose(fh);
+      }
+    }
+  }
+  if (configs_tried) *configs_tried = tried;
+  return QMC_OK;
+}
+
 }  // namespace qmch
+
+extern "C" int qmc_autotune_batch(qmc_context* c, const qmc_request* reqs, uint32_t count, uint32_t* configs_tried) {
+  if (!c || (!reqs && count)) return qmch::fail(QMC_EINVAL, "NULL argument");
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  if (c->broken) return qmch::fail(QMC_EDEVICE, "context is unusable after a device error");
+  HIPCHK(hipSetDevice(c->device));
+  return qmch::autotune(c, reqs, count, configs_tried);
+}

@@ -825,6 +825,154 @@ __device__ __forceinline__ void eval_real_body(const EvalArgs& a, const Fn& fn) 
   eval_real_sched<DMAX, TK, IDX32, S, EXACT, Fn, VRM, false>(a, fn, grid_sched(a, S));
 }
 
+// ------------------------------------------------------------------ table-driven evaluation of SV points at once
+// The exponent table is decoded once per (monomial, variable) with uniform
+// scalar instructions and applied to SV points (a thread's shifts), so the
+// scalar decoding is amortised over SV multiplies.
+
+template <int DMAX, int SV, class T, class C>
+__device__ __forceinline__ void poly_eval_multi(const C* __restrict__ coef, const uint32_t* __restrict__ expo,
+                                                uint32_t first, uint32_t count, const T (&x)[SV][DMAX],
+                                                T (&out)[SV]) {
+#pragma unroll
+  for (int v = 0; v < SV; ++v) out[v] = T(0);
+  for (uint32_t i = first; i < first + count; ++i) {
+    const T c = (T)coef[i];
+    T t[SV];
+#pragma unroll
+    for (int v = 0; v < SV; ++v) t[v] = c;
+#pragma unroll
+    for (int w = 0; w < (DMAX + 7) / 8; ++w) {
+      const uint32_t word = expo[2 * i + w];
+#pragma unroll
+      for (int jj = 0; jj < 8; ++jj) {
+        const int j = 8 * w + jj;
+        if (j >= DMAX) break;
+        const uint32_t e = (word >> (4 * jj)) & 15u;
+        if (e == 0u) continue;
+        if (e == 1u) {
+#pragma unroll
+          for (int v = 0; v < SV; ++v) t[v] *= x[v][j];
+        } else if (e == 2u) {
+#pragma unroll
+          for (int v = 0; v < SV; ++v) t[v] *= x[v][j] * x[v][j];
+        } else {
+#pragma unroll
+          for (int v = 0; v < SV; ++v) t[v] *= xpow<T>(x[v][j], x[v][j] * x[v][j], e);
+        }
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < SV; ++v) out[v] += t[v];
+  }
+}
+
+// prefactor * U^pow_u * F^pow_f at SV points, fp64 (F32 = false) or fp32 polynomials and powers
+template <int DMAX, int SV, bool F32>
+__device__ __forceinline__ void generic_real_multi(const double (&x)[SV][DMAX], double (&f)[SV], const EvalArgs& a) {
+  if constexpr (F32) {
+    float xf[SV][DMAX];
+#pragma unroll
+    for (int v = 0; v < SV; ++v)
+#pragma unroll
+      for (int j = 0; j < DMAX; ++j) xf[v][j] = (float)x[v][j];
+    float U[SV], F[SV];
+    poly_eval_multi<DMAX, SV, float, float>(a.coef32, a.expo, 0, a.n_u, xf, U);
+    if (a.n_f) poly_eval_multi<DMAX, SV, float, float>(a.coef32, a.expo, a.n_u, a.n_f, xf, F);
+#pragma unroll
+    for (int v = 0; v < SV; ++v) {
+      float num = (float)a.prefactor, den = 1.0f;
+      apply_pow_f32(U[v], a.pu_mode, a.pu_k, a.pow_u, num, den);
+      if (a.n_f) apply_pow_f32(F[v], a.pf_mode, a.pf_k, a.pow_f, num, den);
+      f[v] = (double)(num * frcp(den));
+    }
+  } else {
+    double U[SV], F[SV];
+    poly_eval_multi<DMAX, SV, double, double>(a.coef, a.expo, 0, a.n_u, x, U);
+    if (a.n_f) poly_eval_multi<DMAX, SV, double, double>(a.coef, a.expo, a.n_u, a.n_f, x, F);
+#pragma unroll
+    for (int v = 0; v < SV; ++v) {
+      double num = a.prefactor, den = 1.0;
+      apply_pow<double>(U[v], a.pu_mode, a.pu_k, a.pow_u, num, den);
+      if (a.n_f) apply_pow<double>(F[v], a.pf_mode, a.pf_k, a.pow_f, num, den);
+      f[v] = num * fast_rcp(den);
+    }
+  }
+}
+
+// Same contract as eval_real_sched with the table-driven integrand, evaluating
+// the S shifts of the group SV at a time.
+template <int DMAX, int TK, bool IDX32, int S, int SV, bool F32, bool COMP>
+__device__ __forceinline__ void eval_real_multi_sched(const EvalArgs& a, const Sched& sc) {
+  static_assert(S % SV == 0, "shift group must be a multiple of the point group");
+  const uint32_t s0 = sc.s0;
+  const uint32_t ns = (a.m - s0) < (uint32_t)S ? (a.m - s0) : (uint32_t)S;
+  const uint32_t dim = a.dim;
+  double acc[S], cmp[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) acc[s] = cmp[s] = 0.0;
+
+  uint64_t k = sc.k;
+  uint64_t r[DMAX];
+#pragma unroll
+  for (int j = 0; j < DMAX; ++j) r[j] = (j < (int)dim && k < sc.k_end) ? start_index(k, a.z[j], a.n) : 0;
+
+  for (; k < sc.k_end; k += sc.stride) {
+    double q[DMAX];
+#pragma unroll
+    for (int j = 0; j < DMAX; ++j)
+      q[j] = exact_quotient(IDX32 ? (double)(uint32_t)r[j] : (double)r[j], a.n_d, a.inv_n);
+#pragma unroll
+    for (int g = 0; g < S / SV; ++g) {
+      if ((uint32_t)(g * SV) < ns) {
+        double x[SV][DMAX], w[SV];
+#pragma unroll
+        for (int v = 0; v < SV; ++v) {
+          // shifts beyond m reuse the group's first shift; their sums are never stored
+          const uint32_t s = ((uint32_t)(g * SV + v) < ns) ? (uint32_t)(g * SV + v) : 0u;
+          const double* __restrict__ D = a.shifts + (size_t)(s0 + s) * dim;
+          double wt = 1.0, wv = 1.0;
+#pragma unroll
+          for (int j = 0; j < DMAX; ++j) {
+            if (j < (int)dim) {
+              double u = shifted(q[j], D[j]);
+              double y = transform<TK>(u, wt, a);
+              if (a.vr) y = vr_map(y, a.vr + 6 * j, wv);
+              x[v][j] = y;
+            } else {
+              x[v][j] = 0.0;
+            }
+          }
+          if (TK == TK_KOROBOV3 || (TK == TK_RUNTIME && a.tk == TK_KOROBOV3)) wt = a.wscale * (wt * wt * wt);
+          w[v] = wt * wv;
+        }
+        double f[SV];
+        generic_real_multi<DMAX, SV, F32>(x, f, a);
+#pragma unroll
+        for (int v = 0; v < SV; ++v) {
+          double val = (w[v] == 0.0) ? 0.0 : w[v] * f[v];
+          if (COMP)
+            neumaier(acc[g * SV + v], cmp[g * SV + v], val);
+          else
+            acc[g * SV + v] += val;
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < DMAX; ++j) {
+      if (IDX32)
+        r[j] = step_u32((uint32_t)r[j], (uint32_t)sc.step[j], (uint32_t)a.n);
+      else
+        r[j] = step_u64(r[j], sc.step[j], a.n);
+    }
+  }
+  if (COMP) {
+#pragma unroll
+    for (int s = 0; s < S; ++s) acc[s] += cmp[s];
+  }
+  block_store<S>(acc, ns, s0, a.partial, a.nblocks, sc.col);
+}
+
 // Complex (deformed) evaluation: rows [row0, row0+ns) hold Re, rows
 // [m + row0, ...) hold Im of the per-shift partial sums.
 // Padding variables (j >= dim in the class kernels) get x = 0: no monomial

@@ -49,6 +49,10 @@ struct qmc_context {
   uint64_t batch_tile_complex = 1024;  // ... (complex integrands)
   uint64_t batch_max_ktiles = 2048;   // tiles along k per integral at most
   bool batch_graph = true;            // replay each round's launches as a HIP graph
+  // per kernel variant [dimension class][complex][fp32]: tuned schedule (0 = default)
+  int batch_sv[4][2][2] = {};          // index into the compiled points-per-decode variants
+  uint64_t batch_tile[4][2][2] = {};   // minimum points per tile
+  std::string tune_cache;             // file the autotuner reads and appends
   hipStream_t cap_stream = nullptr;   // private stream used only for graph capture
   // serving
   qmc_serve_state* serve = nullptr;     // scheduler, created by the first qmc_submit
@@ -111,6 +115,7 @@ int run_requests(qmc_context* c, const qmc_request* reqs, uint32_t count, qmc_re
 void serve_shutdown(qmc_context* c);
 int serve_inflight(qmc_context* c);
 void free_context(qmc_context* c);
+void load_tune_cache(qmc_context* c);
 
 }  // namespace qmch
 

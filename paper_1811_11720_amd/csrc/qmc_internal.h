@@ -17,6 +17,8 @@ enum Kind { KIND_REAL = 0 };
 
 // shifts per thread group of the real kernel (grid.y = ceil(m / S))
 constexpr int S_REAL = 8;
+// points evaluated together by the table-driven real kernels (register budget)
+constexpr int sv_real(int dmax, bool fp32) { return (fp32 || dmax <= 8) ? 2 : 1; }
 // shifts per thread group of the complex kernels (one evaluation is ~1e3 instructions)
 constexpr int S_COMPLEX = 2;
 // ... of the specialised complex kernels (register pressure: one point's Jacobian at a time)
@@ -42,10 +44,12 @@ hipError_t launch_indices(uint64_t n, uint32_t dim, const uint64_t* z_host, uint
 
 // ---------------------------------------------------------------- batches
 using BatchFn = void (*)(const qmcd::EvalArgs*, const uint32_t*, const uint32_t*, uint32_t, uint32_t*);
-// [dclass][complex][fp32]; complex entries exist for classes up to 12 variables
-BatchFn batch_kernel(int dclass, bool cplx, bool fp32);
-int occupancy_batch(int dclass, bool cplx, bool fp32);
-hipError_t launch_batch(int dclass, bool cplx, bool fp32, const qmcd::EvalArgs* items, const uint32_t* order,
+// [dclass][complex][fp32][sv]; complex entries exist for classes up to 12 variables and sv index 0.
+// sv index i selects 2^i points per decoded monomial (real kernels).
+constexpr int BATCH_SV_VARIANTS = 3;
+BatchFn batch_kernel(int dclass, bool cplx, bool fp32, int sv);
+int occupancy_batch(int dclass, bool cplx, bool fp32, int sv);
+hipError_t launch_batch(int dclass, bool cplx, bool fp32, int sv, const qmcd::EvalArgs* items, const uint32_t* order,
                         const uint32_t* prefix, uint32_t nitems, uint32_t* counter, uint32_t blocks, hipStream_t st);
 
 // Sums rows of per-item partial arrays in a fixed order: out[r] = sum_c rows[r].p[c].

@@ -9,8 +9,9 @@
 namespace qmck {
 
 template <int DMAX, int TK, bool IDX32>
-__global__ __launch_bounds__(QMCD_BLOCK) void k_eval_real(qmcd::EvalArgs a) {
-  qmcd::eval_real_body<DMAX, TK, IDX32, S_REAL, false>(a, qmcd::GenericReal<DMAX>());
+__global__ __launch_bounds__(QMCD_BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void k_eval_real(qmcd::EvalArgs a) {
+  qmcd::eval_real_multi_sched<DMAX, TK, IDX32, S_REAL, sv_real(DMAX, false), false, false>(
+      a, qmcd::grid_sched(a, S_REAL));
 }
 
 }  // namespace qmck
@@ -125,23 +126,24 @@ hipError_t launch_finalize_rows(const RowRef* rows, uint32_t nrows, double* out,
   return hipLaunchKernel((const void*)k_finalize_rows, dim3(nrows), dim3(QMCD_BLOCK), args, 0, st);
 }
 
-extern BatchFn g_batch4[2][2], g_batch8[2][2], g_batch12[2][2], g_batch16[2][2];
+extern BatchFn g_batch4[2][2][3], g_batch8[2][2][3], g_batch12[2][2][3], g_batch16[2][2][3];
 
-BatchFn batch_kernel(int dclass, bool cplx, bool fp32) {
-  BatchFn(*t)[2] = dclass == 0 ? g_batch4 : dclass == 1 ? g_batch8 : dclass == 2 ? g_batch12 : g_batch16;
-  return t[cplx ? 1 : 0][fp32 ? 1 : 0];
+BatchFn batch_kernel(int dclass, bool cplx, bool fp32, int sv) {
+  if (sv < 0 || sv >= BATCH_SV_VARIANTS) return nullptr;
+  BatchFn(*t)[2][3] = dclass == 0 ? g_batch4 : dclass == 1 ? g_batch8 : dclass == 2 ? g_batch12 : g_batch16;
+  return t[cplx ? 1 : 0][fp32 ? 1 : 0][sv];
 }
 
-int occupancy_batch(int dclass, bool cplx, bool fp32) {
-  BatchFn fn = batch_kernel(dclass, cplx, fp32);
+int occupancy_batch(int dclass, bool cplx, bool fp32, int sv) {
+  BatchFn fn = batch_kernel(dclass, cplx, fp32, sv);
   int occ = 0;
   if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)fn, QMCD_BLOCK, 0) != hipSuccess) return 0;
   return occ;
 }
 
-hipError_t launch_batch(int dclass, bool cplx, bool fp32, const qmcd::EvalArgs* items, const uint32_t* order,
+hipError_t launch_batch(int dclass, bool cplx, bool fp32, int sv, const qmcd::EvalArgs* items, const uint32_t* order,
                         const uint32_t* prefix, uint32_t nitems, uint32_t* counter, uint32_t blocks, hipStream_t st) {
-  BatchFn fn = batch_kernel(dclass, cplx, fp32);
+  BatchFn fn = batch_kernel(dclass, cplx, fp32, sv);
   if (!fn) return hipErrorInvalidValue;
   void* args[] = {(void*)&items, (void*)&order, (void*)&prefix, (void*)&nitems, (void*)&counter};
   return hipLaunchKernel((const void*)fn, dim3(blocks), dim3(QMCD_BLOCK), args, 0, st);

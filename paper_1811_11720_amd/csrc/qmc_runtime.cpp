@@ -579,6 +579,17 @@ int qmc_context_create(int device, void* hip_stream, void* workspace, size_t wor
   }
   if (const char* v = std::getenv("QMC_BATCH_GRAPH")) c->batch_graph = atoi(v) != 0;
   if (const char* v = std::getenv("QMC_SERVE_MEM")) c->serve_mem_limit = (size_t)strtoull(v, nullptr, 10);
+  for (int dc = 0; dc < 4; ++dc)
+    for (int f32 = 0; f32 < 2; ++f32) c->batch_sv[dc][0][f32] = qmck::sv_real(qmck::dim_class_max(dc), f32) == 2 ? 1 : 0;
+  if (const char* v = std::getenv("QMC_BATCH_SV")) {  // force one points-per-decode variant
+    const int sv = atoi(v);
+    if (sv >= 0 && sv < qmck::BATCH_SV_VARIANTS)
+      for (int dc = 0; dc < 4; ++dc) c->batch_sv[dc][0][0] = c->batch_sv[dc][0][1] = sv;
+  }
+  if (const char* v = std::getenv("QMC_TUNE_CACHE")) {
+    c->tune_cache = v;
+    load_tune_cache(c);
+  }
   if (const char* v = std::getenv("QMC_BATCH_TILE")) c->batch_tile_real = std::max(256ull, strtoull(v, nullptr, 10));
   if (const char* v = std::getenv("QMC_BATCH_TILE_COMPLEX"))
     c->batch_tile_complex = std::max(256ull, strtoull(v, nullptr, 10));

@@ -143,3 +143,58 @@ def test_batch_of_sector_mix_workload(ctx):
         o = oracle.shift_sums(j.desc, j.n, j.z, j.m, sh, j.transform, ids=[0, 7], threads=THREADS)
         _check_sums(np.asarray(r["sums_re"])[[0, 7]], o,
                     np.asarray(r["sums_im"])[[0, 7]] if j.desc.deform else None)
+
+
+def _ctx_env(**env):
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update({k: str(v) for k, v in env.items()})
+    try:
+        return make_ctx("generic")
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+def test_points_per_decode_variants_give_identical_sums():
+    """The compiled points-per-decode variants only regroup the scalar decode
+    of the monomial table; every point's arithmetic and the accumulation order
+    are the same, so the sums must agree bitwise."""
+    jobs = _mix(12, 6) + _mix(6, 7, fp32=True)
+    outs = []
+    for sv in range(3):
+        c = _ctx_env(QMC_BATCH_SV=sv)
+        outs.append(_run(c, jobs))
+        c.close()
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a["sums_re"], b["sums_re"]) and np.array_equal(a["sums_im"], b["sums_im"])
+
+
+def test_autotune_keeps_parity_and_writes_its_cache(tmp_path):
+    cache = tmp_path / "tune.txt"
+    jobs = _mix(10, 8)
+    c = _ctx_env(QMC_TUNE_CACHE=cache)
+    keep = []
+    fs = [c.integrand(j.desc) for j in jobs]
+    reqs = [dict(f=f, n=j.n, z=j.z, m=j.m, seed=j.seed, transform=j.transform) for f, j in zip(fs, jobs)]
+    tried = c.autotune_batch(reqs)
+    assert tried >= 3
+    res = c.integrate_batch(reqs, sums=True)
+    for j, r in zip(jobs, res):
+        sh = oracle.shifts(j.seed, j.m, j.desc.dim)
+        o = oracle.shift_sums(j.desc, j.n, j.z, j.m, sh, j.transform, threads=THREADS)
+        _check_sums(r["sums_re"], o, r["sums_im"] if j.desc.deform else None, label=f"d{j.desc.dim}")
+    lines = cache.read_text().split()
+    assert len(lines) >= 6 and lines[0] == "gfx950"
+    # a new context reads the cache and reproduces the tuned schedule bitwise
+    c2 = _ctx_env(QMC_TUNE_CACHE=cache)
+    again = _run(c2, jobs, keep=keep)
+    for a, b in zip(res, again):
+        assert np.array_equal(a["sums_re"], b["sums_re"]) and np.array_equal(a["sums_im"], b["sums_im"])
+    for f in fs + keep:
+        f.close()
+    c.close()
+    c2.close()
