@@ -63,6 +63,48 @@ def flops_per_eval(desc, transform) -> float:
     return fl
 
 
+def flops_per_eval_complex(desc, transform) -> float:
+    """Algorithmic flops of one deformed complex evaluation: the real
+    x-generation and transform; per F monomial 3 nnz + 2 nnz (nnz + 1) for its
+    gradient and Hessian terms; 4d for z; 3d^2 to form the matrix whose
+    determinant is the Jacobian and 8 d^3 / 3 for its complex elimination;
+    6 nnz + 4 per complex monomial of U(z) and F(z); complex powers at six
+    flops per complex product (plus 10 for a square root, 8 for a reciprocal);
+    12 for the final products, 2 for the weight and 4 to accumulate."""
+    d = desc.dim
+    fl = 2.0 * d
+    kind = transform[0]
+    if kind == 1:
+        fl += 15.0 * d + (d - 1)
+    elif kind == 2:
+        fl += 2.0 * d
+    ex = np.asarray(desc.expo).reshape(-1, d)
+    for i, row in enumerate(ex):
+        nnz = int(np.count_nonzero(row))
+        if i >= desc.n_u:
+            fl += 3 * nnz + 2 * nnz * (nnz + 1)
+        fl += 6 * nnz + 4
+    fl += 4.0 * d + 3.0 * d * d + 8.0 * d ** 3 / 3.0
+
+    def pw(p):
+        if p == 0:
+            return 0.0
+        k = int(math.floor(abs(p)))
+        c = 6.0 * (max(0, k.bit_length() - 1) + max(0, bin(k).count("1") - 1))
+        if p != math.floor(p):
+            c += 10.0 + 6.0
+        if p < 0:
+            c += 8.0
+        return c
+
+    fl += pw(desc.pow_u) + (pw(desc.pow_f) if desc.n_f else 0.0)
+    return fl + 12 + 2 + 4
+
+
+def desc_flops(desc, transform) -> float:
+    return flops_per_eval_complex(desc, transform) if desc.deform else flops_per_eval(desc, transform)
+
+
 def cpu_baseline(job, target_seconds: float, threads: int):
     """The oracle, as it stands, on all m shifts of a prefix [0, k) of the same
     lattice; k grows until one run takes at least half the target time."""

@@ -260,10 +260,9 @@ int run_requests(qmc_context* c, const qmc_request* reqs, uint32_t count, qmc_re
       s.z.assign(q.z, q.z + dim);
     } else {
       uint64_t nn = 0;
-      if (next_registered(c, q.n, dim, &nn, true) != QMC_OK)
+      if (next_registered(c, q.n, dim, &nn, true, &s.z) != QMC_OK)
         return fail(QMC_ENOTFOUND, "request %u: no registered lattice with %u components", i, dim);
       s.n = nn;
-      s.z.assign(c->lattices[nn].begin(), c->lattices[nn].begin() + dim);
     }
     s.shifts.resize((size_t)q.m * dim);
     make_shifts(q.seed, q.m, dim, s.shifts.data());
@@ -327,14 +326,15 @@ int run_requests(qmc_context* c, const qmc_request* reqs, uint32_t count, qmc_re
       double want = std::max(1.5 * (double)s.n, goal > 0 && std::isfinite(err) ? (double)s.n * err / goal : 2.0 * s.n);
       uint64_t wantu = want >= 9.0e15 ? (uint64_t)9.0e15 : (uint64_t)std::ceil(want);
       uint64_t nn = 0;
-      if (next_registered(c, wantu, s.f->dim, &nn, false) != QMC_OK ||
+      std::vector<uint64_t> zn;
+      if (next_registered(c, wantu, s.f->dim, &nn, false, &zn) != QMC_OK ||
           (q.max_evals && s.r.evaluations + nn * (uint64_t)m > q.max_evals)) {
         s.r.flags |= QMC_MAXEVAL_HIT;
         s.done = true;
         continue;
       }
       s.n = nn;
-      s.z.assign(c->lattices[nn].begin(), c->lattices[nn].begin() + s.f->dim);
+      s.z.swap(zn);
     }
   }
   const double wall = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

@@ -32,12 +32,14 @@ struct qmc_context {
   double* h_stage = nullptr;
   size_t h_stage_bytes = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  std::map<uint64_t, std::vector<uint64_t>> lattices;
+  std::map<uint64_t, std::vector<uint64_t>> lattices;  // guarded by lat_mu
+  std::mutex lat_mu;                                  // innermost lock
   std::recursive_mutex mu;
   int inflight = 0;
   int live_integrands = 0;  // the context is freed only after its last integrand
-  bool closing = false;     // destroy requested while integrands were alive
-  bool broken = false;
+  std::atomic<bool> closing{false};  // destroy requested while integrands were alive
+  std::atomic<bool> broken{false};
+  std::mutex serve_init;              // creation of the serving scheduler
   int max_blocks = 0;          // 0: from occupancy
   int cus = 256;               // compute units of the device
   int grid_rounds = 1;         // resident-block rounds per launch
@@ -55,7 +57,7 @@ struct qmc_context {
   std::string tune_cache;             // file the autotuner reads and appends
   hipStream_t cap_stream = nullptr;   // private stream used only for graph capture
   // serving
-  qmc_serve_state* serve = nullptr;     // scheduler, created by the first qmc_submit
+  std::atomic<qmc_serve_state*> serve{nullptr};     // scheduler, created by the first qmc_submit
   size_t serve_mem_limit = (size_t)8 << 30;  // device bytes admitted requests may use
   uint64_t serve_max_n = (1ull << 31) - 1;   // growth stops above this lattice size
 };
@@ -92,7 +94,12 @@ int scratch(qmc_context* c, size_t need, char** out);
 int stage(qmc_context* c, size_t bytes);
 void estimate(const double* q, uint32_t m, double& mean, double& err);
 bool goal_met(const qmc_result& r, double rel, double abs_, uint32_t mode, bool cplx);
-int next_registered(qmc_context* c, uint64_t want, uint32_t dim, uint64_t* n_out, bool allow_smaller);
+// Smallest registered lattice with n >= want (or the largest, if allow_smaller)
+// and at least dim components; copies its first dim components into *z_out.
+// Takes the table's own lock, so callers need not hold the context lock.
+int next_registered(qmc_context* c, uint64_t want, uint32_t dim, uint64_t* n_out, bool allow_smaller,
+                    std::vector<uint64_t>* z_out = nullptr);
+uint64_t largest_registered(qmc_context* c);
 // fill the integrand/transform part of an EvalArgs
 int fill_integrand_args(qmcd::EvalArgs& a, const qmc_integrand* f, const qmc_transform& t, int& tsel);
 

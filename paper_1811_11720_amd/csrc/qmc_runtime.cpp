@@ -374,22 +374,28 @@ bool goal_met(const qmc_result& r, double rel, double abs_, uint32_t mode, bool 
   return std::max(r.err_re, r.err_im) <= std::max(abs_, rel * std::max(std::fabs(r.re), std::fabs(r.im)));
 }
 
-int next_registered(qmc_context* c, uint64_t want, uint32_t dim, uint64_t* n_out, bool allow_smaller) {
+uint64_t largest_registered(qmc_context* c) {
+  std::lock_guard<std::mutex> g(c->lat_mu);
+  return c->lattices.empty() ? 0 : c->lattices.rbegin()->first;
+}
+
+int next_registered(qmc_context* c, uint64_t want, uint32_t dim, uint64_t* n_out, bool allow_smaller,
+                    std::vector<uint64_t>* z_out) {
+  std::lock_guard<std::mutex> g(c->lat_mu);
   uint64_t best = 0, largest = 0;
   for (auto& kv : c->lattices) {
     if (kv.second.size() < dim) continue;
     largest = std::max(largest, kv.first);
     if (kv.first >= want && (best == 0 || kv.first < best)) best = kv.first;
   }
-  if (best) {
-    *n_out = best;
-    return QMC_OK;
+  if (!best && allow_smaller) best = largest;
+  if (!best) return QMC_ENOTFOUND;
+  *n_out = best;
+  if (z_out) {
+    const std::vector<uint64_t>& z = c->lattices[best];
+    z_out->assign(z.begin(), z.begin() + dim);
   }
-  if (allow_smaller && largest) {
-    *n_out = largest;
-    return QMC_OK;
-  }
-  return QMC_ENOTFOUND;
+  return QMC_OK;
 }
 
 int integrate_request(qmc_context* c, const qmc_request& q, qmc_result* out, double* shift_sums) {
@@ -409,10 +415,9 @@ int integrate_request(qmc_context* c, const qmc_request& q, qmc_result* out, dou
     z.assign(q.z, q.z + dim);
   } else {
     uint64_t nn = 0;
-    if (next_registered(c, n, dim, &nn, true) != QMC_OK)
+    if (next_registered(c, n, dim, &nn, true, &z) != QMC_OK)
       return fail(QMC_ENOTFOUND, "no registered lattice with %u components", dim);
     n = nn;
-    z.assign(c->lattices[n].begin(), c->lattices[n].begin() + dim);
   }
   std::vector<double> sh((size_t)m * dim);
   make_shifts(q.seed, m, dim, sh.data());
@@ -452,13 +457,14 @@ int integrate_request(qmc_context* c, const qmc_request& q, qmc_result* out, dou
     double want = std::max(1.5 * (double)n, goal > 0 && std::isfinite(err) ? (double)n * err / goal : 2.0 * n);
     uint64_t nn = 0;
     uint64_t wantu = want >= 9.0e15 ? (uint64_t)9.0e15 : (uint64_t)std::ceil(want);
-    if (next_registered(c, wantu, dim, &nn, false) != QMC_OK ||
+    std::vector<uint64_t> zn;
+    if (next_registered(c, wantu, dim, &nn, false, &zn) != QMC_OK ||
         (q.max_evals && r.evaluations + nn * (uint64_t)m > q.max_evals)) {
       r.flags |= QMC_MAXEVAL_HIT;
       break;
     }
     n = nn;
-    z.assign(c->lattices[n].begin(), c->lattices[n].begin() + dim);
+    z.swap(zn);
   }
   r.device_seconds = dev;
   r.path = run.path;
@@ -622,14 +628,13 @@ int qmc_register_lattice(qmc_context* c, uint64_t n, uint32_t dim, const uint64_
   if (dim < 1 || dim > 1024) return fail(QMC_EINVAL, "dim=%u", dim);
   int rc = check_lattice(n, dim, z);
   if (rc) return rc;
-  std::lock_guard<std::recursive_mutex> g(c->mu);
+  std::lock_guard<std::mutex> g(c->lat_mu);
   c->lattices[n] = std::vector<uint64_t>(z, z + dim);
   return QMC_OK;
 }
 
 int qmc_next_lattice(qmc_context* c, uint64_t preferred_n, uint32_t dim, uint64_t* n_out) {
   if (!c || !n_out) return fail(QMC_EINVAL, "NULL argument");
-  std::lock_guard<std::recursive_mutex> g(c->mu);
   if (next_registered(c, preferred_n, dim, n_out, true) != QMC_OK)
     return fail(QMC_ENOTFOUND, "no registered lattice with %u components", dim);
   return QMC_OK;

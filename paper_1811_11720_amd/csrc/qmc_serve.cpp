@@ -81,8 +81,7 @@ static void finish_ticket(qmc_serve_state* s, Ticket& t, int status) {
   s->cv_done.notify_all();
 }
 
-static void scheduler(qmc_context* c) {
-  qmc_serve_state* s = c->serve;
+static void scheduler(qmc_context* c, qmc_serve_state* s) {
   std::unique_lock<std::mutex> lk(s->mu);
   for (;;) {
     // admission: arrival order, while the memory budget allows
@@ -180,14 +179,15 @@ static void scheduler(qmc_context* c) {
       double want = std::max(1.5 * (double)r.n, goal > 0 && std::isfinite(err) ? (double)r.n * err / goal : 2.0 * r.n);
       uint64_t wantu = want >= 9.0e15 ? (uint64_t)9.0e15 : (uint64_t)std::ceil(want);
       uint64_t nn = 0;
-      if (next_registered(c, wantu, r.f->dim, &nn, false) != QMC_OK || nn > c->serve_max_n ||
+      std::vector<uint64_t> zn;
+      if (next_registered(c, wantu, r.f->dim, &nn, false, &zn) != QMC_OK || nn > c->serve_max_n ||
           (r.q.max_evals && r.r.evaluations + nn * (uint64_t)m > r.q.max_evals)) {
         r.r.flags |= QMC_MAXEVAL_HIT;
         r.done = true;
         continue;
       }
       r.n = nn;
-      r.z.assign(c->lattices[nn].begin(), c->lattices[nn].begin() + r.f->dim);
+      r.z.swap(zn);
     }
     for (auto it = s->active.begin(); it != s->active.end();) {
       Ticket& t = **it;
@@ -211,21 +211,23 @@ static void scheduler(qmc_context* c) {
 }
 
 void serve_shutdown(qmc_context* c) {
-  if (!c->serve) return;
+  qmc_serve_state* s = c->serve.load();
+  if (!s) return;
   {
-    std::lock_guard<std::mutex> g(c->serve->mu);
-    c->serve->stop = true;
+    std::lock_guard<std::mutex> g(s->mu);
+    s->stop = true;
   }
-  c->serve->cv_work.notify_all();
-  if (c->serve->thr.joinable()) c->serve->thr.join();
-  delete c->serve;
+  s->cv_work.notify_all();
+  if (s->thr.joinable()) s->thr.join();
+  delete s;
   c->serve = nullptr;
 }
 
 int serve_inflight(qmc_context* c) {
-  if (!c->serve) return 0;
-  std::lock_guard<std::mutex> g(c->serve->mu);
-  return (int)(c->serve->queue.size() + c->serve->active.size());
+  qmc_serve_state* s = c->serve.load();
+  if (!s) return 0;
+  std::lock_guard<std::mutex> g(s->mu);
+  return (int)(s->queue.size() + s->active.size());
 }
 
 }  // namespace qmch
@@ -236,10 +238,12 @@ extern "C" {
 
 int qmc_submit(qmc_context* c, const qmc_request* reqs, uint32_t count, uint64_t* ticket) {
   if (!c || !reqs || !ticket || count == 0) return fail(QMC_EINVAL, "bad arguments");
+  const clk::time_point t_entry = clk::now();
   auto t = std::make_shared<Ticket>();
   t->reqs.resize(count);
   {
-    std::lock_guard<std::recursive_mutex> g(c->mu);
+    // Validation needs only the lattice table's lock: a submission never
+    // waits for a round that is running on the device.
     if (c->closing) return fail(QMC_EINVAL, "context has been destroyed");
     if (c->broken) return fail(QMC_EDEVICE, "context is unusable after a device error");
     for (uint32_t i = 0; i < count; ++i) {
@@ -258,10 +262,9 @@ int qmc_submit(qmc_context* c, const qmc_request* reqs, uint32_t count, uint64_t
         r.z.assign(q.z, q.z + dim);
       } else {
         uint64_t nn = 0;
-        if (next_registered(c, q.n, dim, &nn, true) != QMC_OK)
+        if (next_registered(c, q.n, dim, &nn, true, &r.z) != QMC_OK)
           return fail(QMC_ENOTFOUND, "request %u: no registered lattice with %u components", i, dim);
         r.n = nn;
-        r.z.assign(c->lattices[nn].begin(), c->lattices[nn].begin() + dim);
       }
       r.q.z = nullptr;  // the caller's array may be freed after return
       r.shifts.resize((size_t)q.m * dim);
@@ -270,22 +273,27 @@ int qmc_submit(qmc_context* c, const qmc_request* reqs, uint32_t count, uint64_t
       // memory at the largest lattice the request may reach
       const bool grow = q.rel_tol > 0 || q.abs_tol > 0;
       uint64_t nmax = r.n;
-      if (grow) nmax = std::max<uint64_t>(r.n, std::min<uint64_t>(c->serve_max_n, c->lattices.empty() ? r.n : c->lattices.rbegin()->first));
+      if (grow) {
+        const uint64_t top = largest_registered(c);
+        nmax = std::max<uint64_t>(r.n, std::min<uint64_t>(c->serve_max_n, top ? top : r.n));
+      }
       r.bytes = request_bytes(r.f, nmax, q.m, c);
       t->bytes += r.bytes;
     }
     if (t->bytes > serve_budget(c))
       return fail(QMC_ENOMEM, "ticket needs %zu bytes, the serving budget is %zu", t->bytes, serve_budget(c));
+    std::lock_guard<std::mutex> g(c->serve_init);
     if (!c->serve) {
-      c->serve = new qmc_serve_state();
-      c->serve->thr = std::thread(scheduler, c);
+      qmc_serve_state* s = new qmc_serve_state();
+      s->thr = std::thread(scheduler, c, s);
+      c->serve = s;
     }
   }
   qmc_serve_state* s = c->serve;
   {
     std::lock_guard<std::mutex> g(s->mu);
     t->id = s->next_id++;
-    t->t_submit = clk::now();
+    t->t_submit = t_entry;
     for (auto& r : t->reqs) r.f->refs += 1;
     s->queue.push_back(t);
     s->all[t->id] = t;
@@ -311,15 +319,16 @@ static int collect(qmc_serve_state* s, uint64_t ticket, qmc_result* out) {
 
 int qmc_poll(qmc_context* c, uint64_t ticket, qmc_result* out) {
   if (!c) return fail(QMC_EINVAL, "context is NULL");
-  if (!c->serve) return fail(QMC_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
-  std::lock_guard<std::mutex> g(c->serve->mu);
-  return collect(c->serve, ticket, out);
+  qmc_serve_state* s = c->serve.load();
+  if (!s) return fail(QMC_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
+  std::lock_guard<std::mutex> g(s->mu);
+  return collect(s, ticket, out);
 }
 
 int qmc_wait(qmc_context* c, uint64_t ticket, double timeout_s, qmc_result* out) {
   if (!c) return fail(QMC_EINVAL, "context is NULL");
-  if (!c->serve) return fail(QMC_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
-  qmc_serve_state* s = c->serve;
+  qmc_serve_state* s = c->serve.load();
+  if (!s) return fail(QMC_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
   std::unique_lock<std::mutex> lk(s->mu);
   auto deadline = clk::now() + std::chrono::duration_cast<clk::duration>(std::chrono::duration<double>(
                                    timeout_s < 0 ? 1e9 : timeout_s));
@@ -336,8 +345,8 @@ int qmc_wait(qmc_context* c, uint64_t ticket, double timeout_s, qmc_result* out)
 }
 
 int qmc_cancel(qmc_context* c, uint64_t ticket) {
-  if (!c || !c->serve) return fail(QMC_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
-  qmc_serve_state* s = c->serve;
+  qmc_serve_state* s = c ? c->serve.load() : nullptr;
+  if (!s) return fail(QMC_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
   {
     std::lock_guard<std::mutex> g(s->mu);
     auto it = s->all.find(ticket);
@@ -352,12 +361,12 @@ int qmc_cancel(qmc_context* c, uint64_t ticket) {
 int qmc_serve_stats(qmc_context* c, uint64_t* rounds, uint64_t* queued, uint64_t* active, uint64_t* bytes_in_use) {
   if (!c) return fail(QMC_EINVAL, "context is NULL");
   uint64_t r = 0, q = 0, a = 0, b = 0;
-  if (c->serve) {
-    std::lock_guard<std::mutex> g(c->serve->mu);
-    r = c->serve->rounds;
-    q = c->serve->queue.size();
-    a = c->serve->active.size();
-    b = c->serve->in_use;
+  if (qmc_serve_state* s = c->serve.load()) {
+    std::lock_guard<std::mutex> g(s->mu);
+    r = s->rounds;
+    q = s->queue.size();
+    a = s->active.size();
+    b = s->in_use;
   }
   if (rounds) *rounds = r;
   if (queued) *queued = q;
