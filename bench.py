@@ -16,6 +16,7 @@ bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import copy
 import json
 import math
 import os
@@ -130,6 +131,216 @@ def cpu_baseline(job, target_seconds: float, threads: int):
     }
 
 
+def _batch_requests(ctx, pool, fp32: bool):
+    fs, reqs = [], []
+    for j in pool:
+        d = copy.copy(j.desc)
+        d.fp32 = fp32
+        f = ctx.integrand(d)
+        fs.append(f)
+        reqs.append(dict(f=f, n=j.n, z=j.z, m=j.m, seed=j.seed, transform=j.transform))
+    return fs, reqs
+
+
+def bench_batch(a, Q, W, torch):
+    """Many integrals at once: the mixed real/complex sector workload, fixed n
+    per integral (log-uniform over the lattice table in [n_lo, n_hi]), m=32.
+    Times the fp64 batch, the fp32-evaluation batch and, on a subset, one
+    launch per integral through qmc_integrate."""
+    pool = W.batch_mix(count=a.count, seed=4, n_lo=a.n_lo, n_hi=a.n_hi, m=a.m)
+    evals = sum(j.n * j.m for j in pool)
+    flops = sum(desc_flops(j.desc, j.transform) * j.n * j.m for j in pool)
+    ctx = Q.Context(0)
+    modes = {}
+    results = {}
+    for mode in ("fp64", "fp32"):
+        fs, reqs = _batch_requests(ctx, pool, mode == "fp32")
+        tuned = None
+        if a.autotune:
+            # every tenth request, its lattice capped at ~1e6 points
+            sample = []
+            for r in reqs[::10]:
+                n = W.next_table_n(min(r["n"], 1000000))
+                sample.append(dict(r, n=n, z=W.z_for(n, r["f"].dim)))
+            tuned = ctx.autotune_batch(sample)
+        for _ in range(a.warmup):
+            ctx.integrate_batch(reqs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dev = []
+        for _ in range(a.steps):
+            res = ctx.integrate_batch(reqs)
+            dev.append(res[0]["device_seconds"])
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / a.steps
+        kern = float(np.mean(dev))
+        results[mode] = res
+        modes[mode] = {"evals_per_s": evals / el, "ms_per_step": el * 1e3, "device_ms": kern * 1e3,
+                       "achieved_tflops": flops / kern / 1e12, "autotune_configs": tuned}
+        for f in fs:
+            f.close()
+    # fp32 evaluation error against the fp64 batch, in units of the fp64 error estimate
+    dev_sig = []
+    for r64, r32 in zip(results["fp64"], results["fp32"]):
+        e = max(r64["err_re"], r64["err_im"], 1e-300)
+        dev_sig.append(max(abs(r32["re"] - r64["re"]), abs(r32["im"] - r64["im"])) / e)
+    modes["fp32"]["max_abs_diff_over_sigma64"] = float(np.max(dev_sig))
+    modes["fp32"]["median_abs_diff_over_sigma64"] = float(np.median(dev_sig))
+    # one launch per integral on a subset (grid kernels, run-time specialisation as configured)
+    sub = pool[: a.per_integral]
+    if sub:
+        fs, reqs = _batch_requests(ctx, sub, False)
+        for r in reqs[:2]:
+            ctx.integrate(r["f"], r["n"], r["z"], r["m"], r["seed"], r["transform"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for r in reqs:
+            ctx.integrate(r["f"], r["n"], r["z"], r["m"], r["seed"], r["transform"])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        ev_sub = sum(j.n * j.m for j in sub)
+        modes["fp64_per_integral"] = {"evals_per_s": ev_sub / el, "integrals": len(sub)}
+        for f in fs:
+            f.close()
+    ctx.close()
+    value = modes["fp64"]["evals_per_s"]
+    achieved = modes["fp64"]["achieved_tflops"]
+    n_cplx = sum(1 for j in pool if j.desc.deform)
+    out = {
+        "metric": "lattice-point integrand evals/s (FP64) + p50/p99 request latency at rel err",
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": modes["fp64"]["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"batch of {len(pool)} sector integrands (d 2-10, |F| 4-40, {n_cplx} complex), "
+                        f"n log-uniform over the table in [{a.n_lo:g}, {a.n_hi:g}], m={a.m}, one lattice each",
+            "integrals": len(pool),
+            "evals": evals,
+        },
+        "modes": modes,
+        "roofline": {
+            "bound": "alu",
+            "kernel": "k_batch (all variants of one step, fp64 vector ALU)",
+            "achieved": achieved,
+            "peak": FP64_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+            "traffic": None,
+        },
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_serve(a, Q, W, torch):
+    """Serving: requests of 10-500 integrands from the batch pool, each with a
+    relative target log-uniform in [1e-8, 1e-4], arriving as a Poisson process
+    at fractions of the measured saturation rate.  Latency is submit-to-result
+    as the library reports it (wall_seconds of the ticket)."""
+    import threading
+
+    pool = W.batch_mix(count=2000, seed=4, n_lo=a.n_lo, n_hi=a.n_hi, m=a.m)
+    ctx = Q.Context(0)
+    ctx.register_table(W.lattice_table())
+    fs = [ctx.integrand(j.desc) for j in pool]
+    spec = W.serving_requests(a.requests + 8, seed=5, lo=a.req_lo, hi=a.req_hi, pool=pool)
+
+    def make(members, target):
+        return [dict(f=fs[i], n=pool[i].n, z=None, m=pool[i].m, seed=pool[i].seed, transform=pool[i].transform,
+                     rel_tol=target, max_evals=a.max_evals) for i in members]
+
+    def run(rate, reqs):
+        """Open loop: submit at Poisson times (rate 0: all at once); returns
+        per-request latency, evaluations and the span."""
+        rng = np.random.default_rng(17)
+        tickets = []
+        lat, ev = [], 0
+        done = threading.Event()
+        out = []
+
+        def waiter():
+            k = 0
+            while k < len(reqs):
+                while k >= len(tickets):
+                    time.sleep(1e-4)
+                t, cnt = tickets[k]
+                r = ctx.wait(t, cnt, timeout=600)
+                out.append(r)
+                k += 1
+            done.set()
+
+        th = threading.Thread(target=waiter)
+        th.start()
+        t0 = time.perf_counter()
+        t_next = t0
+        for q in reqs:
+            if rate > 0:
+                t_next += rng.exponential(1.0 / rate)
+                dt = t_next - time.perf_counter()
+                if dt > 0:
+                    time.sleep(dt)
+            tickets.append((ctx.submit(q), len(q)))
+        done.wait()
+        th.join()
+        span = time.perf_counter() - t0
+        for r in out:
+            lat.append(max(x["wall_seconds"] for x in r))
+            ev += sum(x["evaluations"] for x in r)
+        conv = sum(sum(1 for x in r if x["flags"] & 1) for r in out)
+        return np.array(lat), ev, span, conv
+
+    warm = [make(*q) for q in spec[:8]]
+    run(0, warm)
+    reqs = [make(*q) for q in spec[8:]]
+    lat0, ev0, span0, conv0 = run(0, reqs)  # saturation: everything queued at once
+    sat = len(reqs) / span0
+    rates = []
+    for frac in a.rates:
+        lat, ev, span, conv = run(frac * sat, reqs)
+        rates.append({"load": frac, "arrival_rate_per_s": frac * sat, "requests_per_s": len(reqs) / span,
+                      "evals_per_s": ev / span, "p50_ms": float(np.percentile(lat, 50)) * 1e3,
+                      "p99_ms": float(np.percentile(lat, 99)) * 1e3,
+                      "integrals_converged": conv, "integrals": sum(len(q) for q in reqs)})
+    st = ctx.serve_stats()
+    for f in fs:
+        f.close()
+    ctx.close()
+    out = {
+        "metric": "lattice-point integrand evals/s (FP64) + p50/p99 request latency at rel err",
+        "value": ev0 / span0,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": len(reqs),
+        "warmup": len(warm),
+        "ms_per_step": span0 / len(reqs) * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"serving: {len(reqs)} requests of {a.req_lo}-{a.req_hi} sector integrands, "
+                        f"rel targets 1e-8..1e-4, start n in [{a.n_lo:g}, {a.n_hi:g}], m={a.m}, growth through "
+                        f"the lattice table",
+        },
+        "saturation": {"requests_per_s": sat, "evals_per_s": ev0 / span0,
+                       "p50_ms": float(np.percentile(lat0, 50)) * 1e3,
+                       "p99_ms": float(np.percentile(lat0, 99)) * 1e3},
+        "latency_by_load": rates,
+        "serve_rounds": st["rounds"],
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -139,11 +350,21 @@ def main():
     ap.add_argument("--m", type=int, default=32)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--workload", choices=["sector_real", "batch", "serve"], default="sector_real")
+    ap.add_argument("--count", type=int, default=2000, help="batch: integrals")
+    ap.add_argument("--n-lo", type=float, default=1e5)
+    ap.add_argument("--n-hi", type=float, default=1e7)
+    ap.add_argument("--autotune", action="store_true", help="batch: tune the schedules first")
+    ap.add_argument("--per-integral", type=int, default=100, help="batch: integrals timed one launch each")
+    ap.add_argument("--requests", type=int, default=200, help="serve: requests per load level")
+    ap.add_argument("--req-lo", type=int, default=10)
+    ap.add_argument("--req-hi", type=int, default=500)
+    ap.add_argument("--max-evals", type=int, default=10 ** 11)
+    ap.add_argument("--rates", type=float, nargs="*", default=[0.5, 0.9])
     a = ap.parse_args()
     if a.gpus != 1:
-        print(f"bench.py runs on exactly one GPU; --gpus {a.gpus} is not supported "
-              "(the integration shards by shifts across GPUs only by design, not in this build)",
-              file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported (sharding the "
+              "shifts across GPUs is a design, not an implementation)", file=sys.stderr)
         return 2
 
     import torch
@@ -151,6 +372,10 @@ def main():
     import paper_1811_11720_amd as Q
     import workloads as W
 
+    if a.workload == "batch":
+        return bench_batch(a, Q, W, torch)
+    if a.workload == "serve":
+        return bench_serve(a, Q, W, torch)
     job = W.job_sector_real(a.n)
     job.m = a.m
     ctx = Q.Context(0)
