@@ -251,7 +251,8 @@ int qmc_integrate_batch(qmc_context* ctx, const qmc_request* reqs, uint32_t coun
 
 /*
  * Autotune the batch kernels on a sample of requests: for every kernel variant
- * (dimension class, real/complex, fp64/fp32) present in the sample, time each
+ * (dimension class; Korobov r=3, baker or any other transform / VR map;
+ * real/complex; fp64/fp32) present in the sample, time each
  * compiled points-per-decode variant and candidate tile size on one round and
  * keep the fastest for this context (and append it to the file named by the
  * environment variable QMC_TUNE_CACHE, read at context creation).  The

@@ -40,7 +40,8 @@ int run_batch(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_secon
   if (kernel_seconds) *kernel_seconds = 0.0;
   if (J == 0) return QMC_OK;
   struct Plan {
-    int variant;  // dclass * 4 + cplx * 2 + fp32
+    qmck::BatchVariant var;
+    int variant;  // var.index()
     uint32_t rows, ktiles, groups;
     uint64_t tile_points;
     size_t part_off, sh_off, row0;
@@ -54,9 +55,14 @@ int run_batch(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_secon
     const bool cplx = (f->flags & QMC_DEFORM) != 0, fp32 = (f->flags & QMC_EVAL_FP32) != 0;
     Plan& p = plan[i];
     const int dclass = qmck::dim_class(f->dim);
-    p.variant = dclass * 4 + (cplx ? 2 : 0) + (fp32 ? 1 : 0);
+    qmcd::EvalArgs probe;
+    int tsel = 0;
+    int trc = set_transform(probe, b.t, tsel);
+    if (trc) return trc;
+    p.var = qmck::BatchVariant{dclass, qmck::batch_tkc(tsel, f->has_vr), cplx, fp32};
+    p.variant = p.var.index();
     const uint32_t S = cplx ? qmck::S_COMPLEX : qmck::S_REAL;
-    const uint64_t tuned = c->batch_tile[dclass][cplx ? 1 : 0][fp32 ? 1 : 0];
+    const uint64_t tuned = c->batch_tile[p.variant];
     const uint64_t tmin = tuned ? tuned : (cplx ? c->batch_tile_complex : c->batch_tile_real);
     uint64_t tp = std::max<uint64_t>(tmin, (b.n + c->batch_max_ktiles - 1) / c->batch_max_ktiles);
     tp = (tp + QMCD_BLOCK - 1) / QMCD_BLOCK * QMCD_BLOCK;
@@ -143,17 +149,16 @@ int run_batch(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_secon
   uint32_t* order = (uint32_t*)(h + o_order);
   uint32_t* prefix = (uint32_t*)(h + o_prefix);
   struct Launch {
-    int dclass;
-    bool cplx, fp32;
+    qmck::BatchVariant var;
+    int variant;
     uint32_t first, count, prefix_off;
   };
   std::vector<Launch> launches;
   uint32_t pos = 0, ppos = 0;
   for (auto& kv : by_var) {
     Launch L;
-    L.dclass = kv.first / 4;
-    L.cplx = (kv.first & 2) != 0;
-    L.fp32 = (kv.first & 1) != 0;
+    L.var = plan[kv.second.front()].var;
+    L.variant = kv.first;
     L.first = pos;
     L.count = (uint32_t)kv.second.size();
     L.prefix_off = ppos;
@@ -177,10 +182,10 @@ int run_batch(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_secon
     HIPCHK(qmck::launch_fill_u64(d_sign, J, 0ull, st));
     for (uint32_t v = 0; v < (uint32_t)launches.size(); ++v) {
       const Launch& L = launches[v];
-      const int sv = L.cplx ? 0 : c->batch_sv[L.dclass][0][L.fp32 ? 1 : 0];
-      int occ = qmck::occupancy_batch(L.dclass, L.cplx, L.fp32, sv);
+      const int sv = L.var.cplx ? 0 : c->batch_sv[L.variant];
+      int occ = qmck::occupancy_batch(L.var, sv);
       uint32_t blocks = (uint32_t)std::max(1, occ) * (uint32_t)c->cus;
-      HIPCHK(qmck::launch_batch(L.dclass, L.cplx, L.fp32, sv, (const qmcd::EvalArgs*)(ws + o_items),
+      HIPCHK(qmck::launch_batch(L.var, sv, (const qmcd::EvalArgs*)(ws + o_items),
                                 (const uint32_t*)(ws + o_order) + L.first,
                                 (const uint32_t*)(ws + o_prefix) + L.prefix_off, L.count,
                                 (uint32_t*)(ws + o_cnt) + v, blocks, st));
@@ -353,24 +358,33 @@ int run_requests(qmc_context* c, const qmc_request* reqs, uint32_t count, qmc_re
 
 // ---------------------------------------------------------------- autotuning
 
-// Variant key of an integrand: dimension class, complex, fp32.
-static void variant_of(const qmc_integrand* f, int& dc, int& cx, int& f32) {
-  dc = qmck::dim_class(f->dim);
-  cx = (f->flags & QMC_DEFORM) ? 1 : 0;
-  f32 = (f->flags & QMC_EVAL_FP32) ? 1 : 0;
+// Kernel variant of a request (dimension class, transform class, complex, fp32).
+static int variant_of(const qmc_request& q, qmck::BatchVariant& v) {
+  const qmc_integrand* f = q.f;
+  qmcd::EvalArgs probe;
+  int tsel = 0;
+  int rc = set_transform(probe, q.t, tsel);
+  if (rc) return rc;
+  v = qmck::BatchVariant{qmck::dim_class(f->dim), qmck::batch_tkc(tsel, f->has_vr), (f->flags & QMC_DEFORM) != 0,
+                         (f->flags & QMC_EVAL_FP32) != 0};
+  return QMC_OK;
 }
 
+// Cache lines: "gfx950 <dclass> <tkc> <complex> <fp32> <sv index> <tile points>".
 void load_tune_cache(qmc_context* c) {
   if (c->tune_cache.empty()) return;
   FILE* fh = std::fopen(c->tune_cache.c_str(), "r");
   if (!fh) return;
-  int dc, cx, f32, sv;
+  int dc, tkc, cx, f32, sv;
   unsigned long long tile;
   char arch[64];
-  while (std::fscanf(fh, "%63s %d %d %d %d %llu", arch, &dc, &cx, &f32, &sv, &tile) == 6) {
-    if (std::strcmp(arch, "gfx950") != 0 || dc < 0 || dc > 3 || cx < 0 || cx > 1 || f32 < 0 || f32 > 1) continue;
-    if (sv >= 0 && sv < qmck::BATCH_SV_VARIANTS) c->batch_sv[dc][cx][f32] = sv;
-    if (tile >= 256 && tile <= (1ull << 24)) c->batch_tile[dc][cx][f32] = tile;
+  while (std::fscanf(fh, "%63s %d %d %d %d %d %llu", arch, &dc, &tkc, &cx, &f32, &sv, &tile) == 7) {
+    if (std::strcmp(arch, "gfx950") != 0 || dc < 0 || dc > 3 || tkc < 0 || tkc >= qmck::TKC_COUNT || cx < 0 ||
+        cx > 1 || f32 < 0 || f32 > 1)
+      continue;
+    const int v = qmck::BatchVariant{dc, tkc, cx != 0, f32 != 0}.index();
+    if (sv >= 0 && sv < qmck::BATCH_SV_VARIANTS) c->batch_sv[v] = sv;
+    if (tile >= 256 && tile <= (1ull << 24)) c->batch_tile[v] = tile;
   }
   std::fclose(fh);
 }
@@ -379,32 +393,36 @@ void load_tune_cache(qmc_context* c) {
 // (one round, first lattice of each request) and keep the fastest.
 int autotune(qmc_context* c, const qmc_request* reqs, uint32_t count, uint32_t* configs_tried) {
   std::map<int, std::vector<uint32_t>> by_var;
+  std::map<int, qmck::BatchVariant> vars;
   for (uint32_t i = 0; i < count; ++i) {
     if (!reqs[i].f || reqs[i].f->ctx != c) return fail(QMC_EINVAL, "request %u: bad integrand", i);
-    int dc, cx, f32;
-    variant_of(reqs[i].f, dc, cx, f32);
-    by_var[dc * 4 + cx * 2 + f32].push_back(i);
+    qmck::BatchVariant v;
+    int rc = variant_of(reqs[i], v);
+    if (rc) return rc;
+    by_var[v.index()].push_back(i);
+    vars[v.index()] = v;
   }
   uint32_t tried = 0;
   for (auto& kv : by_var) {
-    const int dc = kv.first / 4, cx = (kv.first >> 1) & 1, f32 = kv.first & 1;
+    const qmck::BatchVariant& var = vars[kv.first];
+    const int vi = kv.first;
     std::vector<qmc_request> sub;
     for (uint32_t i : kv.second) {
       qmc_request q = reqs[i];
       q.rel_tol = q.abs_tol = 0.0;  // one lattice
       sub.push_back(q);
     }
-    const std::vector<uint64_t> tiles = cx ? std::vector<uint64_t>{512, 1024, 4096}
-                                           : std::vector<uint64_t>{1024, 4096, 16384};
-    const int nsv = cx ? 1 : qmck::BATCH_SV_VARIANTS;
+    const std::vector<uint64_t> tiles = var.cplx ? std::vector<uint64_t>{512, 1024, 4096}
+                                                 : std::vector<uint64_t>{1024, 4096, 16384};
+    const int nsv = var.cplx ? 1 : qmck::BATCH_SV_VARIANTS;
     double best = 1e300;
     int best_sv = 0;
     uint64_t best_tile = tiles[0];
     for (int sv = 0; sv < nsv; ++sv) {
-      if (!qmck::batch_kernel(dc, cx, f32, sv)) continue;
+      if (!qmck::batch_kernel(var, sv)) continue;
       for (uint64_t tile : tiles) {
-        c->batch_sv[dc][cx][f32] = sv;
-        c->batch_tile[dc][cx][f32] = tile;
+        c->batch_sv[vi] = sv;
+        c->batch_tile[vi] = tile;
         double t_best = 1e300;
         for (int rep = 0; rep < 2; ++rep) {
           std::vector<qmc_result> out(sub.size());
@@ -420,11 +438,12 @@ int autotune(qmc_context* c, const qmc_request* reqs, uint32_t count, uint32_t* 
         }
       }
     }
-    c->batch_sv[dc][cx][f32] = best_sv;
-    c->batch_tile[dc][cx][f32] = best_tile;
+    c->batch_sv[vi] = best_sv;
+    c->batch_tile[vi] = best_tile;
     if (!c->tune_cache.empty()) {
       if (FILE* fh = std::fopen(c->tune_cache.c_str(), "a")) {
-        std::fprintf(fh, "gfx950 %d %d %d %d %llu\n", dc, cx, f32, best_sv, (unsigned long long)best_tile);
+        std::fprintf(fh, "gfx950 %d %d %d %d %d %llu\n", var.dclass, var.tkc, var.cplx ? 1 : 0, var.fp32 ? 1 : 0,
+                     best_sv, (unsigned long long)best_tile);
         std::fclose(fh);
       }
     }

@@ -232,7 +232,20 @@ __device__ __forceinline__ double transform(double u, double& w, const EvalArgs&
 }
 
 // PolySingular map of Sec. 2.4 (App. A.5 form with |p2|, |p3|)
-__device__ __forceinline__ double vr_map(double y, const double* __restrict__ p, double& w) {
+// Tables an evaluation reads (coefficients, exponents, shifts, VR parameters)
+// are the same for the whole wavefront and are never written while a kernel
+// runs.  Reading them through the constant address space lets the compiler
+// use scalar loads even inside loops that also store (the persistent batch
+// kernels); otherwise they would become vector loads whose latency the few
+// resident waves cannot hide.
+template <class T>
+using cptr = const __attribute__((address_space(4))) T*;
+template <class T>
+__device__ __forceinline__ cptr<T> as_const(const T* p) {
+  return (cptr<T>)p;
+}
+
+__device__ __forceinline__ double vr_map(double y, cptr<double> p, double& w) {
   double p0 = p[0], p1 = p[1], p2 = __builtin_fabs(p[2]), p3 = __builtin_fabs(p[3]), p4 = p[4], p5 = p[5];
   double c3 = 1.0 - p2 - p3 - p4 - p5;
   double i0 = 1.0 / (p0 - y), i1 = 1.0 / (p1 - y);
@@ -266,17 +279,19 @@ template <int DMAX, class T>
 __device__ __forceinline__ T poly_eval(const double* __restrict__ coef, const uint32_t* __restrict__ expo,
                                        uint32_t first, uint32_t count, const T (&x)[DMAX],
                                        const T (&x2)[DMAX]) {
+  const cptr<double> C = as_const(coef);
+  const cptr<uint32_t> E = as_const(expo);
   T s = T(0);
   for (uint32_t i = first; i < first + count; ++i) {
-    T t = T(coef[i]);
-    uint32_t w0 = expo[2 * i];
+    T t = T(C[i]);
+    uint32_t w0 = E[2 * i];
 #pragma unroll
     for (int j = 0; j < (DMAX < 8 ? DMAX : 8); ++j) {
       uint32_t e = (w0 >> (4 * j)) & 15u;
       if (e) t *= xpow<T>(x[j], x2[j], e);
     }
     if (DMAX > 8) {
-      uint32_t w1 = expo[2 * i + 1];
+      uint32_t w1 = E[2 * i + 1];
 #pragma unroll
       for (int j = 8; j < DMAX; ++j) {
         uint32_t e = (w1 >> (4 * (j - 8))) & 15u;
@@ -491,10 +506,10 @@ struct GenericComplex {
 #pragma unroll
     for (int j = 0; j < Tri<DMAX>::N; ++j) H[j] = 0.0;
     for (uint32_t i = a.n_u; i < a.n_u + a.n_f; ++i) {
-      const double c = a.coef[i];
+      const double c = as_const(a.coef)[i];
       uint32_t e[DMAX];
 #pragma unroll
-      for (int j = 0; j < DMAX; ++j) e[j] = (a.expo[2 * i + j / 8] >> (4 * (j % 8))) & 15u;
+      for (int j = 0; j < DMAX; ++j) e[j] = (as_const(a.expo)[2 * i + j / 8] >> (4 * (j % 8))) & 15u;
       double P[DMAX], D1[DMAX], D2[DMAX];
 #pragma unroll
       for (int j = 0; j < DMAX; ++j) {
@@ -537,10 +552,10 @@ struct GenericComplex {
                                        const EvalArgs& a) const {
     cplx s = cmk(0.0, 0.0);
     for (uint32_t i = first; i < first + count; ++i) {
-      cplx t = cmk(a.coef[i], 0.0);
+      cplx t = cmk(as_const(a.coef)[i], 0.0);
 #pragma unroll
       for (int j = 0; j < DMAX; ++j) {
-        uint32_t e = (a.expo[2 * i + j / 8] >> (4 * (j % 8))) & 15u;
+        uint32_t e = (as_const(a.expo)[2 * i + j / 8] >> (4 * (j % 8))) & 15u;
         for (uint32_t q = 0; q < e; ++q) t = cmul(t, z[j]);
       }
       s = cmk(s.re + t.re, s.im + t.im);
@@ -591,15 +606,15 @@ __device__ __forceinline__ float poly_eval_f32(const float* __restrict__ coef, c
                                                const float (&x2)[DMAX]) {
   float s = 0.0f;
   for (uint32_t i = first; i < first + count; ++i) {
-    float t = coef[i];
-    uint32_t w0 = expo[2 * i];
+    float t = as_const(coef)[i];
+    uint32_t w0 = as_const(expo)[2 * i];
 #pragma unroll
     for (int j = 0; j < (DMAX < 8 ? DMAX : 8); ++j) {
       uint32_t e = (w0 >> (4 * j)) & 15u;
       if (e) t *= xpow<float>(x[j], x2[j], e);
     }
     if (DMAX > 8) {
-      uint32_t w1 = expo[2 * i + 1];
+      uint32_t w1 = as_const(expo)[2 * i + 1];
 #pragma unroll
       for (int j = 8; j < DMAX; ++j) {
         uint32_t e = (w1 >> (4 * (j - 8))) & 15u;
@@ -688,10 +703,10 @@ struct GenericComplexF32 : GenericComplex<DMAX> {
                                          const EvalArgs& a) const {
     cplxf s = cplxf{0.0f, 0.0f};
     for (uint32_t i = first; i < first + count; ++i) {
-      cplxf t = cplxf{a.coef32[i], 0.0f};
+      cplxf t = cplxf{as_const(a.coef32)[i], 0.0f};
 #pragma unroll
       for (int j = 0; j < DMAX; ++j) {
-        uint32_t e = (a.expo[2 * i + j / 8] >> (4 * (j % 8))) & 15u;
+        uint32_t e = (as_const(a.expo)[2 * i + j / 8] >> (4 * (j % 8))) & 15u;
         for (uint32_t q = 0; q < e; ++q) t = cmulf(t, z[j]);
       }
       s = cplxf{s.re + t.re, s.im + t.im};
@@ -779,7 +794,7 @@ __device__ __forceinline__ void eval_real_sched(const EvalArgs& a, const Fn& fn,
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       if ((uint32_t)s < ns) {
-        const double* __restrict__ D = a.shifts + (size_t)(s0 + s) * dim;
+        const cptr<double> D = as_const(a.shifts) + (size_t)(s0 + s) * dim;
         double x[DMAX];
         double wt = 1.0;  // transform weight (Korobov r=3: prod_j u_j (1-u_j))
         double wv = 1.0;  // VR Jacobian prod_j p'_j
@@ -788,7 +803,7 @@ __device__ __forceinline__ void eval_real_sched(const EvalArgs& a, const Fn& fn,
           if (j < (int)dim) {
             double u = shifted(q[j], D[j]);
             double y = transform<TK>(u, wt, a);
-            if (VRM == VRM_ON || (VRM == VRM_RUNTIME && a.vr)) y = vr_map(y, a.vr + 6 * j, wv);
+            if (VRM == VRM_ON || (VRM == VRM_RUNTIME && a.vr)) y = vr_map(y, as_const(a.vr) + 6 * j, wv);
             x[j] = y;
           } else {
             x[j] = 0.0;
@@ -837,13 +852,13 @@ __device__ __forceinline__ void poly_eval_multi(const C* __restrict__ coef, cons
 #pragma unroll
   for (int v = 0; v < SV; ++v) out[v] = T(0);
   for (uint32_t i = first; i < first + count; ++i) {
-    const T c = (T)coef[i];
+    const T c = (T)as_const(coef)[i];
     T t[SV];
 #pragma unroll
     for (int v = 0; v < SV; ++v) t[v] = c;
 #pragma unroll
     for (int w = 0; w < (DMAX + 7) / 8; ++w) {
-      const uint32_t word = expo[2 * i + w];
+      const uint32_t word = as_const(expo)[2 * i + w];
 #pragma unroll
       for (int jj = 0; jj < 8; ++jj) {
         const int j = 8 * w + jj;
@@ -902,7 +917,7 @@ __device__ __forceinline__ void generic_real_multi(const double (&x)[SV][DMAX], 
 
 // Same contract as eval_real_sched with the table-driven integrand, evaluating
 // the S shifts of the group SV at a time.
-template <int DMAX, int TK, bool IDX32, int S, int SV, bool F32, bool COMP>
+template <int DMAX, int TK, bool IDX32, int S, int SV, bool F32, bool COMP, int VRM = VRM_RUNTIME>
 __device__ __forceinline__ void eval_real_multi_sched(const EvalArgs& a, const Sched& sc) {
   static_assert(S % SV == 0, "shift group must be a multiple of the point group");
   const uint32_t s0 = sc.s0;
@@ -930,14 +945,14 @@ __device__ __forceinline__ void eval_real_multi_sched(const EvalArgs& a, const S
         for (int v = 0; v < SV; ++v) {
           // shifts beyond m reuse the group's first shift; their sums are never stored
           const uint32_t s = ((uint32_t)(g * SV + v) < ns) ? (uint32_t)(g * SV + v) : 0u;
-          const double* __restrict__ D = a.shifts + (size_t)(s0 + s) * dim;
+          const cptr<double> D = as_const(a.shifts) + (size_t)(s0 + s) * dim;
           double wt = 1.0, wv = 1.0;
 #pragma unroll
           for (int j = 0; j < DMAX; ++j) {
             if (j < (int)dim) {
               double u = shifted(q[j], D[j]);
               double y = transform<TK>(u, wt, a);
-              if (a.vr) y = vr_map(y, a.vr + 6 * j, wv);
+              if (VRM == VRM_ON || (VRM == VRM_RUNTIME && a.vr)) y = vr_map(y, as_const(a.vr) + 6 * j, wv);
               x[v][j] = y;
             } else {
               x[v][j] = 0.0;
@@ -1000,7 +1015,7 @@ __device__ __forceinline__ void eval_complex_sched(const EvalArgs& a, const Fn& 
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       if ((uint32_t)s < ns) {
-        const double* __restrict__ D = a.shifts + (size_t)(s0 + s) * dim;
+        const cptr<double> D = as_const(a.shifts) + (size_t)(s0 + s) * dim;
         double x[DMAX];
         double wt = 1.0, wv = 1.0;
 #pragma unroll
@@ -1008,7 +1023,7 @@ __device__ __forceinline__ void eval_complex_sched(const EvalArgs& a, const Fn& 
           if (j < (int)dim) {
             double u = shifted(q[j], D[j]);
             double y = transform<TK>(u, wt, a);
-            if (VRM == VRM_ON || (VRM == VRM_RUNTIME && a.vr)) y = vr_map(y, a.vr + 6 * j, wv);
+            if (VRM == VRM_ON || (VRM == VRM_RUNTIME && a.vr)) y = vr_map(y, as_const(a.vr) + 6 * j, wv);
             x[j] = y;
           } else {
             x[j] = 0.0;
@@ -1075,7 +1090,7 @@ struct HistArgs {
 template <int DMAX, bool CPLX, int PASS>
 __device__ __forceinline__ void hist_body(const EvalArgs& a, const HistArgs& h) {
   const uint32_t dim = a.dim;
-  const double* __restrict__ D = a.shifts;
+  const cptr<double> D = as_const(a.shifts);
   double mx = 0.0;
   for (uint64_t k = a.k_begin + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < a.k_end; k += a.stride) {
     double x[DMAX];

@@ -52,8 +52,8 @@ struct qmc_context {
   uint64_t batch_max_ktiles = 2048;   // tiles along k per integral at most
   bool batch_graph = true;            // replay each round's launches as a HIP graph
   // per kernel variant [dimension class][complex][fp32]: tuned schedule (0 = default)
-  int batch_sv[4][2][2] = {};          // index into the compiled points-per-decode variants
-  uint64_t batch_tile[4][2][2] = {};   // minimum points per tile
+  int batch_sv[qmck::BATCH_VARIANTS] = {};         // index into the compiled points-per-decode variants
+  uint64_t batch_tile[qmck::BATCH_VARIANTS] = {};  // minimum points per tile (0 = the default)
   std::string tune_cache;             // file the autotuner reads and appends
   hipStream_t cap_stream = nullptr;   // private stream used only for graph capture
   // serving

@@ -44,12 +44,27 @@ hipError_t launch_indices(uint64_t n, uint32_t dim, const uint64_t* z_host, uint
 
 // ---------------------------------------------------------------- batches
 using BatchFn = void (*)(const qmcd::EvalArgs*, const uint32_t*, const uint32_t*, uint32_t, uint32_t*);
-// [dclass][complex][fp32][sv]; complex entries exist for classes up to 12 variables and sv index 0.
-// sv index i selects 2^i points per decoded monomial (real kernels).
+// Transform class of a batch kernel.  The two common cases get kernels with
+// the transform fixed and the VR map compiled out (a far smaller loop body);
+// every other item (general Korobov, none, or a VR map) runs in the kernel
+// that selects the transform and the map per item.
+enum { TKC_KOROBOV3 = 0, TKC_BAKER = 1, TKC_ANY = 2, TKC_COUNT = 3 };
+struct BatchVariant {
+  int dclass, tkc;
+  bool cplx, fp32;
+  int index() const { return ((dclass * TKC_COUNT + tkc) * 2 + (cplx ? 1 : 0)) * 2 + (fp32 ? 1 : 0); }
+};
+constexpr int BATCH_VARIANTS = 4 * TKC_COUNT * 2 * 2;
+inline int batch_tkc(int tsel, bool has_vr) {
+  if (has_vr) return TKC_ANY;
+  return tsel == TSEL_KOROBOV3 ? TKC_KOROBOV3 : tsel == TSEL_BAKER ? TKC_BAKER : TKC_ANY;
+}
+// Real kernels come with sv index i = 0, 1, 2 (2^i points per decoded
+// monomial); complex kernels exist for classes up to 12 variables, sv index 0.
 constexpr int BATCH_SV_VARIANTS = 3;
-BatchFn batch_kernel(int dclass, bool cplx, bool fp32, int sv);
-int occupancy_batch(int dclass, bool cplx, bool fp32, int sv);
-hipError_t launch_batch(int dclass, bool cplx, bool fp32, int sv, const qmcd::EvalArgs* items, const uint32_t* order,
+BatchFn batch_kernel(const BatchVariant& v, int sv);
+int occupancy_batch(const BatchVariant& v, int sv);
+hipError_t launch_batch(const BatchVariant& v, int sv, const qmcd::EvalArgs* items, const uint32_t* order,
                         const uint32_t* prefix, uint32_t nitems, uint32_t* counter, uint32_t blocks, hipStream_t st);
 
 // Sums rows of per-item partial arrays in a fixed order: out[r] = sum_c rows[r].p[c].

@@ -126,24 +126,26 @@ hipError_t launch_finalize_rows(const RowRef* rows, uint32_t nrows, double* out,
   return hipLaunchKernel((const void*)k_finalize_rows, dim3(nrows), dim3(QMCD_BLOCK), args, 0, st);
 }
 
-extern BatchFn g_batch4[2][2][3], g_batch8[2][2][3], g_batch12[2][2][3], g_batch16[2][2][3];
+extern BatchFn g_batch4[TKC_COUNT][2][2][3], g_batch8[TKC_COUNT][2][2][3], g_batch12[TKC_COUNT][2][2][3],
+    g_batch16[TKC_COUNT][2][2][3];
 
-BatchFn batch_kernel(int dclass, bool cplx, bool fp32, int sv) {
-  if (sv < 0 || sv >= BATCH_SV_VARIANTS) return nullptr;
-  BatchFn(*t)[2][3] = dclass == 0 ? g_batch4 : dclass == 1 ? g_batch8 : dclass == 2 ? g_batch12 : g_batch16;
-  return t[cplx ? 1 : 0][fp32 ? 1 : 0][sv];
+BatchFn batch_kernel(const BatchVariant& v, int sv) {
+  if (sv < 0 || sv >= BATCH_SV_VARIANTS || v.tkc < 0 || v.tkc >= TKC_COUNT || v.dclass < 0 || v.dclass > 3)
+    return nullptr;
+  BatchFn(*t)[2][2][3] = v.dclass == 0 ? g_batch4 : v.dclass == 1 ? g_batch8 : v.dclass == 2 ? g_batch12 : g_batch16;
+  return t[v.tkc][v.cplx ? 1 : 0][v.fp32 ? 1 : 0][sv];
 }
 
-int occupancy_batch(int dclass, bool cplx, bool fp32, int sv) {
-  BatchFn fn = batch_kernel(dclass, cplx, fp32, sv);
+int occupancy_batch(const BatchVariant& v, int sv) {
+  BatchFn fn = batch_kernel(v, sv);
   int occ = 0;
   if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)fn, QMCD_BLOCK, 0) != hipSuccess) return 0;
   return occ;
 }
 
-hipError_t launch_batch(int dclass, bool cplx, bool fp32, int sv, const qmcd::EvalArgs* items, const uint32_t* order,
+hipError_t launch_batch(const BatchVariant& v, int sv, const qmcd::EvalArgs* items, const uint32_t* order,
                         const uint32_t* prefix, uint32_t nitems, uint32_t* counter, uint32_t blocks, hipStream_t st) {
-  BatchFn fn = batch_kernel(dclass, cplx, fp32, sv);
+  BatchFn fn = batch_kernel(v, sv);
   if (!fn) return hipErrorInvalidValue;
   void* args[] = {(void*)&items, (void*)&order, (void*)&prefix, (void*)&nitems, (void*)&counter};
   return hipLaunchKernel((const void*)fn, dim3(blocks), dim3(QMCD_BLOCK), args, 0, st);

@@ -585,13 +585,15 @@ int qmc_context_create(int device, void* hip_stream, void* workspace, size_t wor
   }
   if (const char* v = std::getenv("QMC_BATCH_GRAPH")) c->batch_graph = atoi(v) != 0;
   if (const char* v = std::getenv("QMC_SERVE_MEM")) c->serve_mem_limit = (size_t)strtoull(v, nullptr, 10);
+  int force_sv = -1;
+  if (const char* v = std::getenv("QMC_BATCH_SV")) force_sv = atoi(v);  // one points-per-decode variant for all
   for (int dc = 0; dc < 4; ++dc)
-    for (int f32 = 0; f32 < 2; ++f32) c->batch_sv[dc][0][f32] = qmck::sv_real(qmck::dim_class_max(dc), f32) == 2 ? 1 : 0;
-  if (const char* v = std::getenv("QMC_BATCH_SV")) {  // force one points-per-decode variant
-    const int sv = atoi(v);
-    if (sv >= 0 && sv < qmck::BATCH_SV_VARIANTS)
-      for (int dc = 0; dc < 4; ++dc) c->batch_sv[dc][0][0] = c->batch_sv[dc][0][1] = sv;
-  }
+    for (int tkc = 0; tkc < qmck::TKC_COUNT; ++tkc)
+      for (int f32 = 0; f32 < 2; ++f32) {
+        const int v = qmck::BatchVariant{dc, tkc, false, f32 != 0}.index();
+        c->batch_sv[v] = qmck::sv_real(qmck::dim_class_max(dc), f32) == 2 ? 1 : 0;
+        if (force_sv >= 0 && force_sv < qmck::BATCH_SV_VARIANTS) c->batch_sv[v] = force_sv;
+      }
   if (const char* v = std::getenv("QMC_TUNE_CACHE")) {
     c->tune_cache = v;
     load_tune_cache(c);
