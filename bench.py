@@ -425,7 +425,8 @@ def main():
         "result": {"estimate": res["re"], "err": res["err_re"], "rel_err": res["err_re"] / abs(res["re"])},
         "roofline": {
             "bound": "alu",
-            "kernel": "k_eval_real (fp64 vector ALU)",
+            "kernel": ("qmc_jit_eval32 (run-time specialised)" if res["path"] == 1 else "k_eval_real (generic)")
+                      + ", fp64 vector ALU",
             "achieved": achieved,
             "peak": FP64_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s",
