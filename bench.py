@@ -174,6 +174,7 @@ def bench_batch(a, Q, W, torch):
         torch.cuda.synchronize()
         el = (time.perf_counter() - t0) / a.steps
         kern = float(np.mean(dev))
+        print(f"[batch] {mode}: {el * 1e3:.1f} ms per step, {evals / el:.3e} evals/s", file=sys.stderr, flush=True)
         results[mode] = res
         modes[mode] = {"evals_per_s": evals / el, "ms_per_step": el * 1e3, "device_ms": kern * 1e3,
                        "achieved_tflops": flops / kern / 1e12, "autotune_configs": tuned}
@@ -199,6 +200,7 @@ def bench_batch(a, Q, W, torch):
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         ev_sub = sum(j.n * j.m for j in sub)
+        print(f"[batch] one launch per integral: {ev_sub / el:.3e} evals/s", file=sys.stderr, flush=True)
         modes["fp64_per_integral"] = {"evals_per_s": ev_sub / el, "integrals": len(sub)}
         for f in fs:
             f.close()
@@ -302,9 +304,12 @@ def bench_serve(a, Q, W, torch):
     reqs = [make(*q) for q in spec[8:]]
     lat0, ev0, span0, conv0 = run(0, reqs)  # saturation: everything queued at once
     sat = len(reqs) / span0
+    print(f"[serve] saturation {sat:.2f} requests/s, {ev0 / span0:.3e} evals/s", file=sys.stderr, flush=True)
     rates = []
     for frac in a.rates:
         lat, ev, span, conv = run(frac * sat, reqs)
+        print(f"[serve] load {frac}: p50 {np.percentile(lat, 50) * 1e3:.1f} ms, p99 {np.percentile(lat, 99) * 1e3:.1f} ms",
+              file=sys.stderr, flush=True)
         rates.append({"load": frac, "arrival_rate_per_s": frac * sat, "requests_per_s": len(reqs) / span,
                       "evals_per_s": ev / span, "p50_ms": float(np.percentile(lat, 50)) * 1e3,
                       "p99_ms": float(np.percentile(lat, 99)) * 1e3,
@@ -359,7 +364,7 @@ def main():
     ap.add_argument("--requests", type=int, default=200, help="serve: requests per load level")
     ap.add_argument("--req-lo", type=int, default=10)
     ap.add_argument("--req-hi", type=int, default=500)
-    ap.add_argument("--max-evals", type=int, default=10 ** 11)
+    ap.add_argument("--max-evals", type=int, default=10 ** 9, help="serve: evaluations per integral")
     ap.add_argument("--rates", type=float, nargs="*", default=[0.5, 0.9])
     a = ap.parse_args()
     if a.gpus != 1:
