@@ -245,6 +245,34 @@ __device__ __forceinline__ cptr<T> as_const(const T* p) {
   return (cptr<T>)p;
 }
 
+// Visits the entries [first, first+count) of a monomial table (coefficient,
+// two packed exponent words per entry) in order.  Entries are fetched four at
+// a time: scalar loads can complete out of order, so every wait on one waits
+// on all, and grouping them pays the load latency once per four entries
+// instead of once per entry.
+template <class Cf, class Body>
+__device__ __forceinline__ void for_each_mono(const Cf* coef, const uint32_t* expo, uint32_t first, uint32_t count,
+                                              Body&& body) {
+  const cptr<Cf> c = as_const(coef) + first;
+  const cptr<uint32_t> e = as_const(expo) + 2 * (size_t)first;
+  uint32_t i = 0;
+  for (; i + 4 <= count; i += 4) {
+    Cf cc[4];
+    uint32_t w[8];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) cc[q] = c[i + q];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) w[q] = e[2 * i + q];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) body(cc[q], w[2 * q], w[2 * q + 1]);
+  }
+  for (; i < count; ++i) body(c[i], e[2 * i], e[2 * i + 1]);
+}
+// exponent of variable j in an entry's packed words
+__device__ __forceinline__ uint32_t mono_exp(uint32_t w0, uint32_t w1, int j) {
+  return ((j < 8 ? w0 : w1) >> (4 * (j & 7))) & 15u;
+}
+
 __device__ __forceinline__ double vr_map(double y, cptr<double> p, double& w) {
   double p0 = p[0], p1 = p[1], p2 = __builtin_fabs(p[2]), p3 = __builtin_fabs(p[3]), p4 = p[4], p5 = p[5];
   double c3 = 1.0 - p2 - p3 - p4 - p5;
@@ -279,19 +307,15 @@ template <int DMAX, class T>
 __device__ __forceinline__ T poly_eval(const double* __restrict__ coef, const uint32_t* __restrict__ expo,
                                        uint32_t first, uint32_t count, const T (&x)[DMAX],
                                        const T (&x2)[DMAX]) {
-  const cptr<double> C = as_const(coef);
-  const cptr<uint32_t> E = as_const(expo);
   T s = T(0);
-  for (uint32_t i = first; i < first + count; ++i) {
-    T t = T(C[i]);
-    uint32_t w0 = E[2 * i];
+  for_each_mono(coef, expo, first, count, [&](double ci, uint32_t w0, uint32_t w1) {
+    T t = T(ci);
 #pragma unroll
     for (int j = 0; j < (DMAX < 8 ? DMAX : 8); ++j) {
       uint32_t e = (w0 >> (4 * j)) & 15u;
       if (e) t *= xpow<T>(x[j], x2[j], e);
     }
     if (DMAX > 8) {
-      uint32_t w1 = E[2 * i + 1];
 #pragma unroll
       for (int j = 8; j < DMAX; ++j) {
         uint32_t e = (w1 >> (4 * (j - 8))) & 15u;
@@ -299,7 +323,7 @@ __device__ __forceinline__ T poly_eval(const double* __restrict__ coef, const ui
       }
     }
     s += t;
-  }
+  });
   return s;
 }
 
@@ -505,11 +529,14 @@ struct GenericComplex {
     for (int j = 0; j < DMAX; ++j) g[j] = 0.0;
 #pragma unroll
     for (int j = 0; j < Tri<DMAX>::N; ++j) H[j] = 0.0;
+    const cptr<double> C = as_const(a.coef);
+    const cptr<uint32_t> E = as_const(a.expo);
     for (uint32_t i = a.n_u; i < a.n_u + a.n_f; ++i) {
-      const double c = as_const(a.coef)[i];
+      const double c = C[i];
+      const uint32_t w0 = E[2 * i], w1 = E[2 * i + 1];
       uint32_t e[DMAX];
 #pragma unroll
-      for (int j = 0; j < DMAX; ++j) e[j] = (as_const(a.expo)[2 * i + j / 8] >> (4 * (j % 8))) & 15u;
+      for (int j = 0; j < DMAX; ++j) e[j] = mono_exp(w0, w1, j);
       double P[DMAX], D1[DMAX], D2[DMAX];
 #pragma unroll
       for (int j = 0; j < DMAX; ++j) {
@@ -551,11 +578,14 @@ struct GenericComplex {
   __device__ __forceinline__ cplx poly(const cplx (&z)[DMAX], uint32_t first, uint32_t count,
                                        const EvalArgs& a) const {
     cplx s = cmk(0.0, 0.0);
+    const cptr<double> C = as_const(a.coef);
+    const cptr<uint32_t> E = as_const(a.expo);
     for (uint32_t i = first; i < first + count; ++i) {
-      cplx t = cmk(as_const(a.coef)[i], 0.0);
+      const uint32_t w0 = E[2 * i], w1 = E[2 * i + 1];
+      cplx t = cmk(C[i], 0.0);
 #pragma unroll
       for (int j = 0; j < DMAX; ++j) {
-        uint32_t e = (as_const(a.expo)[2 * i + j / 8] >> (4 * (j % 8))) & 15u;
+        uint32_t e = mono_exp(w0, w1, j);
         for (uint32_t q = 0; q < e; ++q) t = cmul(t, z[j]);
       }
       s = cmk(s.re + t.re, s.im + t.im);
@@ -605,16 +635,13 @@ __device__ __forceinline__ float poly_eval_f32(const float* __restrict__ coef, c
                                                uint32_t first, uint32_t count, const float (&x)[DMAX],
                                                const float (&x2)[DMAX]) {
   float s = 0.0f;
-  for (uint32_t i = first; i < first + count; ++i) {
-    float t = as_const(coef)[i];
-    uint32_t w0 = as_const(expo)[2 * i];
+  for_each_mono(coef, expo, first, count, [&](float t, uint32_t w0, uint32_t w1) {
 #pragma unroll
     for (int j = 0; j < (DMAX < 8 ? DMAX : 8); ++j) {
       uint32_t e = (w0 >> (4 * j)) & 15u;
       if (e) t *= xpow<float>(x[j], x2[j], e);
     }
     if (DMAX > 8) {
-      uint32_t w1 = as_const(expo)[2 * i + 1];
 #pragma unroll
       for (int j = 8; j < DMAX; ++j) {
         uint32_t e = (w1 >> (4 * (j - 8))) & 15u;
@@ -622,7 +649,7 @@ __device__ __forceinline__ float poly_eval_f32(const float* __restrict__ coef, c
       }
     }
     s += t;
-  }
+  });
   return s;
 }
 
@@ -702,11 +729,14 @@ struct GenericComplexF32 : GenericComplex<DMAX> {
   __device__ __forceinline__ cplxf polyf(const cplxf (&z)[DMAX], uint32_t first, uint32_t count,
                                          const EvalArgs& a) const {
     cplxf s = cplxf{0.0f, 0.0f};
+    const cptr<float> C = as_const(a.coef32);
+    const cptr<uint32_t> E = as_const(a.expo);
     for (uint32_t i = first; i < first + count; ++i) {
-      cplxf t = cplxf{as_const(a.coef32)[i], 0.0f};
+      const uint32_t w0 = E[2 * i], w1 = E[2 * i + 1];
+      cplxf t = cplxf{C[i], 0.0f};
 #pragma unroll
       for (int j = 0; j < DMAX; ++j) {
-        uint32_t e = (as_const(a.expo)[2 * i + j / 8] >> (4 * (j % 8))) & 15u;
+        uint32_t e = mono_exp(w0, w1, j);
         for (uint32_t q = 0; q < e; ++q) t = cmulf(t, z[j]);
       }
       s = cplxf{s.re + t.re, s.im + t.im};
@@ -851,14 +881,14 @@ __device__ __forceinline__ void poly_eval_multi(const C* __restrict__ coef, cons
                                                 T (&out)[SV]) {
 #pragma unroll
   for (int v = 0; v < SV; ++v) out[v] = T(0);
-  for (uint32_t i = first; i < first + count; ++i) {
-    const T c = (T)as_const(coef)[i];
+  for_each_mono(coef, expo, first, count, [&](C ci, uint32_t w0, uint32_t w1) {
+    const T c = (T)ci;
     T t[SV];
 #pragma unroll
     for (int v = 0; v < SV; ++v) t[v] = c;
 #pragma unroll
     for (int w = 0; w < (DMAX + 7) / 8; ++w) {
-      const uint32_t word = as_const(expo)[2 * i + w];
+      const uint32_t word = w == 0 ? w0 : w1;
 #pragma unroll
       for (int jj = 0; jj < 8; ++jj) {
         const int j = 8 * w + jj;
@@ -879,7 +909,7 @@ __device__ __forceinline__ void poly_eval_multi(const C* __restrict__ coef, cons
     }
 #pragma unroll
     for (int v = 0; v < SV; ++v) out[v] += t[v];
-  }
+  });
 }
 
 // prefactor * U^pow_u * F^pow_f at SV points, fp64 (F32 = false) or fp32 polynomials and powers
