@@ -293,6 +293,8 @@ def bench_serve(a, Q, W, torch):
                 r = ctx.wait(t, cnt, timeout=600)
                 out.append(r)
                 k += 1
+                if k % 10 == 0:
+                    print(f"[serve] {k}/{len(reqs)} requests done", file=sys.stderr, flush=True)
             done.set()
 
         th = threading.Thread(target=waiter)
