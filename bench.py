@@ -131,6 +131,53 @@ def cpu_baseline(job, target_seconds: float, threads: int):
     }
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_qmc_jit_eval32_sector_real_n100000007_m32.json")
+KERNEL_SOURCES = ["paper_1811_11720_amd/csrc/qmc_device.h", "paper_1811_11720_amd/csrc/qmc_jit.cpp"]
+
+
+def kernel_source_hash() -> str:
+    """Hash of the sources that generate the specialised evaluation kernel."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(n: int, m: int):
+    """HBM bytes per launch of the specialised kernel from the committed
+    FETCH_SIZE / WRITE_SIZE counter runs (each scaled by what the counter
+    reads for a plain copy of known size), or None when the counters were
+    taken on another workload or on kernel sources that have changed since."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except OSError:
+        return None
+    if t.get("source_hash") != kernel_source_hash() or t.get("n") != n or t.get("m") != m:
+        return None
+    return t["fetch_kib"] * 1024 * t["fetch_scale"] + t["write_kib"] * 1024 * t["write_scale"]
+
+
+def bench_copy(a, torch):
+    """A plain device copy of known size: the reference for scaling the
+    FETCH_SIZE / WRITE_SIZE counters."""
+    nbytes = 1 << 30
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").uniform_()
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / 3
+    print(json.dumps({"workload": "copy", "bytes_read_per_copy": nbytes, "bytes_written_per_copy": nbytes,
+                      "copies": 3, "GB_per_s": 2 * nbytes / el / 1e9}), flush=True)
+    return 0
+
+
 def _batch_requests(ctx, pool, fp32: bool):
     fs, reqs = [], []
     for j in pool:
@@ -373,7 +420,7 @@ def main():
     ap.add_argument("--m", type=int, default=32)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--workload", choices=["sector_real", "batch", "serve"], default="sector_real")
+    ap.add_argument("--workload", choices=["sector_real", "batch", "serve", "copy"], default="sector_real")
     ap.add_argument("--count", type=int, default=2000, help="batch: integrals")
     ap.add_argument("--n-lo", type=float, default=1e5)
     ap.add_argument("--n-hi", type=float, default=1e7)
@@ -399,6 +446,8 @@ def main():
         return bench_batch(a, Q, W, torch)
     if a.workload == "serve":
         return bench_serve(a, Q, W, torch)
+    if a.workload == "copy":
+        return bench_copy(a, torch)
     job = W.job_sector_real(a.n)
     job.m = a.m
     ctx = Q.Context(0)
@@ -454,7 +503,7 @@ def main():
             "peak": FP64_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": measured_traffic(job.n, job.m) if res["path"] == 1 else None,
             "kernel_ms": kern * 1e3,
             "evals_per_s_kernel": evals / kern,
         },

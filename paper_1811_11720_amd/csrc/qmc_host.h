@@ -48,7 +48,7 @@ struct qmc_context {
   int jit_S = 8;
   // batch executor
   uint64_t batch_tile_real = 4096;    // minimum points per tile (real integrands)
-  uint64_t batch_tile_complex = 1024;  // ... (complex integrands)
+  uint64_t batch_tile_complex = 4096;  // ... (complex integrands)
   uint64_t batch_max_ktiles = 2048;   // tiles along k per integral at most
   bool batch_graph = true;            // replay each round's launches as a HIP graph
   // per kernel variant [dimension class][complex][fp32]: tuned schedule (0 = default)

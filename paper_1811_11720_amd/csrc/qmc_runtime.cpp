@@ -591,7 +591,9 @@ int qmc_context_create(int device, void* hip_stream, void* workspace, size_t wor
     for (int tkc = 0; tkc < qmck::TKC_COUNT; ++tkc)
       for (int f32 = 0; f32 < 2; ++f32) {
         const int v = qmck::BatchVariant{dc, tkc, false, f32 != 0}.index();
-        c->batch_sv[v] = qmck::sv_real(qmck::dim_class_max(dc), f32) == 2 ? 1 : 0;
+        // measured on MI355X: fp64 variants are fastest at 4 points per decode
+        // (despite some spilling), fp32 ones at 2
+        c->batch_sv[v] = f32 ? 1 : 2;
         if (force_sv >= 0 && force_sv < qmck::BATCH_SV_VARIANTS) c->batch_sv[v] = force_sv;
       }
   if (const char* v = std::getenv("QMC_TUNE_CACHE")) {
