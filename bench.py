@@ -195,6 +195,8 @@ def bench_batch(a, Q, W, torch):
     Times the fp64 batch, the fp32-evaluation batch and, on a subset, one
     launch per integral through qmc_integrate."""
     pool = W.batch_mix(count=a.count, seed=4, n_lo=a.n_lo, n_hi=a.n_hi, m=a.m)
+    if a.kind != "all":
+        pool = [j for j in pool if j.desc.deform == (a.kind == "complex")]
     evals = sum(j.n * j.m for j in pool)
     flops = sum(desc_flops(j.desc, j.transform) * j.n * j.m for j in pool)
     ctx = Q.Context(0)
@@ -425,6 +427,7 @@ def main():
     ap.add_argument("--n-lo", type=float, default=1e5)
     ap.add_argument("--n-hi", type=float, default=1e7)
     ap.add_argument("--autotune", action="store_true", help="batch: tune the schedules first")
+    ap.add_argument("--kind", choices=["all", "real", "complex"], default="all", help="batch: integrands kept")
     ap.add_argument("--per-integral", type=int, default=100, help="batch: integrals timed one launch each")
     ap.add_argument("--requests", type=int, default=200, help="serve: requests per load level")
     ap.add_argument("--req-lo", type=int, default=10)
