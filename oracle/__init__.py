@@ -27,7 +27,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-T_NONE, T_KOROBOV, T_BAKER = 0, 1, 2
+T_NONE, T_KOROBOV, T_BAKER, T_SIDI = 0, 1, 2, 3
 
 
 def build(force: bool = True) -> str:
@@ -77,6 +77,9 @@ def lib():
             getattr(L, f).restype = C.c_double
         L.oracle_baker_phi.argtypes = [C.c_double]
         L.oracle_baker_phi.restype = C.c_double
+        for f in ("oracle_sidi_omega", "oracle_sidi_phi"):
+            getattr(L, f).argtypes = [C.c_double, C.c_int]
+            getattr(L, f).restype = C.c_double
         L.oracle_vr_map.argtypes = [dp, C.c_double, dp, dp]
         L.oracle_eval_point.argtypes = [C.POINTER(_Desc), dp, dp, dp]
         L.oracle_eval_point.restype = C.c_int
@@ -147,6 +150,15 @@ def korobov_omega(u, r0=3, r1=3):
 
 def baker_phi(u):
     return lib().oracle_baker_phi(float(u))
+
+
+def sidi_phi(u, r):
+    """Sidi map (eq. sidi), integrated numerically from its weight."""
+    return lib().oracle_sidi_phi(float(u), int(r))
+
+
+def sidi_omega(u, r):
+    return lib().oracle_sidi_omega(float(u), int(r))
 
 
 def vr_map(a, y):

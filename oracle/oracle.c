@@ -40,7 +40,7 @@
 
 #define OR_MAX_DIM 32
 
-enum { OR_T_NONE = 0, OR_T_KOROBOV = 1, OR_T_BAKER = 2 };
+enum { OR_T_NONE = 0, OR_T_KOROBOV = 1, OR_T_BAKER = 2, OR_T_SIDI = 3 };
 
 typedef struct {
   uint32_t dim;
@@ -135,6 +135,57 @@ double oracle_korobov_phi(double u, int r0, int r1) {
 
 /* eq. (baker): phi(u) = 2u for u <= 1/2, 2 - 2u otherwise; weight 1 */
 double oracle_baker_phi(double u) { return u <= 0.5 ? 2.0 * u : 2.0 - 2.0 * u; }
+
+/* eq. (sidi): omega_r(u) = c_r sin(pi u)^r, normalised by
+ * c_r = pi 2^-r Gamma(r+1) / Gamma((r+1)/2)^2 */
+double oracle_sidi_omega(double u, int r) {
+  double g = tgamma(0.5 * (r + 1.0));
+  double c = M_PI * pow(2.0, -r) * tgamma(r + 1.0) / (g * g);
+  return c * pow(sin(M_PI * u), r);
+}
+
+/* Gauss-Legendre nodes and weights on [-1, 1] (Newton on P_N) */
+#define OR_GL_N 32
+static double gl_x[OR_GL_N], gl_w[OR_GL_N];
+static int gl_ready = 0;
+static void gl_init(void) {
+  if (gl_ready) return;
+  for (int i = 0; i < OR_GL_N; ++i) {
+    double x = cos(M_PI * (i + 0.75) / (OR_GL_N + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = x;
+      for (int k = 2; k <= OR_GL_N; ++k) {
+        double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = OR_GL_N * (x * p1 - p0) / (x * x - 1.0);
+      double dx = p1 / dp;
+      x -= dx;
+      if (fabs(dx) < 1e-17) break;
+    }
+    gl_x[i] = x;
+    gl_w[i] = 2.0 / ((1.0 - x * x) * dp * dp);
+  }
+  gl_ready = 1;
+}
+/* filled once when the library loads, before any (threaded) caller */
+__attribute__((constructor)) static void gl_ctor(void) { gl_init(); }
+
+/* phi_r(u) = int_0^u omega_r(t) dt by composite Gauss-Legendre (8 panels of
+ * 32 nodes; the integrand is entire, so this is exact to rounding) */
+double oracle_sidi_phi(double u, int r) {
+  gl_init();
+  const int panels = 8;
+  double h = u / panels, s = 0.0;
+  for (int p = 0; p < panels; ++p) {
+    double a = p * h, ps = 0.0;
+    for (int i = 0; i < OR_GL_N; ++i) ps += gl_w[i] * oracle_sidi_omega(a + 0.5 * h * (gl_x[i] + 1.0), r);
+    s += 0.5 * h * ps;
+  }
+  return s;
+}
 
 /* ------------------------------------------------------------------ */
 /* variance-reduction map (Sec. 2.4, eq. ISfit; App. A.5 PolySingular)  */
@@ -322,6 +373,9 @@ static int contribution(const point_ctx* P, uint64_t k, const double* delta, dou
       w *= oracle_korobov_omega(u, P->r0, P->r1);
     } else if (P->tkind == OR_T_BAKER) {
       y = oracle_baker_phi(u);
+    } else if (P->tkind == OR_T_SIDI) {
+      y = oracle_sidi_phi(u, P->r0);
+      w *= oracle_sidi_omega(u, P->r0);
     } else {
       y = u;
     }

@@ -141,6 +141,44 @@ def test_baker_preserves_integrals():
     assert oracle.baker_phi(0.25) == 0.5 and oracle.baker_phi(0.75) == 0.5
 
 
+@pytest.mark.parametrize("r", [1, 2, 3, 4, 5, 6, 9])
+def test_sidi_weight_normalised_and_map_symmetric(r):
+    """eq. sidi: the Gamma-function constant normalises the weight (checked by
+    mpmath quadrature of sin^r), phi(0)=0, phi(1)=1, phi(u) + phi(1-u) = 1."""
+    mp.mp.dps = 30
+    num = mp.quad(lambda t: mp.sin(mp.pi * t) ** r, [0, 0.5, 1])
+    assert oracle.sidi_omega(0.5, r) == pytest.approx(float(1 / num), rel=1e-14)
+    assert oracle.sidi_phi(0.0, r) == 0.0
+    assert oracle.sidi_phi(1.0, r) == pytest.approx(1.0, abs=2e-15)
+    for u in np.linspace(0.0, 1.0, 17):
+        assert oracle.sidi_phi(u, r) + oracle.sidi_phi(1.0 - u, r) == pytest.approx(1.0, abs=2e-15)
+
+
+@pytest.mark.parametrize("r", [1, 2, 3, 4, 7])
+def test_sidi_map_matches_closed_forms(r):
+    """int_0^u sin^r(pi t) dt in closed form (mpmath, 30 digits) against the
+    oracle's numerical map; small u checks relative accuracy near 0."""
+    mp.mp.dps = 30
+    norm = mp.quad(lambda t: mp.sin(mp.pi * t) ** r, [0, 1])
+    for u in (1e-3, 0.013, 0.2, 0.5, 0.77, 0.999):
+        exact = mp.quad(lambda t: mp.sin(mp.pi * t) ** r, [0, u]) / norm
+        assert oracle.sidi_phi(u, r) == pytest.approx(float(exact), rel=1e-13, abs=1e-300)
+    # r = 1 and r = 2 by hand
+    if r == 1:
+        assert oracle.sidi_phi(0.3, 1) == pytest.approx((1 - math.cos(math.pi * 0.3)) / 2, rel=1e-15)
+    if r == 2:
+        assert oracle.sidi_phi(0.3, 2) == pytest.approx(0.3 - math.sin(0.6 * math.pi) / (2 * math.pi), rel=1e-15)
+
+
+def test_sidi_preserves_integrals():
+    """int_0^1 q(phi(u)) omega(u) du = int_0^1 q(x) dx for the Sidi change of variables."""
+    q = lambda x: 3.0 * x ** 5 - x ** 2 + 0.5
+    for r in (2, 3, 6):
+        lhs = _gl(lambda u: q(oracle.sidi_phi(u, r)) * oracle.sidi_omega(u, r), 0.0, 0.5) + \
+              _gl(lambda u: q(oracle.sidi_phi(u, r)) * oracle.sidi_omega(u, r), 0.5, 1.0)
+        assert lhs == pytest.approx(0.5 - 1.0 / 3.0 + 0.5, abs=1e-13)
+
+
 # ------------------------------------------------------------------ VR map
 
 
@@ -202,6 +240,18 @@ def test_product_of_linear_closed_form(power):
     val, err, _, _ = _integrate(desc, cbc.next_prime(50000), m=16)
     assert abs(val.real - exact) < max(6 * err, 1e-13)
     assert abs(val.real - exact) < 1e-9 * abs(exact)
+
+
+@pytest.mark.parametrize("r", [2, 3])
+def test_sidi_lattice_rule_on_a_closed_form(r):
+    """The whole rule with the Sidi transform on a product-of-linear integrand
+    (closed form above) converges to the exact value."""
+    a, b = np.array([1.0, 0.7]), np.array([0.5, 0.9])
+    desc = W.product_of_linear(a, b, -1.5)
+    exact = np.prod(((a + b) ** -0.5 - a ** -0.5) / (b * -0.5))
+    val, err, _, _ = _integrate(desc, 4099, m=8, transform=(oracle.T_SIDI, r, r))
+    assert abs(val.real - exact) < max(6 * err, 1e-12)
+    assert abs(val.real - exact) < 1e-7 * abs(exact)
 
 
 def test_plain_product_workload_integrates_to_one():
