@@ -168,9 +168,11 @@ int qmc_fit_vr(qmc_context* ctx, qmc_integrand* f, uint64_t n, const uint64_t* z
                double* params, uint32_t* fallback_mask);
 
 /* ---------------------------------------------------------------- transforms */
-enum { QMC_T_NONE = 0, QMC_T_KOROBOV = 1, QMC_T_BAKER = 2 };
+enum { QMC_T_NONE = 0, QMC_T_KOROBOV = 1, QMC_T_BAKER = 2, QMC_T_SIDI = 3 };
 
-/* Korobov<r0,r1> (eq. korobov, 0 <= r0, r1 <= 12), baker (eq. baker), none. */
+/* Korobov<r0,r1> (eq. korobov, 0 <= r0, r1 <= 12), baker (eq. baker), none,
+ * Sidi<r> (eq. sidi, weight proportional to sin(pi u)^r, 1 <= r = r0 <= 25;
+ * r1 is ignored). */
 typedef struct {
   int32_t kind;
   int32_t r0, r1;

@@ -24,7 +24,7 @@ QMC_OK, QMC_PENDING = 0, 1
 QMC_EINVAL, QMC_ENOMEM, QMC_EDEVICE, QMC_EBUSY, QMC_ENOTFOUND, QMC_ECANCELED, QMC_EUNSUPPORTED = (
     -1, -2, -3, -4, -5, -6, -7)
 QMC_DEFORM, QMC_EVAL_FP32 = 1, 2
-T_NONE, T_KOROBOV, T_BAKER = 0, 1, 2
+T_NONE, T_KOROBOV, T_BAKER, T_SIDI = 0, 1, 2, 3
 QMC_CONVERGED, QMC_MAXEVAL_HIT, QMC_NONFINITE, QMC_VR_FALLBACK, QMC_DEFORM_SIGN = 1, 2, 4, 8, 16
 ERRMODE_ALL, ERRMODE_LARGEST = 0, 1
 

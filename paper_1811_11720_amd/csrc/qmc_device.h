@@ -38,7 +38,7 @@ typedef unsigned char uint8_t;
 
 namespace qmcd {
 
-enum { TK_NONE = 0, TK_KOROBOV = 1, TK_BAKER = 2, TK_KOROBOV3 = 3, TK_RUNTIME = 4 };  // RUNTIME: EvalArgs::tk
+enum { TK_NONE = 0, TK_KOROBOV = 1, TK_BAKER = 2, TK_KOROBOV3 = 3, TK_SIDI = 4, TK_RUNTIME = 5 };  // RUNTIME: EvalArgs::tk
 enum { PW_ONE = 0, PW_INT = 1, PW_HALF = 2, PW_GEN = 3 };
 
 // Everything one evaluation launch needs, passed by value.
@@ -69,7 +69,7 @@ struct EvalArgs {
   const double* vr;           // [dim][6] or nullptr
   double wscale;              // Korobov r=3: prod_j omega = wscale * (prod_j u_j (1-u_j))^3, wscale = 140^dim
   unsigned long long* sign_count;  // complex kernels: points with Im F(z) > 0
-  int32_t tk;                 // transform kind for TK_RUNTIME kernels (TK_NONE..TK_KOROBOV3)
+  int32_t tk;                 // transform kind for TK_RUNTIME kernels (TK_NONE..TK_SIDI)
   const float* coef32;        // coefficients rounded to fp32 (fp32-evaluation kernels)
   uint64_t tile_points;       // batch: points per tile (a multiple of the block size)
   uint32_t ktiles;            // batch: tiles along k (= columns of partial[][])
@@ -190,6 +190,8 @@ __device__ __forceinline__ double transform_rt(double u, double& w, const EvalAr
       return transform<TK_KOROBOV>(u, w, a);
     case TK_BAKER:
       return transform<TK_BAKER>(u, w, a);
+    case TK_SIDI:
+      return transform<TK_SIDI>(u, w, a);
     default:
       return u;
   }
@@ -209,6 +211,42 @@ __device__ __forceinline__ double transform(double u, double& w, const EvalArgs&
   } else if (TK == TK_BAKER) {
     double v = 1.0 - u;  // exact for u >= 1/2
     return 2.0 * (u < v ? u : v);
+  } else if (TK == TK_SIDI) {
+    // Sidi<r> (eq. sidi): omega = c_r sin(pi u)^r, phi = its integral from 0.
+    // Evaluated at v = min(u, 1-u) (phi(1-v) = 1 - phi(v)) from the half-angle
+    // sine and cosine h, g of pi v / 2: sin(pi v) = 2 h g, 1 - cos(pi v) = 2 h^2.
+    // Odd r = 2k+1: phi = W^(k+1) sum_i phi_c[i] W^i with W = 2 h^2 (no
+    // cancellation as v -> 0).  Even r = 2k: the reduction
+    // I_2j = -sin^(2j-1) cos / (2 j pi) + (2j-1)/(2j) I_2j-2, I_0 = v.
+    const double c = 1.0 - u;
+    const bool refl = c < u;
+    const double v = refl ? c : u;
+    double h, g;
+    sincospi(0.5 * v, &h, &g);
+    const double s = 2.0 * h * g;
+    const int r = a.r0;
+    double phi;
+    if (r & 1) {
+      const double W = 2.0 * h * h;
+      double pp = a.phi_c[a.deg_phi];
+      for (int i = a.deg_phi - 1; i >= 0; --i) pp = __builtin_fma(pp, W, a.phi_c[i]);
+      double wk = W;
+      for (int i = 0; i < a.deg_phi; ++i) wk *= W;
+      phi = pp * wk;
+    } else {
+      const double cs = (g - h) * (g + h);  // cos(pi v)
+      const double s2 = s * s;
+      double I = v, sp = s;
+      for (int j = 0; j < a.deg_phi; ++j) {
+        I = __builtin_fma(-sp * cs, a.phi_c[2 * j], a.phi_c[2 * j + 1] * I);
+        sp *= s2;
+      }
+      phi = a.om_c[0] * I;
+    }
+    double sr = a.om_c[0];
+    for (int i = 0; i < r; ++i) sr *= s;
+    w *= sr;
+    return refl ? 1.0 - phi : phi;
   } else {
     // Korobov<r0,r1>; for r0 == r1 evaluate at v = min(u, 1-u) (phi(1-v) = 1-phi(v))
     double v = u;

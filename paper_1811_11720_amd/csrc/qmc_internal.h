@@ -27,7 +27,8 @@ constexpr int S_COMPLEX_JIT = 1;
 constexpr uint32_t MAX_DIM_COMPLEX = 12;
 
 // transform selector of the AOT kernels: generic Korobov, the written-out r=3 form, baker, none
-enum { TSEL_NONE = 0, TSEL_KOROBOV = 1, TSEL_BAKER = 2, TSEL_KOROBOV3 = 3 };
+// (numbered like the device's TK_* kinds)
+enum { TSEL_NONE = 0, TSEL_KOROBOV = 1, TSEL_BAKER = 2, TSEL_KOROBOV3 = 3, TSEL_SIDI = 4, TSEL_COUNT = 5 };
 
 hipError_t launch_eval_real(const qmcd::EvalArgs& a, int dclass, int tsel, bool idx32, dim3 grid,
                             hipStream_t st);

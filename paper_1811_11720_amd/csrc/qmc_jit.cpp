@@ -389,6 +389,7 @@ std::string generate(const Spec& s) {
   const char* tk = s.tk == qmcd::TK_KOROBOV3 ? "qmcd::TK_KOROBOV3"
                    : s.tk == qmcd::TK_KOROBOV ? "qmcd::TK_KOROBOV"
                    : s.tk == qmcd::TK_BAKER   ? "qmcd::TK_BAKER"
+                   : s.tk == qmcd::TK_SIDI    ? "qmcd::TK_SIDI"
                                                : "qmcd::TK_NONE";
   if (s.cplx) {
     std::ostringstream o;

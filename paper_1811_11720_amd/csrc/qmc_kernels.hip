@@ -25,14 +25,15 @@ using EvalFn = void (*)(qmcd::EvalArgs);
     {k_eval_real<D, qmcd::TK_NONE, false>, k_eval_real<D, qmcd::TK_NONE, true>},                 \
         {k_eval_real<D, qmcd::TK_KOROBOV, false>, k_eval_real<D, qmcd::TK_KOROBOV, true>},       \
         {k_eval_real<D, qmcd::TK_BAKER, false>, k_eval_real<D, qmcd::TK_BAKER, true>},           \
-        {k_eval_real<D, qmcd::TK_KOROBOV3, false>, k_eval_real<D, qmcd::TK_KOROBOV3, true>},                                 \
+        {k_eval_real<D, qmcd::TK_KOROBOV3, false>, k_eval_real<D, qmcd::TK_KOROBOV3, true>},     \
+        {k_eval_real<D, qmcd::TK_SIDI, false>, k_eval_real<D, qmcd::TK_SIDI, true>},             \
   }
 
-static EvalFn g_real[4][4][2] = {QMC_ROW(4), QMC_ROW(8), QMC_ROW(12), QMC_ROW(16)};
+static EvalFn g_real[4][TSEL_COUNT][2] = {QMC_ROW(4), QMC_ROW(8), QMC_ROW(12), QMC_ROW(16)};
 #undef QMC_ROW
 
 // complex kernels: one table per dimension class, defined in qmc_kernels_c{4,8,12}.hip
-using EvalTable = EvalFn[4][2];
+using EvalTable = EvalFn[TSEL_COUNT][2];
 extern EvalTable g_complex4, g_complex8, g_complex12;
 static EvalTable* const g_complex[3] = {&g_complex4, &g_complex8, &g_complex12};
 

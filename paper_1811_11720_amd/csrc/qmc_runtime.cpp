@@ -150,6 +150,29 @@ int set_transform(qmcd::EvalArgs& a, const qmc_transform& t, int& tsel) {
       a.om_c[i] = b;
       a.phi_c[i] = b / (double)(t.r0 + 1 + i);  // phi = int_0^v omega
     }
+  } else if (t.kind == QMC_T_SIDI) {
+    if (t.r0 < 1 || t.r0 > 25) return fail(QMC_EINVAL, "Sidi weight r=%d outside [1, 25]", t.r0);
+    tsel = qmck::TSEL_SIDI;
+    const int r = t.r0;
+    // c_r = pi 2^-r Gamma(r+1) / Gamma((r+1)/2)^2   (eq. sidi)
+    const double gh = std::tgamma(0.5 * (r + 1.0));
+    const double cr = M_PI * std::ldexp(1.0, -r) * std::tgamma(r + 1.0) / (gh * gh);
+    a.r0 = r;
+    a.sym = 1;
+    a.om_c[0] = cr;
+    a.deg_om = 0;
+    const int k = r / 2;
+    a.deg_phi = k;
+    if (r & 1) {
+      // phi = c_r / pi * int_0^W (w (2 - w))^k dw = sum_i c_r/pi C(k,i) 2^(k-i) (-1)^i W^(k+i+1) / (k+i+1)
+      for (int i = 0; i <= k; ++i)
+        a.phi_c[i] = cr / M_PI * binom(k, i) * std::ldexp(1.0, k - i) * ((i & 1) ? -1.0 : 1.0) / (double)(k + i + 1);
+    } else {
+      for (int j = 1; j <= k; ++j) {
+        a.phi_c[2 * (j - 1)] = 1.0 / (2.0 * j * M_PI);
+        a.phi_c[2 * (j - 1) + 1] = (2.0 * j - 1.0) / (2.0 * j);
+      }
+    }
   } else {
     return fail(QMC_EINVAL, "unknown transform kind %d", t.kind);
   }
@@ -501,6 +524,7 @@ int fill_integrand_args(qmcd::EvalArgs& a, const qmc_integrand* f, const qmc_tra
   if (rc) return rc;
   a.tk = tsel == qmck::TSEL_KOROBOV3 ? qmcd::TK_KOROBOV3
          : tsel == qmck::TSEL_KOROBOV ? qmcd::TK_KOROBOV
+         : tsel == qmck::TSEL_SIDI    ? qmcd::TK_SIDI
          : tsel == qmck::TSEL_BAKER   ? qmcd::TK_BAKER
                                        : qmcd::TK_NONE;
   a.dim = f->dim;

@@ -47,7 +47,8 @@ def _mix(count, seed, n_choices=(1009, 4099, 10007), fp32=False):
                         complex_=cplx, lam=0.5, neg_frac=0.3)
         desc.fp32 = fp32
         n = int(rng.choice(n_choices))
-        tr = [KOR3, (W.T_BAKER, 0, 0), (W.T_KOROBOV, 2, 2), (W.T_NONE, 0, 0)][int(rng.integers(0, 4))]
+        tr = [KOR3, (W.T_BAKER, 0, 0), (W.T_KOROBOV, 2, 2), (W.T_NONE, 0, 0), (W.T_SIDI, 2, 0),
+              (W.T_SIDI, 3, 0)][int(rng.integers(0, 6))]
         m = int(rng.integers(1, 20))
         jobs.append(W.Job(desc, n, cbc.fast_cbc(n, dim), m, seed=7000 + i, transform=tr))
     return jobs

@@ -93,7 +93,7 @@ def test_u_on_the_contour(ctx):
     assert abs(complex(g["re"], g["im"]) - exact) < 1e-10 * abs(exact)
 
 
-@pytest.mark.parametrize("tr", [KOR3, (W.T_BAKER, 0, 0), (W.T_KOROBOV, 2, 2), (W.T_NONE, 0, 0)],
+@pytest.mark.parametrize("tr", [KOR3, (W.T_BAKER, 0, 0), (W.T_KOROBOV, 2, 2), (W.T_NONE, 0, 0), (W.T_SIDI, 3, 0)],
                          ids=lambda t: f"T{t[0]}_{t[1]}_{t[2]}")
 @pytest.mark.parametrize("dim", [2, 3, 5, 8, 12])
 def test_random_complex_integrands(ctx, dim, tr):

@@ -120,6 +120,18 @@ def test_random_real_integrands(ctx, dim, tr):
     _check_sums(g["sums_re"], o, label=f"d{dim}")
 
 
+@pytest.mark.parametrize("r", [1, 2, 3, 4, 7])
+@pytest.mark.parametrize("dim", [1, 3, 9])
+def test_sidi_transform(ctx, dim, r):
+    """Sidi<r> (eq. sidi): odd r from the half-angle polynomial, even r from the
+    reduction formula, against the oracle's quadrature of the weight."""
+    desc = W.random_real_small(seed=200 + dim, dim=dim, n_u=3, n_f=6)
+    n = 4099
+    z = cbc.fast_cbc(n, dim)
+    g, o, _ = _run_both(ctx, desc, n, z, 5, 700 + dim, (W.T_SIDI, r, 0))
+    _check_sums(g["sums_re"], o, label=f"d{dim} r{r}")
+
+
 @pytest.mark.parametrize("pu,pf", [(1.0, 0.0), (-3.0, 2.0), (-2.5, 0.5), (-1.3, -2.0), (0.0, -1.0), (2.0, -0.5)])
 def test_power_classes(ctx, pu, pf):
     desc = W.random_real_small(seed=7, dim=4, n_u=4, n_f=5, pow_u=pu, pow_f=pf)

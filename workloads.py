@@ -43,7 +43,7 @@ LATTICE_TABLE = os.path.join(
 )
 
 # transform kinds shared by the C interface of both sides
-T_NONE, T_KOROBOV, T_BAKER = 0, 1, 2
+T_NONE, T_KOROBOV, T_BAKER, T_SIDI = 0, 1, 2, 3
 
 
 @dataclass
