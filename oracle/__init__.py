@@ -257,24 +257,46 @@ def goal_met(re, im, err_re, err_im, rel_tol, abs_tol, errormode, is_complex) ->
     return max(err_re, err_im) <= max(abs_tol, rel_tol * max(abs(re), abs(im)))
 
 
+MAX_SHIFTS = 1024  # largest number of shifts (the library's limit)
+
+
 def integrate(desc, n, z_of, m, seed, transform=(T_KOROBOV, 3, 3), vr=None, rel_tol=0.0,
               abs_tol=0.0, errormode="largest", max_evals=None, table_ns=None, threads=None):
     """Oracle integration: Case 2 (one lattice) when rel_tol <= 0 and abs_tol <= 0,
-    else the Case-1 growth loop over `table_ns` with generating vectors z_of(n)."""
-    sh = shifts(seed, m, desc.dim)
+    else the Case-1 loop of Sec. 3.3.1 over `table_ns` with generating vectors
+    z_of(n): a round that misses its goal is discarded and the next lattice of
+    at least max(1.5 n, n err/goal) points is taken.  When the table has none,
+    the largest lattice is taken, and once there the error is reduced by adding
+    shifts (Monte Carlo scaling): m grows to max(m+1, ceil(m (err/goal)^2)), at
+    most MAX_SHIFTS; the new shifts continue the same random stream, so the
+    sums of the earlier shifts are kept.  A round that would pass max_evals is
+    never started."""
+    table = sorted(table_ns) if table_ns is not None else [n]
+    m_all = m
+    sh = shifts(seed, m_all, desc.dim)
+    s_re = np.zeros(0)
+    s_im = np.zeros(0)
+    a_re = np.zeros(0)
+    a_im = np.zeros(0)
     evals = 0
     it = 0
     visited = []
+    first_new = 0  # shifts [first_new, m_all) still to evaluate at this lattice
     while True:
-        visited.append(n)
-        s = shift_sums(desc, n, z_of(n), m, sh, transform, vr, threads=threads)
+        visited.append((n, m_all))
+        ids = list(range(first_new, m_all))
+        s = shift_sums(desc, n, z_of(n), m_all, sh, transform, vr, ids=ids, threads=threads)
+        s_re = np.concatenate([s_re[:first_new], s.re])
+        s_im = np.concatenate([s_im[:first_new], s.im])
+        a_re = np.concatenate([a_re[:first_new], s.abs_re])
+        a_im = np.concatenate([a_im[:first_new], s.abs_im])
         it += 1
-        evals += n * m
-        re, err_re = estimate(s.re / n)
-        im, err_im = estimate(s.im / n)
-        res = dict(re=re, im=im, err_re=err_re, err_im=err_im, n=n, m=m, iterations=it,
-                   evaluations=evals, sums_re=s.re.copy(), sums_im=s.im.copy(),
-                   abs_re=s.abs_re.copy(), abs_im=s.abs_im.copy(), converged=False,
+        evals += n * len(ids)
+        re, err_re = estimate(s_re / n)
+        im, err_im = estimate(s_im / n)
+        res = dict(re=re, im=im, err_re=err_re, err_im=err_im, n=n, m=m_all, iterations=it,
+                   evaluations=evals, sums_re=s_re.copy(), sums_im=s_im.copy(),
+                   abs_re=a_re.copy(), abs_im=a_im.copy(), converged=False,
                    maxeval_hit=False, visited=list(visited))
         if rel_tol <= 0 and abs_tol <= 0:
             return res
@@ -283,12 +305,27 @@ def integrate(desc, n, z_of, m, seed, transform=(T_KOROBOV, 3, 3), vr=None, rel_
             return res
         goal = max(abs_tol, rel_tol * (max(abs(re), abs(im)) if desc.deform else abs(re)))
         err = max(err_re, err_im) if desc.deform else err_re
-        want = max(1.5 * n, n * (err / goal if goal > 0 else 2.0))
-        larger = [v for v in sorted(table_ns) if v >= want]
-        if not larger or (max_evals is not None and evals + larger[0] * m > max_evals):
+        want = max(1.5 * n, n * (err / goal if goal > 0 and math.isfinite(err) else 2.0))
+        larger = [v for v in table if v >= want]
+        if larger or table[-1] > n:
+            nn = larger[0] if larger else table[-1]
+            if max_evals is not None and evals + nn * m_all > max_evals:
+                res["maxeval_hit"] = True
+                return res
+            n = nn
+            first_new = 0
+            continue
+        # at the largest lattice: more shifts
+        ratio = (err / goal) ** 2 if goal > 0 and math.isfinite(err) else math.inf
+        m_new = MAX_SHIFTS if ratio * m_all >= MAX_SHIFTS else max(m_all + 1, math.ceil(m_all * ratio))
+        if max_evals is not None:
+            m_new = min(m_new, m_all + (max_evals - evals) // n)
+        if m_new <= m_all:
             res["maxeval_hit"] = True
             return res
-        n = larger[0]
+        first_new = m_all
+        m_all = m_new
+        sh = shifts(seed, m_all, desc.dim)
 
 
 # ---------------------------------------------------------------- CBC

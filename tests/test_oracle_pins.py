@@ -433,12 +433,14 @@ def test_growth_loop_stops_at_first_lattice_meeting_goal():
     res = oracle.integrate(desc, table[0], zs.__getitem__, 16, 77, BAKER, rel_tol=1e-8, table_ns=table)
     assert res["converged"]
     assert res["err_re"] <= 1e-8 * abs(res["re"])
-    assert res["visited"][-1] == res["n"] and len(res["visited"]) == res["iterations"] > 1
+    ns = [v[0] for v in res["visited"]]
+    assert ns[-1] == res["n"] and len(ns) == res["iterations"] > 1
+    assert all(v[1] == 16 for v in res["visited"])
     # every earlier visited lattice failed the goal (otherwise the loop stops there)
-    for n in res["visited"][:-1]:
+    for n in ns[:-1]:
         r2 = oracle.integrate(desc, n, zs.__getitem__, 16, 77, BAKER)
         assert r2["err_re"] > 1e-8 * abs(r2["re"])
-    assert res["evaluations"] == sum(res["visited"]) * 16
+    assert res["evaluations"] == sum(ns) * 16
 
 
 def test_growth_loop_respects_maxeval():
@@ -449,6 +451,49 @@ def test_growth_loop_respects_maxeval():
                            max_evals=20000, table_ns=table)
     assert res["maxeval_hit"] and not res["converged"]
     assert res["evaluations"] <= 20000 or res["iterations"] == 1
+
+
+def test_shift_stream_is_prefix_stable():
+    """More shifts continue the same SplitMix64 stream: the first m rows of
+    shifts(seed, m') are shifts(seed, m)."""
+    a = oracle.shifts(42, 5, 3)
+    b = oracle.shifts(42, 40, 3)
+    assert np.array_equal(a, b[:5])
+
+
+def test_fallback_adds_shifts_at_the_largest_lattice():
+    """Sec. 3.3.1: when the goal needs a lattice larger than the table holds,
+    the largest lattice is used and shifts are added (Monte Carlo scaling);
+    earlier shifts are kept, and the result is the plain m'-shift estimate."""
+    desc = W.product_of_linear([1.0, 1.0], [0.8, 0.5], -1.5)
+    table = [cbc.next_prime(v) for v in (500, 1000)]
+    zs = {n: cbc.fast_cbc(n, 2) for n in table}
+    BAKER = (oracle.T_BAKER, 0, 0)
+    first = oracle.integrate(desc, table[0], zs.__getitem__, 8, 5, BAKER)
+    goal = first["err_re"] / abs(first["re"]) / 12.0  # needs ~100x the variance reduction of one lattice step
+    res = oracle.integrate(desc, table[0], zs.__getitem__, 8, 5, BAKER, rel_tol=goal, table_ns=table)
+    assert res["n"] == table[-1] and res["m"] > 8
+    ns = [v[0] for v in res["visited"]]
+    assert ns[0] == table[0] and ns[1] == table[-1]
+    ms = [v[1] for v in res["visited"] if v[0] == table[-1]]
+    assert ms == sorted(ms) and ms[0] == 8
+    # the same estimate from scratch with all m' shifts at the largest lattice
+    direct = oracle.integrate(desc, table[-1], zs.__getitem__, res["m"], 5, BAKER)
+    assert np.array_equal(direct["sums_re"], res["sums_re"])
+    assert direct["re"] == res["re"] and direct["err_re"] == res["err_re"]
+    # the evaluations count every shift once per lattice
+    assert res["evaluations"] == table[0] * 8 + table[-1] * res["m"]
+    assert res["converged"] == (res["err_re"] <= goal * abs(res["re"]))
+    assert res["converged"] or res["m"] == oracle.MAX_SHIFTS
+
+
+def test_fallback_stops_at_maxeval():
+    desc = W.product_of_linear([1.0, 1.0], [0.8, 0.5], -1.5)
+    table = [cbc.next_prime(500)]
+    zs = {table[0]: cbc.fast_cbc(table[0], 2)}
+    res = oracle.integrate(desc, table[0], zs.__getitem__, 8, 5, (oracle.T_BAKER, 0, 0), rel_tol=1e-14,
+                           max_evals=table[0] * 20, table_ns=table)
+    assert res["maxeval_hit"] and res["m"] == 20 and res["evaluations"] == table[0] * 20
 
 
 def test_goal_rules_complex():
