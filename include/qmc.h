@@ -195,7 +195,8 @@ typedef struct {
   double re, im;          /* estimate; im = 0 for real integrands */
   double err_re, err_im;  /* sqrt of eq. lattice-error per component; +inf if m = 1 */
   uint64_t n;             /* lattice size of the returned (last) iteration */
-  uint32_t m;             /* shifts */
+  uint32_t m;             /* shifts of the last lattice (more than requested after the
+                             Monte Carlo fallback) */
   uint32_t iterations;    /* lattices evaluated (earlier ones discarded) */
   uint64_t evaluations;   /* total integrand evaluations over all iterations */
   uint32_t flags;         /* QMC_CONVERGED | ... */
@@ -215,8 +216,14 @@ typedef struct {
  * rel_tol > 0:  grow n through the registered table until the error goal
  *               (errormode "largest" for complex results) is met, as in the
  *               paper's "Case 1" (Sec. 3.3.1); only the last lattice counts.
+ *               When the goal needs a lattice larger than the table holds,
+ *               the largest one is used and, once there, shifts are added
+ *               (m -> max(m+1, ceil(m (err/goal)^2)), at most QMC_MAX_SHIFTS;
+ *               Monte Carlo scaling); the added shifts continue the same
+ *               SplitMix64 stream, so earlier shifts' sums are kept.
  * shift_sums: optional host [m] (real) or [2m] (complex: re[0..m) then
- * im[0..m)) receiving the raw per-shift sums sum_k w f of the last lattice.
+ * im[0..m)) receiving the raw per-shift sums sum_k w f of the last lattice
+ * for the first m (requested) shifts.
  */
 int qmc_integrate(qmc_context* ctx, const qmc_integrand* f, uint32_t dim, uint64_t n,
                   const uint64_t* z, uint32_t m, uint64_t seed, qmc_transform t, double rel_tol,
@@ -241,11 +248,13 @@ typedef struct {
  * kernels (one per dimension class / real-complex / fp64-fp32 variant) that
  * drain a shared tile list, replayed as one HIP graph; requests that miss
  * their goal move to the next registered lattice for the next round
- * (Sec. 3.3.1).  A request's tiling depends only on its own n and m, so its
+ * (Sec. 3.3.1), with the same Monte Carlo fallback as qmc_integrate.  A
+ * request's tiling depends only on its own n and m, so its
  * per-shift sums are bitwise the same alone or in any batch.  QMC_EVAL_FP32
  * integrands run here (U, F and powers in fp32, compensated fp64 sums).
  * shift_sums (optional) gets each request's per-shift sums of its last
- * lattice back to back ([m] or [2m] each).  device_seconds is the batch's
+ * lattice for its requested m shifts, back to back ([m] or [2m] each).
+ * device_seconds is the batch's
  * total kernel time.
  */
 int qmc_integrate_batch(qmc_context* ctx, const qmc_request* reqs, uint32_t count,

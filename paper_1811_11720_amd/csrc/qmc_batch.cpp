@@ -245,6 +245,9 @@ int run_requests(qmc_context* c, const qmc_request* reqs, uint32_t count, qmc_re
     std::vector<double> shifts;
     std::vector<uint64_t> z;
     uint64_t n;
+    uint32_t mcur = 0, first_new = 0;  // shifts [first_new, mcur) run next
+    std::vector<double> sre, sim;      // per-shift sums at the current lattice
+    uint64_t signs = 0;
     bool done = false;
     qmc_result r{};
     BatchJob job;
@@ -271,6 +274,7 @@ int run_requests(qmc_context* c, const qmc_request* reqs, uint32_t count, qmc_re
     }
     s.shifts.resize((size_t)q.m * dim);
     make_shifts(q.seed, q.m, dim, s.shifts.data());
+    s.mcur = q.m;
     s.r.m = q.m;
     s.r.path = 2;
   }
@@ -284,8 +288,8 @@ int run_requests(qmc_context* c, const qmc_request* reqs, uint32_t count, qmc_re
       s.job.f = s.f;
       s.job.n = s.n;
       s.job.z = s.z.data();
-      s.job.m = reqs[i].m;
-      s.job.shifts = s.shifts.data();
+      s.job.m = s.mcur - s.first_new;
+      s.job.shifts = s.shifts.data() + (size_t)s.first_new * s.f->dim;
       s.job.t = reqs[i].t;
       jobs.push_back(&s.job);
       idx.push_back(i);
@@ -299,20 +303,29 @@ int run_requests(qmc_context* c, const qmc_request* reqs, uint32_t count, qmc_re
       St& s = st[i];
       const qmc_request& q = reqs[i];
       const bool cplx = (s.f->flags & QMC_DEFORM) != 0;
-      const uint32_t m = q.m;
+      const uint32_t madd = s.mcur - s.first_new, m = s.mcur;
+      s.sre.resize(s.first_new);
+      s.sim.resize(s.first_new);
+      s.sre.insert(s.sre.end(), s.job.sums.begin(), s.job.sums.begin() + madd);
+      if (cplx)
+        s.sim.insert(s.sim.end(), s.job.sums.begin() + madd, s.job.sums.begin() + 2 * (size_t)madd);
+      else
+        s.sim.resize(m, 0.0);
+      s.signs = (s.first_new ? s.signs : 0) + s.job.sign_points;
       s.r.iterations += 1;
-      s.r.evaluations += s.n * (uint64_t)m;
+      s.r.evaluations += s.n * (uint64_t)madd;
       s.r.n = s.n;
+      s.r.m = m;
       std::vector<double> qs(m);
-      for (uint32_t k = 0; k < m; ++k) qs[k] = s.job.sums[k] / (double)s.n;
+      for (uint32_t k = 0; k < m; ++k) qs[k] = s.sre[k] / (double)s.n;
       estimate(qs.data(), m, s.r.re, s.r.err_re);
       s.r.im = s.r.err_im = 0.0;
       if (cplx) {
-        for (uint32_t k = 0; k < m; ++k) qs[k] = s.job.sums[m + k] / (double)s.n;
+        for (uint32_t k = 0; k < m; ++k) qs[k] = s.sim[k] / (double)s.n;
         estimate(qs.data(), m, s.r.im, s.r.err_im);
       }
       s.r.flags &= ~(uint32_t)(QMC_NONFINITE | QMC_DEFORM_SIGN);
-      if (s.job.sign_points) s.r.flags |= QMC_DEFORM_SIGN;
+      if (s.signs) s.r.flags |= QMC_DEFORM_SIGN;
       const bool finite = std::isfinite(s.r.re) && std::isfinite(s.r.im);
       if (!finite) s.r.flags |= QMC_NONFINITE;
       const bool grow = q.rel_tol > 0 || q.abs_tol > 0;
@@ -325,32 +338,37 @@ int run_requests(qmc_context* c, const qmc_request* reqs, uint32_t count, qmc_re
         s.done = true;
         continue;
       }
-      double goal = std::max(q.abs_tol, q.rel_tol * (cplx ? std::max(std::fabs(s.r.re), std::fabs(s.r.im))
-                                                          : std::fabs(s.r.re)));
-      double err = cplx ? std::max(s.r.err_re, s.r.err_im) : s.r.err_re;
-      double want = std::max(1.5 * (double)s.n, goal > 0 && std::isfinite(err) ? (double)s.n * err / goal : 2.0 * s.n);
-      uint64_t wantu = want >= 9.0e15 ? (uint64_t)9.0e15 : (uint64_t)std::ceil(want);
-      uint64_t nn = 0;
-      std::vector<uint64_t> zn;
-      if (next_registered(c, wantu, s.f->dim, &nn, false, &zn) != QMC_OK ||
-          (q.max_evals && s.r.evaluations + nn * (uint64_t)m > q.max_evals)) {
+      GrowthStep g = growth_step(c, q, s.r, s.n, m, s.f->dim, cplx, UINT64_MAX, QMC_MAX_SHIFTS);
+      if (g.kind == GrowthStep::STOP) {
         s.r.flags |= QMC_MAXEVAL_HIT;
         s.done = true;
-        continue;
+      } else if (g.kind == GrowthStep::LATTICE) {
+        s.n = g.n;
+        s.z.swap(g.z);
+        s.first_new = 0;
+      } else {
+        s.first_new = m;
+        s.mcur = g.m;
+        s.shifts.resize((size_t)g.m * s.f->dim);
+        make_shifts(q.seed, g.m, s.f->dim, s.shifts.data());
       }
-      s.n = nn;
-      s.z.swap(zn);
     }
   }
   const double wall = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   size_t off = 0;
   for (uint32_t i = 0; i < count; ++i) {
-    st[i].r.device_seconds = dev;  // shared launches: the batch's total device time
-    st[i].r.wall_seconds = wall;
-    if (out) out[i] = st[i].r;
-    if (shift_sums) {
-      std::memcpy(shift_sums + off, st[i].job.sums.data(), st[i].job.sums.size() * 8);
-      off += st[i].job.sums.size();
+    St& s = st[i];
+    s.r.device_seconds = dev;  // shared launches: the batch's total device time
+    s.r.wall_seconds = wall;
+    if (out) out[i] = s.r;
+    if (shift_sums) {  // the requested m shifts of each request
+      const uint32_t m = reqs[i].m;
+      std::memcpy(shift_sums + off, s.sre.data(), (size_t)m * 8);
+      off += m;
+      if (s.f->flags & QMC_DEFORM) {
+        std::memcpy(shift_sums + off, s.sim.data(), (size_t)m * 8);
+        off += m;
+      }
     }
   }
   return QMC_OK;

@@ -100,6 +100,22 @@ bool goal_met(const qmc_result& r, double rel, double abs_, uint32_t mode, bool 
 int next_registered(qmc_context* c, uint64_t want, uint32_t dim, uint64_t* n_out, bool allow_smaller,
                     std::vector<uint64_t>* z_out = nullptr);
 uint64_t largest_registered(qmc_context* c);
+
+// Next step of the Case-1 loop (Sec. 3.3.1) after a round that missed its goal:
+// the next registered lattice of at least max(1.5 n, n err/goal) points (the
+// round is discarded); when the table has none, its largest lattice; once
+// there, more shifts, m -> max(m+1, ceil(m (err/goal)^2)) up to QMC_MAX_SHIFTS,
+// continuing the same shift stream so the earlier shifts' sums are kept (at
+// most max_m shifts).  No step may take the evaluations past q.max_evals
+// (0 = no limit); lattices larger than max_n are not used.
+struct GrowthStep {
+  enum Kind { STOP = 0, LATTICE = 1, SHIFTS = 2 } kind = STOP;
+  uint64_t n = 0;
+  uint32_t m = 0;                // shift count after the step
+  std::vector<uint64_t> z;       // LATTICE: generating vector [dim]
+};
+GrowthStep growth_step(qmc_context* c, const qmc_request& q, const qmc_result& r, uint64_t n, uint32_t m,
+                       uint32_t dim, bool cplx, uint64_t max_n, uint32_t max_m);
 // fill the integrand/transform part of an EvalArgs
 int fill_integrand_args(qmcd::EvalArgs& a, const qmc_integrand* f, const qmc_transform& t, int& tsel);
 

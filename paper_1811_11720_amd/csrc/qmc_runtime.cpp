@@ -421,6 +421,60 @@ int next_registered(qmc_context* c, uint64_t want, uint32_t dim, uint64_t* n_out
   return QMC_OK;
 }
 
+GrowthStep growth_step(qmc_context* c, const qmc_request& q, const qmc_result& r, uint64_t n, uint32_t m,
+                       uint32_t dim, bool cplx, uint64_t max_n, uint32_t max_m) {
+  GrowthStep g;
+  const double goal =
+      std::max(q.abs_tol, q.rel_tol * (cplx ? std::max(std::fabs(r.re), std::fabs(r.im)) : std::fabs(r.re)));
+  const double err = cplx ? std::max(r.err_re, r.err_im) : r.err_re;
+  const bool ratio_ok = goal > 0 && std::isfinite(err);
+  const double want = std::max(1.5 * (double)n, ratio_ok ? (double)n * err / goal : 2.0 * (double)n);
+  const uint64_t wantu = want >= 9.0e15 ? (uint64_t)9.0e15 : (uint64_t)std::ceil(want);
+  uint64_t nn = 0;
+  std::vector<uint64_t> zn;
+  bool found = next_registered(c, wantu, dim, &nn, false, &zn) == QMC_OK && nn <= max_n;
+  if (!found) {
+    // the largest usable lattice
+    uint64_t top = 0;
+    std::vector<uint64_t> zt;
+    {
+      std::lock_guard<std::mutex> lk(c->lat_mu);
+      for (auto& kv : c->lattices)
+        if (kv.first <= max_n && kv.second.size() >= dim) {
+          top = kv.first;
+          zt.assign(kv.second.begin(), kv.second.begin() + dim);
+        }
+    }
+    if (top > n) {
+      found = true;
+      nn = top;
+      zn.swap(zt);
+    }
+  }
+  if (found) {
+    if (q.max_evals && r.evaluations + nn * (uint64_t)m > q.max_evals) return g;
+    g.kind = GrowthStep::LATTICE;
+    g.n = nn;
+    g.m = m;
+    g.z.swap(zn);
+    return g;
+  }
+  // at the largest lattice: add shifts (Monte Carlo scaling)
+  const double ratio = ratio_ok ? (err / goal) * (err / goal) : HUGE_VAL;
+  uint64_t m_new = ratio * m >= (double)max_m ? (uint64_t)max_m
+                                              : std::max<uint64_t>(m + 1, (uint64_t)std::ceil(ratio * m));
+  m_new = std::min<uint64_t>(m_new, max_m);
+  if (q.max_evals) {
+    const uint64_t left = q.max_evals > r.evaluations ? q.max_evals - r.evaluations : 0;
+    m_new = std::min<uint64_t>(m_new, m + left / n);
+  }
+  if (m_new <= m) return g;
+  g.kind = GrowthStep::SHIFTS;
+  g.n = n;
+  g.m = (uint32_t)m_new;
+  return g;
+}
+
 int integrate_request(qmc_context* c, const qmc_request& q, qmc_result* out, double* shift_sums) {
   auto t0 = std::chrono::steady_clock::now();
   qmc_integrand* f = const_cast<qmc_integrand*>(q.f);
@@ -446,27 +500,39 @@ int integrate_request(qmc_context* c, const qmc_request& q, qmc_result* out, dou
   make_shifts(q.seed, m, dim, sh.data());
   qmc_result r;
   std::memset(&r, 0, sizeof r);
-  r.m = m;
   double dev = 0;
   LatticeRun run;
+  uint32_t mcur = m, first_new = 0;  // shifts [first_new, mcur) are evaluated next
+  std::vector<double> sre, sim;      // per-shift sums at the current lattice
+  uint64_t signs = 0;
   while (true) {
-    int rc = run_lattice(c, f, n, z.data(), m, sh.data(), q.t, 0, n, run);
+    const uint32_t madd = mcur - first_new;
+    int rc = run_lattice(c, f, n, z.data(), madd, sh.data() + (size_t)first_new * dim, q.t, 0, n, run);
     if (rc) return rc;
     dev += run.kernel_seconds;
+    sre.resize(first_new);
+    sim.resize(first_new);
+    sre.insert(sre.end(), run.sums.begin(), run.sums.begin() + madd);
+    if (cplx)
+      sim.insert(sim.end(), run.sums.begin() + madd, run.sums.begin() + 2 * (size_t)madd);
+    else
+      sim.resize(mcur, 0.0);
+    signs = (first_new ? signs : 0) + run.sign_points;
     r.iterations += 1;
-    r.evaluations += n * (uint64_t)m;
+    r.evaluations += n * (uint64_t)madd;
     r.n = n;
-    std::vector<double> qs(m);
-    for (uint32_t s = 0; s < m; ++s) qs[s] = run.sums[s] / (double)n;
-    estimate(qs.data(), m, r.re, r.err_re);
+    r.m = mcur;
+    std::vector<double> qs(mcur);
+    for (uint32_t s = 0; s < mcur; ++s) qs[s] = sre[s] / (double)n;
+    estimate(qs.data(), mcur, r.re, r.err_re);
     r.im = 0;
     r.err_im = 0;
     if (cplx) {
-      for (uint32_t s = 0; s < m; ++s) qs[s] = run.sums[m + s] / (double)n;
-      estimate(qs.data(), m, r.im, r.err_im);
+      for (uint32_t s = 0; s < mcur; ++s) qs[s] = sim[s] / (double)n;
+      estimate(qs.data(), mcur, r.im, r.err_im);
     }
     r.flags &= ~(uint32_t)(QMC_NONFINITE | QMC_DEFORM_SIGN);
-    if (run.sign_points) r.flags |= QMC_DEFORM_SIGN;
+    if (signs) r.flags |= QMC_DEFORM_SIGN;
     bool finite = std::isfinite(r.re) && std::isfinite(r.im);
     if (!finite) r.flags |= QMC_NONFINITE;
     if (!grow) break;
@@ -474,26 +540,30 @@ int integrate_request(qmc_context* c, const qmc_request& q, qmc_result* out, dou
       r.flags |= QMC_CONVERGED;
       break;
     }
-    // next size: assume err ~ 1/n (reading of Sec. 3.3.1; see design notes)
-    double goal = std::max(q.abs_tol, q.rel_tol * (cplx ? std::max(std::fabs(r.re), std::fabs(r.im)) : std::fabs(r.re)));
-    double err = cplx ? std::max(r.err_re, r.err_im) : r.err_re;
-    double want = std::max(1.5 * (double)n, goal > 0 && std::isfinite(err) ? (double)n * err / goal : 2.0 * n);
-    uint64_t nn = 0;
-    uint64_t wantu = want >= 9.0e15 ? (uint64_t)9.0e15 : (uint64_t)std::ceil(want);
-    std::vector<uint64_t> zn;
-    if (next_registered(c, wantu, dim, &nn, false, &zn) != QMC_OK ||
-        (q.max_evals && r.evaluations + nn * (uint64_t)m > q.max_evals)) {
+    GrowthStep g = growth_step(c, q, r, n, mcur, dim, cplx, UINT64_MAX, QMC_MAX_SHIFTS);
+    if (g.kind == GrowthStep::STOP) {
       r.flags |= QMC_MAXEVAL_HIT;
       break;
     }
-    n = nn;
-    z.swap(zn);
+    if (g.kind == GrowthStep::LATTICE) {
+      n = g.n;
+      z.swap(g.z);
+      first_new = 0;
+    } else {
+      first_new = mcur;
+      mcur = g.m;
+      sh.resize((size_t)mcur * dim);
+      make_shifts(q.seed, mcur, dim, sh.data());
+    }
   }
   r.device_seconds = dev;
   r.path = run.path;
   r.wall_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (out) *out = r;
-  if (shift_sums) std::memcpy(shift_sums, run.sums.data(), run.sums.size() * sizeof(double));
+  if (shift_sums) {  // the requested m shifts
+    std::memcpy(shift_sums, sre.data(), (size_t)m * sizeof(double));
+    if (cplx) std::memcpy(shift_sums + m, sim.data(), (size_t)m * sizeof(double));
+  }
   return QMC_OK;
 }
 

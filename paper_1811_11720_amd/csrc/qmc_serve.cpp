@@ -6,7 +6,8 @@
 // the context's budget; one round evaluates the current lattice of every
 // admitted, unfinished request with the persistent batch kernels
 // (run_batch), then applies each request's own error goal and growth rule
-// (Sec. 3.3.1).  Requests that finish free their memory at once, so tickets
+// (Sec. 3.3.1; at the largest lattice a request stops instead of adding
+// shifts, so its memory stays within what admission reserved).  Requests that finish free their memory at once, so tickets
 // that arrive while others are on the GPU join the next round.  A request's
 // results do not depend on what it was batched with (its tiling depends only
 // on its own n and m).  Descriptors stay resident on the device between
@@ -173,21 +174,16 @@ static void scheduler(qmc_context* c, qmc_serve_state* s) {
         r.done = true;
         continue;
       }
-      double goal = std::max(r.q.abs_tol, r.q.rel_tol * (cplx ? std::max(std::fabs(r.r.re), std::fabs(r.r.im))
-                                                              : std::fabs(r.r.re)));
-      double err = cplx ? std::max(r.r.err_re, r.r.err_im) : r.r.err_re;
-      double want = std::max(1.5 * (double)r.n, goal > 0 && std::isfinite(err) ? (double)r.n * err / goal : 2.0 * r.n);
-      uint64_t wantu = want >= 9.0e15 ? (uint64_t)9.0e15 : (uint64_t)std::ceil(want);
-      uint64_t nn = 0;
-      std::vector<uint64_t> zn;
-      if (next_registered(c, wantu, r.f->dim, &nn, false, &zn) != QMC_OK || nn > c->serve_max_n ||
-          (r.q.max_evals && r.r.evaluations + nn * (uint64_t)m > r.q.max_evals)) {
+      // no added shifts here (max_m = m): a request's device memory stays
+      // within its admission estimate
+      GrowthStep g = growth_step(c, r.q, r.r, r.n, m, r.f->dim, cplx, c->serve_max_n, m);
+      if (g.kind != GrowthStep::LATTICE) {
         r.r.flags |= QMC_MAXEVAL_HIT;
         r.done = true;
         continue;
       }
-      r.n = nn;
-      r.z.swap(zn);
+      r.n = g.n;
+      r.z.swap(g.z);
     }
     for (auto it = s->active.begin(); it != s->active.end();) {
       Ticket& t = **it;

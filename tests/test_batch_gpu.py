@@ -130,6 +130,34 @@ def test_batched_growth_matches_oracle(ctx):
     ctx2.close()
 
 
+def test_batched_growth_fallback_matches_oracle(ctx):
+    """The batch path's Monte Carlo fallback (shifts added at the table's
+    largest lattice) against the oracle."""
+    table = [cbc.next_prime(500), cbc.next_prime(1000)]
+    zs = {n: cbc.fast_cbc(n, 2) for n in table}
+    ctx2 = _ctx(True)
+    ctx2.register_table(zs)
+    BAKER = (W.T_BAKER, 0, 0)
+    descs = [W.product_of_linear([1.0, 1.0], [0.8, 0.5], -1.5), W.product_of_linear([1.0, 0.6], [0.3, 0.9], -1.0)]
+    fs = [ctx2.integrand(d) for d in descs]
+    goals = []
+    for d in descs:
+        first = oracle.integrate(d, table[0], zs.__getitem__, 8, 5, BAKER)
+        goals.append(first["err_re"] / abs(first["re"]) / 12.0)
+    reqs = [dict(f=f, n=table[0], z=zs[table[0]], m=8, seed=5, transform=BAKER, rel_tol=gl)
+            for f, gl in zip(fs, goals)]
+    res = ctx2.integrate_batch(reqs, sums=True)
+    for d, r, gl in zip(descs, res, goals):
+        o = oracle.integrate(d, table[0], zs.__getitem__, 8, 5, BAKER, rel_tol=gl, table_ns=table, threads=THREADS)
+        assert o["m"] > 8 and r["n"] == o["n"] and r["m"] == o["m"]
+        assert r["iterations"] == o["iterations"] and r["evaluations"] == o["evaluations"]
+        assert np.all(np.abs(r["sums_re"] - o["sums_re"][:8]) <= TOL * o["abs_re"][:8])
+        assert r["err_re"] == pytest.approx(o["err_re"], rel=1e-6)
+    for f in fs:
+        f.close()
+    ctx2.close()
+
+
 def test_batch_of_sector_mix_workload(ctx):
     """Integrands from the batch-mix generator (dims 2..10, 4..40 monomials,
     half complex) on a small lattice, against the oracle on sampled shifts."""

@@ -234,6 +234,33 @@ def test_sector_real_sampled_shifts_full_size(ctx, n, ids):
     _check_sums(np.asarray(g["sums_re"])[ids], o, label=f"sector n={n}")
 
 
+def test_growth_fallback_adds_shifts_like_the_oracle(ctx):
+    """Sec. 3.3.1: past the table's largest lattice the loop adds shifts; the
+    device path visits the same sizes and shift counts as the oracle."""
+    desc = W.product_of_linear([1.0, 1.0], [0.8, 0.5], -1.5)
+    table = [cbc.next_prime(500), cbc.next_prime(1000)]
+    zs = {n: cbc.fast_cbc(n, 2) for n in table}
+    BAKER = (W.T_BAKER, 0, 0)
+    first = oracle.integrate(desc, table[0], zs.__getitem__, 8, 5, BAKER)
+    goal = first["err_re"] / abs(first["re"]) / 12.0
+    o = oracle.integrate(desc, table[0], zs.__getitem__, 8, 5, BAKER, rel_tol=goal, table_ns=table,
+                         threads=THREADS)
+    c2 = make_ctx("specialised" if ctx.path else "generic")
+    c2.register_table(zs)
+    f = c2.integrand(desc)
+    g = c2.integrate(f, table[0], zs[table[0]], 8, 5, BAKER, rel_tol=goal, sums=True)
+    assert o["m"] > 8 and g["n"] == o["n"] == table[-1]
+    assert g["m"] == o["m"] and g["iterations"] == o["iterations"] and g["evaluations"] == o["evaluations"]
+    assert bool(g["flags"] & 1) == o["converged"]
+    # the returned sums are the first 8 shifts' at the last lattice
+    assert np.all(np.abs(g["sums_re"] - o["sums_re"][:8]) <= TOL * o["abs_re"][:8])
+    scale = np.sum(o["abs_re"]) / o["n"] / o["m"]
+    assert abs(g["re"] - o["re"]) <= TOL * scale
+    assert g["err_re"] == pytest.approx(o["err_re"], rel=1e-6)
+    f.close()
+    c2.close()
+
+
 def test_growth_loop_matches_oracle(ctx):
     desc = W.product_of_linear([1.0, 1.0, 1.0], [0.8, 0.5, 0.3], -1.5)
     table_ns = [cbc.next_prime(v) for v in (1000, 2000, 4000, 8000, 16000, 32000, 64000, 128000)]
