@@ -54,6 +54,7 @@ class _Desc(C.Structure):
         ("prefactor", C.c_double),
         ("deform", C.c_int32),
         ("lam", C.c_double),
+        ("genz", C.c_int32),
     ]
 
 
@@ -112,7 +113,8 @@ def _mk_desc(desc):
     coef = np.ascontiguousarray(desc.coef, dtype=np.float64)
     expo = np.ascontiguousarray(desc.expo, dtype=np.uint8)
     d = _Desc(desc.dim, desc.n_u, desc.n_f, _dp(coef), expo.ctypes.data_as(C.POINTER(C.c_uint8)),
-              desc.pow_u, desc.pow_f, desc.prefactor, 1 if desc.deform else 0, desc.lam)
+              desc.pow_u, desc.pow_f, desc.prefactor, 1 if desc.deform else 0, desc.lam,
+              int(getattr(desc, "genz", 0)))
     return d, (coef, expo)
 
 

@@ -50,6 +50,7 @@ typedef struct {
   double pow_u, pow_f, prefactor;
   int32_t deform;         /* 1: complex result under contour deformation */
   double lambda;
+  int32_t genz;           /* 0: U^a F^b; 1..6: Genz family with coef = [c_0..c_d-1, w_0..w_d-1] */
 } oracle_desc;
 
 /* ------------------------------------------------------------------ */
@@ -333,10 +334,46 @@ static double complex f_complex(const oracle_desc* D, const double* x, int* sign
   return f;
 }
 
+/* The six test families of Genz as the paper lists them (Sec. 5.3), with
+ * parameters c_i > 0 and 0 <= w_i <= 1. */
+static double f_genz(const oracle_desc* D, const double* x) {
+  const uint32_t d = D->dim;
+  const double* c = D->coef;
+  const double* w = D->coef + d;
+  double s = 0.0, p = 1.0;
+  switch (D->genz) {
+    case 1: /* oscillatory */
+      s = 2.0 * M_PI * w[0];
+      for (uint32_t j = 0; j < d; ++j) s += c[j] * x[j];
+      return cos(s);
+    case 2: /* product peak */
+      for (uint32_t j = 0; j < d; ++j) p *= 1.0 / (1.0 / (c[j] * c[j]) + (x[j] - w[j]) * (x[j] - w[j]));
+      return p;
+    case 3: /* corner peak */
+      s = 1.0;
+      for (uint32_t j = 0; j < d; ++j) s += c[j] * x[j];
+      return pow(s, -(double)(d + 1));
+    case 4: /* Gaussian */
+      for (uint32_t j = 0; j < d; ++j) s += c[j] * c[j] * (x[j] - w[j]) * (x[j] - w[j]);
+      return exp(-s);
+    case 5: /* continuous (C^0) */
+      for (uint32_t j = 0; j < d; ++j) s += c[j] * fabs(x[j] - w[j]);
+      return exp(-s);
+    case 6: /* discontinuous */
+      if (x[0] > w[0] || (d > 1 && x[1] > w[1])) return 0.0;
+      for (uint32_t j = 0; j < d; ++j) s += c[j] * x[j];
+      return exp(s);
+  }
+  return NAN;
+}
+
 /* f at one point x in [0,1]^d (no transform): real or complex */
 int oracle_eval_point(const oracle_desc* D, const double* x, double* re, double* im) {
   int flag = 0;
-  if (D->deform) {
+  if (D->genz) {
+    *re = f_genz(D, x);
+    *im = 0.0;
+  } else if (D->deform) {
     double complex f = f_complex(D, x, &flag);
     *re = creal(f);
     *im = cimag(f);

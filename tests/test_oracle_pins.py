@@ -254,6 +254,48 @@ def test_sidi_lattice_rule_on_a_closed_form(r):
     assert abs(val.real - exact) < 1e-7 * abs(exact)
 
 
+@pytest.mark.parametrize("family", [1, 2, 3, 4, 5, 6])
+def test_genz_families_converge_to_their_closed_forms(family):
+    """Sec. 5.3 test functions: the oracle's rule on each Genz family agrees
+    with the family's exact integral within its error estimate, and to many
+    digits for the smooth families."""
+    desc = W.genz(family, 3, 11)
+    exact = W.genz_exact(desc)
+    val, err, _, _ = _integrate(desc, cbc.next_prime(50000), m=16, seed=3)
+    assert abs(val.real - exact) < 6 * err + 1e-14 * abs(exact)
+    if family <= 4:
+        assert abs(val.real - exact) < 1e-8 * abs(exact)
+
+
+def test_genz_exact_values_by_quadrature():
+    """The closed forms themselves, against mpmath quadrature in two dimensions."""
+    mp.mp.dps = 20
+    for family in (1, 2, 3, 4, 5, 6):
+        desc = W.genz(family, 2, 5)
+        c, w = desc.coef[:2], desc.coef[2:]
+
+        def f(x0, x1):
+            x = (x0, x1)
+            if family == 1:
+                return mp.cos(2 * mp.pi * w[0] + c[0] * x0 + c[1] * x1)
+            if family == 2:
+                return mp.fprod(1 / (c[j] ** -2 + (x[j] - w[j]) ** 2) for j in range(2))
+            if family == 3:
+                return (1 + c[0] * x0 + c[1] * x1) ** -3
+            if family == 4:
+                return mp.exp(-sum(c[j] ** 2 * (x[j] - w[j]) ** 2 for j in range(2)))
+            if family == 5:
+                return mp.exp(-sum(c[j] * abs(x[j] - w[j]) for j in range(2)))
+            return mp.exp(c[0] * x0 + c[1] * x1) if (x0 <= w[0] and x1 <= w[1]) else 0
+
+        if family in (5, 6):  # kinks and jumps at w: split the domain there
+            pts = [[0, w[0], 1], [0, w[1], 1]]
+        else:
+            pts = [[0, 1], [0, 1]]
+        q = mp.quad(f, pts[0], pts[1])
+        assert float(q) == pytest.approx(W.genz_exact(desc), rel=1e-10)
+
+
 def test_plain_product_workload_integrates_to_one():
     job = W.job_plain_product()
     sh = oracle.shifts(job.seed, job.m, job.desc.dim)

@@ -60,6 +60,7 @@ class Desc:
     prefactor: float = 1.0
     deform: bool = False
     lam: float = 0.0
+    genz: int = 0  # 1..6: Genz family, coef = [c, w], no monomials
 
     def __post_init__(self):
         self.coef = np.ascontiguousarray(self.coef, dtype=np.float64)
@@ -218,6 +219,57 @@ def sector_complex(seed: int = 3) -> Desc:
 
 # --------------------------------------------------------------------------
 # named configurations
+
+# ---------------------------------------------------------------- Genz test families
+
+# ||c||_1 per family (the paper's difficulty settings, Sec. 5.3)
+GENZ_DIFFICULTY = {1: 6.0, 2: 18.0, 3: 2.2, 4: 15.2, 5: 16.1, 6: 16.4}
+GENZ_NAMES = {1: "oscillatory", 2: "product peak", 3: "corner peak", 4: "Gaussian", 5: "C0", 6: "discontinuous"}
+
+
+def genz(family: int, dim: int, seed: int) -> Desc:
+    """Genz family `family` in `dim` dimensions: w_i ~ U(0,1), c_i ~ U(0,1)
+    rescaled so that sum c_i is the family's difficulty."""
+    rng = np.random.default_rng(seed)
+    w = rng.uniform(0.0, 1.0, dim)
+    c = rng.uniform(0.0, 1.0, dim)
+    c *= GENZ_DIFFICULTY[family] / c.sum()
+    return Desc(dim=dim, coef=np.concatenate([c, w]), expo=np.zeros(2 * dim * dim, np.uint8), n_u=2 * dim, n_f=0,
+                genz=family)
+
+
+def genz_exact(desc: Desc) -> float:
+    """The exact integral of a Genz integrand over the unit cube (closed forms
+    of each family; the input's known answer, like Job.exact)."""
+    from scipy.special import erf
+
+    d = desc.dim
+    c = desc.coef[:d]
+    w = desc.coef[d:]
+    f = desc.genz
+    if f == 1:
+        z = np.exp(2j * np.pi * w[0])
+        for cj in c:
+            z *= (np.exp(1j * cj) - 1.0) / (1j * cj)
+        return float(z.real)
+    if f == 2:
+        return float(np.prod(c * (np.arctan(c * (1.0 - w)) + np.arctan(c * w))))
+    if f == 3:
+        tot = 0.0
+        for mask in range(1 << d):
+            bits = [(mask >> j) & 1 for j in range(d)]
+            tot += (-1) ** sum(bits) / (1.0 + float(np.dot(c, bits)))
+        return tot / (math.factorial(d) * float(np.prod(c)))
+    if f == 4:
+        return float(np.prod(np.sqrt(np.pi) / (2.0 * c) * (erf(c * (1.0 - w)) + erf(c * w))))
+    if f == 5:
+        return float(np.prod((2.0 - np.exp(-c * w) - np.exp(-c * (1.0 - w))) / c))
+    if f == 6:
+        lim = np.ones(d)
+        lim[: min(d, 2)] = w[: min(d, 2)]
+        return float(np.prod((np.exp(c * lim) - 1.0) / c))
+    raise ValueError(f)
+
 
 PLAIN_N = 10007
 SECTOR_REAL_NS = [100003, 316241, 1000003, 3162283, 10000019, 31622777, 100000007]
