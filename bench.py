@@ -307,6 +307,64 @@ def bench_batch(a, Q, W, torch):
     return 0
 
 
+def bench_genz(a, Q, W, torch):
+    """The paper's Genz timings (Sec. 5.3): families 1-6 in 5, 8 and 10
+    dimensions, `reps` random parameter sets each at the paper's difficulty,
+    Korobov r=3 (or baker with --baker), relative goal 1e-8, at most 7e8
+    evaluations, m = 32 shifts from the smallest table lattice >= 8191.
+    Reports correct digits against the closed forms and time per integral."""
+    table = W.lattice_table()
+    ctx = Q.Context(0)
+    ctx.register_table(table)
+    n0 = min(v for v in table if v >= 8191)
+    tr = (W.T_BAKER, 0, 0) if a.baker else (W.T_KOROBOV, 3, 3)
+    rows = []
+    tot_ev = tot_wall = tot_dev = 0.0
+    for dim in (5, 8, 10):
+        for fam in range(1, 7):
+            digits, walls, evs = [], [], []
+            for rep in range(a.reps):
+                desc = W.genz(fam, dim, 1000 * fam + 100 * dim + rep)
+                exact = W.genz_exact(desc)
+                f = ctx.integrand(desc)
+                r = ctx.integrate_request(dict(f=f, n=n0, z=table[n0][:dim], m=32, seed=5000 + rep, transform=tr,
+                                               rel_tol=1e-8, max_evals=700_000_000))
+                f.close()
+                rel = abs(r["re"] - exact) / abs(exact)
+                digits.append(min(16.0, -math.log10(max(rel, 1e-16))))
+                walls.append(r["wall_seconds"])
+                evs.append(r["evaluations"])
+                tot_ev += r["evaluations"]
+                tot_wall += r["wall_seconds"]
+                tot_dev += r["device_seconds"]
+            rows.append({"family": fam, "name": W.GENZ_NAMES[fam], "dim": dim,
+                         "digits": float(np.mean(digits)), "seconds": float(np.mean(walls)),
+                         "evaluations": float(np.mean(evs))})
+            print(f"[genz] family {fam} d={dim}: {np.mean(digits):.1f} digits, {np.mean(walls) * 1e3:.1f} ms",
+                  file=sys.stderr, flush=True)
+    ctx.close()
+    out = {
+        "metric": "lattice-point integrand evals/s (FP64) + p50/p99 request latency at rel err",
+        "value": tot_ev / tot_wall,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": len(rows) * a.reps,
+        "warmup": 0,
+        "ms_per_step": tot_wall / (len(rows) * a.reps) * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"Genz families 1-6, d = 5, 8, 10, {a.reps} parameter sets each, "
+                               f"{'baker' if a.baker else 'Korobov r=3'}, rel 1e-8, max 7e8 evaluations, m=32"},
+        "device_evals_per_s": tot_ev / tot_dev,
+        "results": rows,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def bench_serve(a, Q, W, torch):
     """Serving: requests of 10-500 integrands from the batch pool, each with a
     relative target log-uniform in [1e-8, 1e-4], arriving as a Poisson process
@@ -422,7 +480,9 @@ def main():
     ap.add_argument("--m", type=int, default=32)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--workload", choices=["sector_real", "batch", "serve", "copy"], default="sector_real")
+    ap.add_argument("--workload", choices=["sector_real", "batch", "serve", "genz", "copy"], default="sector_real")
+    ap.add_argument("--reps", type=int, default=10, help="genz: parameter sets per family and dimension")
+    ap.add_argument("--baker", action="store_true", help="genz: baker transform instead of Korobov r=3")
     ap.add_argument("--count", type=int, default=2000, help="batch: integrals")
     ap.add_argument("--n-lo", type=float, default=1e5)
     ap.add_argument("--n-hi", type=float, default=1e7)
@@ -451,6 +511,8 @@ def main():
         return bench_serve(a, Q, W, torch)
     if a.workload == "copy":
         return bench_copy(a, torch)
+    if a.workload == "genz":
+        return bench_genz(a, Q, W, torch)
     job = W.job_sector_real(a.n)
     job.m = a.m
     ctx = Q.Context(0)

@@ -132,6 +132,18 @@ typedef struct {
 int qmc_create_integrand(qmc_context* ctx, const qmc_integrand_desc* desc, qmc_integrand** out);
 
 /* Free; QMC_EBUSY while a pending request references it. */
+/*
+ * One of the six Genz test functions the paper benchmarks (Sec. 5.3):
+ * family 1 oscillatory cos(2 pi w_1 + sum c_i x_i), 2 product peak
+ * prod (c_i^-2 + (x_i - w_i)^2)^-1, 3 corner peak (1 + sum c_i x_i)^-(d+1),
+ * 4 Gaussian exp(-sum c_i^2 (x_i - w_i)^2), 5 continuous
+ * exp(-sum c_i |x_i - w_i|), 6 discontinuous (0 if x_1 > w_1 or x_2 > w_2,
+ * else exp(sum c_i x_i)).  c: host [dim], finite, > 0; w: host [dim] in
+ * [0, 1]; both copied.  The handle works with qmc_integrate and qmc_set_vr;
+ * the batch and serving calls and qmc_histogram return QMC_EUNSUPPORTED.
+ */
+int qmc_create_genz(qmc_context* ctx, int family, uint32_t dim, const double* c, const double* w,
+                    qmc_integrand** out);
 int qmc_destroy_integrand(qmc_integrand* f);
 
 /*
@@ -241,6 +253,12 @@ typedef struct {
   double rel_tol, abs_tol; /* both <= 0: one lattice only */
   uint64_t max_evals;      /* 0 = unlimited */
 } qmc_request;
+
+/*
+ * One request with all of its options (rel_tol, abs_tol, max_evals,
+ * errormode) through the single-integral kernels, the loop of qmc_integrate.
+ */
+int qmc_integrate_request(qmc_context* ctx, const qmc_request* req, qmc_result* out, double* shift_sums);
 
 /*
  * Run `count` requests together; results in out[count].  Each round, the

@@ -107,6 +107,9 @@ def _declare(L):
         "qmc_register_lattice": ([vp, C.c_uint64, C.c_uint32, up], C.c_int),
         "qmc_next_lattice": ([vp, C.c_uint64, C.c_uint32, up], C.c_int),
         "qmc_create_integrand": ([vp, C.POINTER(IntegrandDesc), C.POINTER(vp)], C.c_int),
+        "qmc_integrate_request": ([vp, C.POINTER(Request), C.POINTER(Result), C.POINTER(C.c_double)], C.c_int),
+        "qmc_create_genz": ([vp, C.c_int, C.c_uint32, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(vp)],
+                            C.c_int),
         "qmc_destroy_integrand": ([vp], C.c_int),
         "qmc_set_vr": ([vp, dp], C.c_int),
         "qmc_integrate": ([vp, vp, C.c_uint32, C.c_uint64, up, C.c_uint32, C.c_uint64, Transform, C.c_double,
@@ -211,9 +214,15 @@ class Integrand:
         self.dim = int(desc.dim)
         self.complex = bool(getattr(desc, "deform", False))
         self._keep = []
-        d = _desc_struct(desc, self._keep)
         h = C.c_void_p()
-        _check(lib().qmc_create_integrand(ctx.handle, C.byref(d), C.byref(h)))
+        family = int(getattr(desc, "genz", 0))
+        if family:  # Genz test function: coef = [c | w]
+            cw = np.ascontiguousarray(desc.coef, dtype=np.float64)
+            _check(lib().qmc_create_genz(ctx.handle, family, self.dim, _dp(cw[: self.dim]), _dp(cw[self.dim:]),
+                                         C.byref(h)))
+        else:
+            d = _desc_struct(desc, self._keep)
+            _check(lib().qmc_create_integrand(ctx.handle, C.byref(d), C.byref(h)))
         self.handle = h
 
     def set_vr(self, params):
@@ -301,6 +310,19 @@ class Context:
                              _tr(r.get("transform", (T_KOROBOV, 3, 3))), r.get("rel_tol", 0.0),
                              r.get("abs_tol", 0.0), r.get("max_evals", 0))
         return arr, keep
+
+    def integrate_request(self, req, sums: bool = False):
+        """One request dict (as in integrate_batch) through the single-integral path."""
+        arr, keep = self._requests([req])
+        res = Result()
+        out = np.zeros(req["m"] * (2 if req["f"].complex else 1))
+        _check(lib().qmc_integrate_request(self.handle, arr, C.byref(res), _dp(out)))
+        d = res.as_dict()
+        if sums:
+            m = req["m"]
+            d["sums_re"] = out[:m].copy()
+            d["sums_im"] = out[m:].copy() if req["f"].complex else np.zeros(m)
+        return d
 
     def autotune_batch(self, reqs) -> int:
         arr, keep = self._requests(reqs)

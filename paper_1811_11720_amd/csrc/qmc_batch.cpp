@@ -259,6 +259,7 @@ int run_requests(qmc_context* c, const qmc_request* reqs, uint32_t count, qmc_re
     St& s = st[i];
     s.f = const_cast<qmc_integrand*>(q.f);
     if (s.f->ctx != c) return fail(QMC_EINVAL, "request %u: integrand belongs to another context", i);
+    if (s.f->genz) return fail(QMC_EUNSUPPORTED, "request %u: Genz integrands run through qmc_integrate", i);
     if (q.m < 1 || q.m > QMC_MAX_SHIFTS) return fail(QMC_EINVAL, "request %u: m=%u", i, q.m);
     const uint32_t dim = s.f->dim;
     if (q.z) {

@@ -70,6 +70,7 @@ struct EvalArgs {
   double wscale;              // Korobov r=3: prod_j omega = wscale * (prod_j u_j (1-u_j))^3, wscale = 140^dim
   unsigned long long* sign_count;  // complex kernels: points with Im F(z) > 0
   int32_t tk;                 // transform kind for TK_RUNTIME kernels (TK_NONE..TK_SIDI)
+  int32_t genz;               // 1..6: Genz family (coef = [c | w | family constants]); 0 otherwise
   const float* coef32;        // coefficients rounded to fp32 (fp32-evaluation kernels)
   uint64_t tile_points;       // batch: points per tile (a multiple of the block size)
   uint32_t ktiles;            // batch: tiles along k (= columns of partial[][])
@@ -902,6 +903,63 @@ __device__ __forceinline__ void eval_real_sched(const EvalArgs& a, const Fn& fn,
   }
   block_store<S>(acc, ns, s0, a.partial, a.nblocks, sc.col);
 }
+
+// The six Genz test families as the paper lists them (Sec. 5.3).  coef holds
+// c[0..d), w[d..2d) and a per-variable constant k[2d..3d): 1/c^2 for the
+// product peak, c^2 for the Gaussian.
+template <int DMAX>
+struct GenzReal {
+  __device__ __forceinline__ double operator()(const double (&x)[DMAX], const EvalArgs& a) const {
+    const uint32_t d = a.dim;
+    const cptr<double> c = as_const(a.coef);
+    const cptr<double> w = c + d;
+    const cptr<double> k = c + 2 * d;
+    double s = 0.0, p = 1.0;
+    switch (a.genz) {
+      case 1:  // oscillatory
+        s = 6.283185307179586 * w[0];  // 2 pi w_1
+#pragma unroll
+        for (int j = 0; j < DMAX; ++j)
+          if (j < (int)d) s = __builtin_fma(c[j], x[j], s);
+        return cos(s);
+      case 2:  // product peak
+#pragma unroll
+        for (int j = 0; j < DMAX; ++j)
+          if (j < (int)d) {
+            const double t = x[j] - w[j];
+            p *= __builtin_fma(t, t, k[j]);
+          }
+        return fast_rcp(p);
+      case 3: {  // corner peak
+        s = 1.0;
+#pragma unroll
+        for (int j = 0; j < DMAX; ++j)
+          if (j < (int)d) s = __builtin_fma(c[j], x[j], s);
+        for (uint32_t i = 0; i <= d; ++i) p *= s;
+        return fast_rcp(p);
+      }
+      case 4:  // Gaussian
+#pragma unroll
+        for (int j = 0; j < DMAX; ++j)
+          if (j < (int)d) {
+            const double t = x[j] - w[j];
+            s = __builtin_fma(k[j] * t, t, s);
+          }
+        return exp(-s);
+      case 5:  // continuous
+#pragma unroll
+        for (int j = 0; j < DMAX; ++j)
+          if (j < (int)d) s = __builtin_fma(c[j], __builtin_fabs(x[j] - w[j]), s);
+        return exp(-s);
+      default:  // 6: discontinuous
+        if (x[0] > w[0] || (d > 1 && x[DMAX > 1 ? 1 : 0] > w[1])) return 0.0;
+#pragma unroll
+        for (int j = 0; j < DMAX; ++j)
+          if (j < (int)d) s = __builtin_fma(c[j], x[j], s);
+        return exp(s);
+    }
+  }
+};
 
 template <int DMAX, int TK, bool IDX32, int S, bool EXACT, class Fn, int VRM = VRM_RUNTIME>
 __device__ __forceinline__ void eval_real_body(const EvalArgs& a, const Fn& fn) {

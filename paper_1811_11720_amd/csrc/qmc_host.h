@@ -65,6 +65,7 @@ struct qmc_context {
 struct qmc_integrand {
   qmc_context* ctx = nullptr;
   uint32_t dim = 0, n_u = 0, n_f = 0, flags = 0;
+  int genz = 0;  // 1..6: a Genz test family (coef = [c | w]), no monomial table
   double pow_u = 1, pow_f = 1, prefactor = 1, lambda = 0;
   int pu_mode = 0, pu_k = 0, pf_mode = 0, pf_k = 0;
   std::vector<double> coef;

@@ -35,6 +35,9 @@ hipError_t launch_eval_real(const qmcd::EvalArgs& a, int dclass, int tsel, bool 
 int occupancy_eval(bool cplx, int dclass, int tsel, bool idx32);
 hipError_t launch_eval_complex(const qmcd::EvalArgs& a, int dclass, int tsel, bool idx32, dim3 grid,
                                hipStream_t st);
+// Genz test families (real, transform from EvalArgs::tk)
+int occupancy_genz(int dclass, bool idx32);
+hipError_t launch_eval_genz(const qmcd::EvalArgs& a, int dclass, bool idx32, dim3 grid, hipStream_t st);
 hipError_t launch_hist(const qmcd::EvalArgs& a, const qmcd::HistArgs& h, int dclass, bool cplx, int pass, dim3 grid,
                        hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long* p, uint32_t count, unsigned long long v, hipStream_t st);

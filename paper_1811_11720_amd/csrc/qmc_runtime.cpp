@@ -220,7 +220,7 @@ int run_lattice(qmc_context* c, qmc_integrand* f, uint64_t n, const uint64_t* z,
   bool use_jit = false;
   int S = cplx ? qmck::S_COMPLEX : qmck::S_REAL;
   const int jkey = tsel * 2 + (f->has_vr ? 1 : 0);
-  if (c->jit && npts * (uint64_t)m >= c->jit_min_evals && !f->jit_failed.count(jkey)) {
+  if (!f->genz && c->jit && npts * (uint64_t)m >= c->jit_min_evals && !f->jit_failed.count(jkey)) {
     auto it = f->jit.find(jkey);
     if (it == f->jit.end()) {
       qmcj::Spec sp{dim, f->n_u, f->n_f, f->expo.data(), f->pu_mode, f->pu_k, f->pf_mode, f->pf_k, tsel,
@@ -239,7 +239,9 @@ int run_lattice(qmc_context* c, qmc_integrand* f, uint64_t n, const uint64_t* z,
     if (use_jit) S = cplx ? qmck::S_COMPLEX_JIT : c->jit_S;
   }
   const uint32_t groups = (m + S - 1) / S;
-  const int occ = use_jit ? jk.occ_blocks : qmck::occupancy_eval(cplx, dclass, tsel, idx32);
+  const int occ = use_jit     ? jk.occ_blocks
+                  : f->genz ? qmck::occupancy_genz(dclass, idx32)
+                            : qmck::occupancy_eval(cplx, dclass, tsel, idx32);
   const uint32_t nb = plan_blocks(c, occ, groups, npts);
 
   size_t off_sh = 0, sz_sh = (size_t)m * dim * sizeof(double);
@@ -282,12 +284,16 @@ int run_lattice(qmc_context* c, qmc_integrand* f, uint64_t n, const uint64_t* z,
   a.lambda = f->lambda;
   a.vr = f->has_vr ? f->d_vr : nullptr;
   a.wscale = std::pow(140.0, (double)dim);
+  a.tk = tsel;  // TSEL_* and TK_* share their numbering
+  a.genz = f->genz;
   // the sign counter sits right after the per-shift sums
   a.sign_count = (unsigned long long*)(ws + off_out + rows * sizeof(double));
   HIPCHK(qmck::launch_fill_u64(a.sign_count, 1, 0ull, c->stream));
   HIPCHK(hipEventRecord(c->ev0, c->stream));
   if (use_jit) {
     HIPCHK(qmcj::launch(jk, idx32, a, dim3(nb, groups), c->stream));
+  } else if (f->genz) {
+    HIPCHK(qmck::launch_eval_genz(a, dclass, idx32, dim3(nb, groups), c->stream));
   } else if (cplx) {
     HIPCHK(qmck::launch_eval_complex(a, dclass, tsel, idx32, dim3(nb, groups), c->stream));
   } else {
@@ -791,6 +797,48 @@ int qmc_create_integrand(qmc_context* c, const qmc_integrand_desc* d, qmc_integr
   return QMC_OK;
 }
 
+int qmc_create_genz(qmc_context* c, int family, uint32_t dim, const double* cv, const double* wv,
+                    qmc_integrand** out) {
+  if (!c || !cv || !wv || !out) return fail(QMC_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (family < 1 || family > 6) return fail(QMC_EINVAL, "Genz family %d outside [1, 6]", family);
+  if (dim < 1 || dim > QMC_MAX_DIM) return fail(QMC_EINVAL, "dim=%u outside [1, %d]", dim, QMC_MAX_DIM);
+  for (uint32_t j = 0; j < dim; ++j) {
+    if (!(cv[j] > 0.0) || !std::isfinite(cv[j])) return fail(QMC_EINVAL, "c[%u] must be finite and > 0", j);
+    if (!(wv[j] >= 0.0 && wv[j] <= 1.0)) return fail(QMC_EINVAL, "w[%u] outside [0, 1]", j);
+  }
+  qmc_integrand* f = new qmc_integrand();
+  f->ctx = c;
+  f->dim = dim;
+  f->genz = family;
+  f->coef.assign(cv, cv + dim);
+  f->coef.insert(f->coef.end(), wv, wv + dim);
+  // device table: c | w | per-variable constant of the family
+  std::vector<double> tab(f->coef);
+  for (uint32_t j = 0; j < dim; ++j)
+    tab.push_back(family == 2 ? 1.0 / (cv[j] * cv[j]) : family == 4 ? cv[j] * cv[j] : 0.0);
+  const size_t b_coef = (tab.size() * 8 + 255) & ~(size_t)255;
+  const size_t b_vr = ((size_t)dim * 6 * 8 + 255) & ~(size_t)255;
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  (void)hipSetDevice(c->device);
+  hipError_t e = hipMalloc((void**)&f->dmem, b_coef + b_vr);
+  if (e != hipSuccess) {
+    delete f;
+    return fail(QMC_ENOMEM, "hipMalloc for the descriptor failed: %s", hipGetErrorString(e));
+  }
+  f->d_coef = (double*)f->dmem;
+  f->d_vr = (double*)(f->dmem + b_coef);
+  e = hipMemcpy(f->d_coef, tab.data(), tab.size() * 8, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(f->dmem);
+    delete f;
+    return fail(QMC_EDEVICE, "descriptor upload failed: %s", hipGetErrorString(e));
+  }
+  c->live_integrands += 1;
+  *out = f;
+  return QMC_OK;
+}
+
 int qmc_destroy_integrand(qmc_integrand* f) {
   if (!f) return QMC_OK;
   if (f->refs.load()) return fail(QMC_EBUSY, "integrand referenced by %d pending requests", f->refs.load());
@@ -853,6 +901,17 @@ int qmc_integrate(qmc_context* c, const qmc_integrand* f, uint32_t dim, uint64_t
   HIPCHK(hipSetDevice(c->device));
   // fp32 evaluation exists only in the batch kernels
   int rc = (f->flags & QMC_EVAL_FP32) ? run_requests(c, &q, 1, out, shift_sums) : integrate_request(c, q, out, shift_sums);
+  if (rc == QMC_EDEVICE) c->broken = true;
+  return rc;
+}
+
+int qmc_integrate_request(qmc_context* c, const qmc_request* q, qmc_result* out, double* shift_sums) {
+  if (!c || !q || !q->f) return fail(QMC_EINVAL, "NULL context, request or integrand");
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  if (c->closing) return fail(QMC_EINVAL, "context has been destroyed");
+  if (c->broken) return fail(QMC_EDEVICE, "context is unusable after a device error");
+  HIPCHK(hipSetDevice(c->device));
+  int rc = (q->f->flags & QMC_EVAL_FP32) ? run_requests(c, q, 1, out, shift_sums) : integrate_request(c, *q, out, shift_sums);
   if (rc == QMC_EDEVICE) c->broken = true;
   return rc;
 }
@@ -949,6 +1008,7 @@ int qmc_specialize_check(const qmc_integrand_desc* d, qmc_transform t, size_t* c
 int qmc_histogram(qmc_context* c, const qmc_integrand* f, uint64_t n, const uint64_t* z, uint64_t seed,
                   uint32_t bins, double* hist) {
   if (!c || !f || !hist) return fail(QMC_EINVAL, "NULL argument");
+  if (f->genz) return fail(QMC_EUNSUPPORTED, "histograms are for sector integrands");
   if (bins < 2 || bins > 65536) return fail(QMC_EINVAL, "bins=%u outside [2, 65536]", bins);
   if (n >= (1ull << 53)) return fail(QMC_EINVAL, "n too large");
   int rc = check_lattice(n, f->dim, z);

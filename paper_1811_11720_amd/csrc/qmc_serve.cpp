@@ -249,6 +249,7 @@ int qmc_submit(qmc_context* c, const qmc_request* reqs, uint32_t count, uint64_t
       r.q = q;
       r.f = const_cast<qmc_integrand*>(q.f);
       if (r.f->ctx != c) return fail(QMC_EINVAL, "request %u: integrand belongs to another context", i);
+      if (r.f->genz) return fail(QMC_EUNSUPPORTED, "request %u: Genz integrands run through qmc_integrate", i);
       if (q.m < 1 || q.m > QMC_MAX_SHIFTS) return fail(QMC_EINVAL, "request %u: m=%u", i, q.m);
       const uint32_t dim = r.f->dim;
       if (q.z) {
