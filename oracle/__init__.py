@@ -272,7 +272,9 @@ def integrate(desc, n, z_of, m, seed, transform=(T_KOROBOV, 3, 3), vr=None, rel_
     shifts (Monte Carlo scaling): m grows to max(m+1, ceil(m (err/goal)^2)), at
     most MAX_SHIFTS; the new shifts continue the same random stream, so the
     sums of the earlier shifts are kept.  A round that would pass max_evals is
-    never started."""
+    never started: a lattice too large for the remaining budget is replaced by
+    the largest larger-than-current one that fits, and the loop stops when
+    none does."""
     table = sorted(table_ns) if table_ns is not None else [n]
     m_all = m
     sh = shifts(seed, m_all, desc.dim)
@@ -312,8 +314,11 @@ def integrate(desc, n, z_of, m, seed, transform=(T_KOROBOV, 3, 3), vr=None, rel_
         if larger or table[-1] > n:
             nn = larger[0] if larger else table[-1]
             if max_evals is not None and evals + nn * m_all > max_evals:
-                res["maxeval_hit"] = True
-                return res
+                fits = [v for v in table if n < v and evals + v * m_all <= max_evals]
+                if not fits:
+                    res["maxeval_hit"] = True
+                    return res
+                nn = fits[-1]
             n = nn
             first_new = 0
             continue

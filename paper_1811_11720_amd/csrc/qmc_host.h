@@ -108,7 +108,9 @@ uint64_t largest_registered(qmc_context* c);
 // there, more shifts, m -> max(m+1, ceil(m (err/goal)^2)) up to QMC_MAX_SHIFTS,
 // continuing the same shift stream so the earlier shifts' sums are kept (at
 // most max_m shifts).  No step may take the evaluations past q.max_evals
-// (0 = no limit); lattices larger than max_n are not used.
+// (0 = no limit): a lattice too large for the remaining budget is replaced by
+// the largest larger-than-current one that fits.  Lattices larger than max_n
+// are not used.
 struct GrowthStep {
   enum Kind { STOP = 0, LATTICE = 1, SHIFTS = 2 } kind = STOP;
   uint64_t n = 0;

@@ -457,8 +457,21 @@ GrowthStep growth_step(qmc_context* c, const qmc_request& q, const qmc_result& r
       zn.swap(zt);
     }
   }
+  if (found && q.max_evals && r.evaluations + nn * (uint64_t)m > q.max_evals) {
+    // too large for the remaining budget: the largest larger-than-current
+    // lattice that still fits, else stop
+    const uint64_t left = q.max_evals > r.evaluations ? q.max_evals - r.evaluations : 0;
+    found = false;
+    std::lock_guard<std::mutex> lk(c->lat_mu);
+    for (auto& kv : c->lattices)
+      if (kv.first > n && kv.first <= max_n && kv.second.size() >= dim && kv.first * (uint64_t)m <= left) {
+        found = true;
+        nn = kv.first;
+        zn.assign(kv.second.begin(), kv.second.begin() + dim);
+      }
+    if (!found) return g;
+  }
   if (found) {
-    if (q.max_evals && r.evaluations + nn * (uint64_t)m > q.max_evals) return g;
     g.kind = GrowthStep::LATTICE;
     g.n = nn;
     g.m = m;

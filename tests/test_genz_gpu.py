@@ -111,5 +111,8 @@ def test_integrate_request_honours_max_evals(ctx):
                                   max_evals=cap))
     assert r["flags"] & 2 and not r["flags"] & 1
     assert r["evaluations"] <= cap and r["iterations"] >= 2
+    # the lattice after the first is the largest whose round fits the budget
+    left = cap - n0 * 32
+    assert r["n"] == max(v for v in table if n0 < v and v * 32 <= left)
     f.close()
     c2.close()

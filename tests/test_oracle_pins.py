@@ -529,6 +529,19 @@ def test_fallback_adds_shifts_at_the_largest_lattice():
     assert res["converged"] or res["m"] == oracle.MAX_SHIFTS
 
 
+def test_maxeval_takes_the_largest_affordable_lattice():
+    """A wanted lattice beyond the remaining budget is replaced by the largest
+    larger lattice that fits; the loop stops when none does."""
+    desc = W.product_of_linear([1.0, 1.0], [0.8, 0.5], -1.5)
+    table = [cbc.next_prime(v) for v in (500, 1000, 2000, 4000)]
+    zs = {n: cbc.fast_cbc(n, 2) for n in table}
+    cap = table[0] * 8 + table[2] * 8 + 100  # room for the 2000 lattice, not the 4000 one
+    res = oracle.integrate(desc, table[0], zs.__getitem__, 8, 5, (oracle.T_BAKER, 0, 0), rel_tol=1e-15,
+                           max_evals=cap, table_ns=table)
+    assert [v[0] for v in res["visited"]] == [table[0], table[2]]
+    assert res["maxeval_hit"] and res["evaluations"] <= cap
+
+
 def test_fallback_stops_at_maxeval():
     desc = W.product_of_linear([1.0, 1.0], [0.8, 0.5], -1.5)
     table = [cbc.next_prime(500)]
