@@ -101,6 +101,23 @@ int qmc_register_lattice(qmc_context* ctx, uint64_t n, uint32_t dim, const uint6
  */
 int qmc_next_lattice(qmc_context* ctx, uint64_t preferred_n, uint32_t dim, uint64_t* n_out);
 
+/*
+ * Fast component-by-component construction of a generating vector on the
+ * device (Sec. 2.2; App. A.3): prime n in [3, 2^31), z[0] = 1, each next
+ * component minimising the shift-averaged worst-case error of the Korobov
+ * space with kernel omega(x) = 2 pi^2 (x^2 - x + 1/6) and product weights
+ * gammas (host [dim], > 0; NULL = gamma_j = j^-2).  Candidates are
+ * 1..(n-1)/2; among those within a relative 1e-9 of the minimum the smallest
+ * wins.  The sums over all candidates are a cyclic convolution of length n-1
+ * (Nuyens and Cools), done with power-of-two FFTs of length
+ * N = 2^ceil(log2(2n-3)): device memory 48 N + 16 n bytes (13 GB at
+ * n = 1e8), allocated for the call and freed before it returns.  z: host
+ * [dim].  QMC_EINVAL for
+ * a composite or out-of-range n, QMC_ENOMEM when the buffers do not fit.
+ * The result can be registered with qmc_register_lattice.
+ */
+int qmc_cbc(qmc_context* ctx, uint64_t n, uint32_t dim, const double* gammas, uint64_t* z);
+
 /* ---------------------------------------------------------------- integrand */
 typedef struct qmc_integrand qmc_integrand;
 

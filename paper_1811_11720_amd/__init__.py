@@ -108,6 +108,7 @@ def _declare(L):
         "qmc_next_lattice": ([vp, C.c_uint64, C.c_uint32, up], C.c_int),
         "qmc_create_integrand": ([vp, C.POINTER(IntegrandDesc), C.POINTER(vp)], C.c_int),
         "qmc_integrate_request": ([vp, C.POINTER(Request), C.POINTER(Result), C.POINTER(C.c_double)], C.c_int),
+        "qmc_cbc": ([vp, C.c_uint64, C.c_uint32, C.POINTER(C.c_double), C.POINTER(C.c_uint64)], C.c_int),
         "qmc_create_genz": ([vp, C.c_int, C.c_uint32, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(vp)],
                             C.c_int),
         "qmc_destroy_integrand": ([vp], C.c_int),
@@ -310,6 +311,13 @@ class Context:
                              _tr(r.get("transform", (T_KOROBOV, 3, 3))), r.get("rel_tol", 0.0),
                              r.get("abs_tol", 0.0), r.get("max_evals", 0))
         return arr, keep
+
+    def cbc(self, n: int, dim: int, gammas=None) -> list:
+        """Fast CBC generating vector for prime n, built on the device."""
+        z = np.zeros(dim, dtype=np.uint64)
+        g = None if gammas is None else np.ascontiguousarray(gammas, dtype=np.float64)
+        _check(lib().qmc_cbc(self.handle, n, dim, None if g is None else _dp(g), _up(z)))
+        return [int(v) for v in z]
 
     def integrate_request(self, req, sums: bool = False):
         """One request dict (as in integrate_batch) through the single-integral path."""

@@ -1,0 +1,81 @@
+"""Device fast CBC (Sec. 2.2, App. A.3) against the oracle's brute-force CBC,
+the host fast CBC and the oracle's direct worst-case error."""
+
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from paper_1811_11720_amd import cbc
+from test_parity_gpu import make_ctx
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = make_ctx("generic")
+    yield c
+    c.close()
+
+
+def _gam(d):
+    return [1.0 / (j + 1) ** 2 for j in range(d)]
+
+
+@pytest.mark.parametrize("n", [3, 5, 7, 11, 13, 101, 1009, 1999])
+def test_device_cbc_equals_brute_force(ctx, n):
+    d = 6
+    assert ctx.cbc(n, d) == oracle.cbc_brute(n, d, _gam(d))
+
+
+def test_paper_vectors_reach_the_minimum_under_equal_weights(ctx):
+    """App. A.3 vectors (1,3)@7 and (1,7)@11 under gamma = (1/2, 1/2): the
+    device's choice has the same (minimal) worst-case error."""
+    for n, zp in [(7, [1, 3]), (11, [1, 7])]:
+        z = ctx.cbc(n, 2, [0.5, 0.5])
+        assert oracle.cbc_criterion(n, z, [0.5, 0.5]) == pytest.approx(oracle.cbc_criterion(n, zp, [0.5, 0.5]),
+                                                                      rel=1e-12)
+
+
+@pytest.mark.parametrize("n", [10007, 65537, 1000003])
+def test_device_cbc_matches_host_fast_cbc(ctx, n):
+    """Same vector as the host construction, or (inside the 1e-9 tie band,
+    where FFT rounding may decide) a vector of the same worst-case error."""
+    d = 8
+    zg = ctx.cbc(n, d)
+    zh = cbc.fast_cbc(n, d)
+    if zg != zh:
+        for j in range(2, d + 1):
+            eg = oracle.cbc_criterion(n, zg[:j], _gam(j))
+            eh = oracle.cbc_criterion(n, zh[:j], _gam(j))
+            assert eg == pytest.approx(eh, rel=1e-8)
+
+
+def test_device_cbc_at_the_headline_size(ctx):
+    """n = 100000007: the first components against the committed table's
+    (host-built) vector by the oracle's direct worst-case error."""
+    n, d = 100000007, 4
+    t0 = time.perf_counter()
+    zg = ctx.cbc(n, d)
+    dt = time.perf_counter() - t0
+    print(f"device CBC n={n} d={d}: {dt:.2f} s")
+    zt = W.lattice_table()[n][:d]
+    if zg != zt:
+        eg = oracle.cbc_criterion(n, zg, _gam(d))
+        et = oracle.cbc_criterion(n, zt, _gam(d))
+        assert eg == pytest.approx(et, rel=1e-8)
+    assert zg[0] == 1 and all(1 <= v <= (n - 1) // 2 for v in zg)
+
+
+def test_device_cbc_rejects_bad_sizes(ctx):
+    import paper_1811_11720_amd as Q
+
+    for n in (1, 2, 4, 1001, 2 ** 31 + 11):
+        with pytest.raises(Q.QmcError) as e:
+            ctx.cbc(n, 3)
+        assert e.value.code == Q.QMC_EINVAL
+    with pytest.raises(Q.QmcError):
+        ctx.cbc(101, 3, [0.5, -1.0, 0.5])
