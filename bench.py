@@ -365,6 +365,30 @@ def bench_genz(a, Q, W, torch):
     return 0
 
 
+def bench_cbc(a, Q, W, torch):
+    """Device fast CBC of a generating vector (Sec. 2.2) for prime n, d = 10,
+    timed end to end; the host construction (scipy FFT) of the first two
+    components at the same n for reference."""
+    from paper_1811_11720_amd import cbc
+
+    ctx = Q.Context(0)
+    ctx.cbc(10007, 3)  # warm-up
+    t0 = time.perf_counter()
+    z = ctx.cbc(a.n, a.cbc_dim)
+    dev = time.perf_counter() - t0
+    host = None
+    if a.n <= 200_000_000:
+        t0 = time.perf_counter()
+        zh = cbc.fast_cbc(a.n, 2, workers=min(16, os.cpu_count() or 1))
+        host = time.perf_counter() - t0
+    ctx.close()
+    out = {"workload": "cbc", "n": a.n, "dim": a.cbc_dim, "z": z, "device_seconds": dev,
+           "device_seconds_per_component": dev / max(1, a.cbc_dim - 1),
+           "host_seconds_per_component": host, "host_z2": None if host is None else zh[1]}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def bench_serve(a, Q, W, torch):
     """Serving: requests of 10-500 integrands from the batch pool, each with a
     relative target log-uniform in [1e-8, 1e-4], arriving as a Poisson process
@@ -480,7 +504,9 @@ def main():
     ap.add_argument("--m", type=int, default=32)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--workload", choices=["sector_real", "batch", "serve", "genz", "copy"], default="sector_real")
+    ap.add_argument("--workload", choices=["sector_real", "batch", "serve", "genz", "cbc", "copy"],
+                    default="sector_real")
+    ap.add_argument("--cbc-dim", type=int, default=10, help="cbc: components")
     ap.add_argument("--reps", type=int, default=10, help="genz: parameter sets per family and dimension")
     ap.add_argument("--baker", action="store_true", help="genz: baker transform instead of Korobov r=3")
     ap.add_argument("--count", type=int, default=2000, help="batch: integrals")
@@ -513,6 +539,8 @@ def main():
         return bench_copy(a, torch)
     if a.workload == "genz":
         return bench_genz(a, Q, W, torch)
+    if a.workload == "cbc":
+        return bench_cbc(a, Q, W, torch)
     job = W.job_sector_real(a.n)
     job.m = a.m
     ctx = Q.Context(0)
