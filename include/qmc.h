@@ -118,6 +118,16 @@ int qmc_next_lattice(qmc_context* ctx, uint64_t preferred_n, uint32_t dim, uint6
  */
 int qmc_cbc(qmc_context* ctx, uint64_t n, uint32_t dim, const double* gammas, uint64_t* z);
 
+/*
+ * max_n > 0: when the growth loop of qmc_integrate / qmc_integrate_request /
+ * qmc_integrate_batch wants a lattice of want <= max_n points and none is
+ * registered, it builds the lattice of the smallest prime >= want with
+ * qmc_cbc (max(dim, 10) components, gamma_j = j^-2) and registers it, instead
+ * of falling back to the largest registered lattice.  0 (the default) turns
+ * this off.  max_n < 2^31.  The serving loop never builds lattices.
+ */
+int qmc_set_lattice_builder(qmc_context* ctx, uint64_t max_n);
+
 /* ---------------------------------------------------------------- integrand */
 typedef struct qmc_integrand qmc_integrand;
 

@@ -262,8 +262,19 @@ def goal_met(re, im, err_re, err_im, rel_tol, abs_tol, errormode, is_complex) ->
 MAX_SHIFTS = 1024  # largest number of shifts (the library's limit)
 
 
+def _is_prime(v: int) -> bool:
+    if v < 2:
+        return False
+    p = 2
+    while p * p <= v:
+        if v % p == 0:
+            return False
+        p += 1
+    return True
+
+
 def integrate(desc, n, z_of, m, seed, transform=(T_KOROBOV, 3, 3), vr=None, rel_tol=0.0,
-              abs_tol=0.0, errormode="largest", max_evals=None, table_ns=None, threads=None):
+              abs_tol=0.0, errormode="largest", max_evals=None, table_ns=None, threads=None, build_max=None):
     """Oracle integration: Case 2 (one lattice) when rel_tol <= 0 and abs_tol <= 0,
     else the Case-1 loop of Sec. 3.3.1 over `table_ns` with generating vectors
     z_of(n): a round that misses its goal is discarded and the next lattice of
@@ -274,7 +285,9 @@ def integrate(desc, n, z_of, m, seed, transform=(T_KOROBOV, 3, 3), vr=None, rel_
     sums of the earlier shifts are kept.  A round that would pass max_evals is
     never started: a lattice too large for the remaining budget is replaced by
     the largest larger-than-current one that fits, and the loop stops when
-    none does."""
+    none does.  With build_max, a wanted size <= build_max that the table
+    lacks becomes the smallest prime >= the wanted size (z_of must supply its
+    generating vector) instead of the fallback."""
     table = sorted(table_ns) if table_ns is not None else [n]
     m_all = m
     sh = shifts(seed, m_all, desc.dim)
@@ -311,6 +324,14 @@ def integrate(desc, n, z_of, m, seed, transform=(T_KOROBOV, 3, 3), vr=None, rel_
         err = max(err_re, err_im) if desc.deform else err_re
         want = max(1.5 * n, n * (err / goal if goal > 0 and math.isfinite(err) else 2.0))
         larger = [v for v in table if v >= want]
+        wantu = math.ceil(want)
+        if (not larger and build_max is not None and wantu <= build_max
+                and (max_evals is None or evals + wantu * m_all <= max_evals)):
+            nb = max(wantu, 3)
+            while not _is_prime(nb):
+                nb += 1
+            table = sorted(set(table) | {nb})
+            larger = [nb]
         if larger or table[-1] > n:
             nn = larger[0] if larger else table[-1]
             if max_evals is not None and evals + nn * m_all > max_evals:

@@ -108,6 +108,7 @@ def _declare(L):
         "qmc_next_lattice": ([vp, C.c_uint64, C.c_uint32, up], C.c_int),
         "qmc_create_integrand": ([vp, C.POINTER(IntegrandDesc), C.POINTER(vp)], C.c_int),
         "qmc_integrate_request": ([vp, C.POINTER(Request), C.POINTER(Result), C.POINTER(C.c_double)], C.c_int),
+        "qmc_set_lattice_builder": ([vp, C.c_uint64], C.c_int),
         "qmc_cbc": ([vp, C.c_uint64, C.c_uint32, C.POINTER(C.c_double), C.POINTER(C.c_uint64)], C.c_int),
         "qmc_create_genz": ([vp, C.c_int, C.c_uint32, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(vp)],
                             C.c_int),
@@ -311,6 +312,10 @@ class Context:
                              _tr(r.get("transform", (T_KOROBOV, 3, 3))), r.get("rel_tol", 0.0),
                              r.get("abs_tol", 0.0), r.get("max_evals", 0))
         return arr, keep
+
+    def set_lattice_builder(self, max_n: int):
+        """Let the growth loop build missing lattices up to max_n (0 = off)."""
+        _check(lib().qmc_set_lattice_builder(self.handle, max_n))
 
     def cbc(self, n: int, dim: int, gammas=None) -> list:
         """Fast CBC generating vector for prime n, built on the device."""

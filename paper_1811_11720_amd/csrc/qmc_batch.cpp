@@ -339,7 +339,7 @@ int run_requests(qmc_context* c, const qmc_request* reqs, uint32_t count, qmc_re
         s.done = true;
         continue;
       }
-      GrowthStep g = growth_step(c, q, s.r, s.n, m, s.f->dim, cplx, UINT64_MAX, QMC_MAX_SHIFTS);
+      GrowthStep g = growth_step(c, q, s.r, s.n, m, s.f->dim, cplx, UINT64_MAX, QMC_MAX_SHIFTS, true);
       if (g.kind == GrowthStep::STOP) {
         s.r.flags |= QMC_MAXEVAL_HIT;
         s.done = true;

@@ -60,6 +60,7 @@ struct qmc_context {
   std::atomic<qmc_serve_state*> serve{nullptr};     // scheduler, created by the first qmc_submit
   size_t serve_mem_limit = (size_t)8 << 30;  // device bytes admitted requests may use
   uint64_t serve_max_n = (1ull << 31) - 1;   // growth stops above this lattice size
+  uint64_t build_max_n = 0;  // > 0: the growth loop builds missing lattices up to this size (qmc_cbc)
 };
 
 struct qmc_integrand {
@@ -118,7 +119,10 @@ struct GrowthStep {
   std::vector<uint64_t> z;       // LATTICE: generating vector [dim]
 };
 GrowthStep growth_step(qmc_context* c, const qmc_request& q, const qmc_result& r, uint64_t n, uint32_t m,
-                       uint32_t dim, bool cplx, uint64_t max_n, uint32_t max_m);
+                       uint32_t dim, bool cplx, uint64_t max_n, uint32_t max_m, bool may_build = false);
+// Builds (qmc_cbc) and registers the lattice of the smallest prime >= want
+// with max(dim, 10) components; returns its size (0 on failure).
+uint64_t build_lattice(qmc_context* c, uint64_t want, uint32_t dim);
 // fill the integrand/transform part of an EvalArgs
 int fill_integrand_args(qmcd::EvalArgs& a, const qmc_integrand* f, const qmc_transform& t, int& tsel);
 

@@ -428,7 +428,7 @@ int next_registered(qmc_context* c, uint64_t want, uint32_t dim, uint64_t* n_out
 }
 
 GrowthStep growth_step(qmc_context* c, const qmc_request& q, const qmc_result& r, uint64_t n, uint32_t m,
-                       uint32_t dim, bool cplx, uint64_t max_n, uint32_t max_m) {
+                       uint32_t dim, bool cplx, uint64_t max_n, uint32_t max_m, bool may_build) {
   GrowthStep g;
   const double goal =
       std::max(q.abs_tol, q.rel_tol * (cplx ? std::max(std::fabs(r.re), std::fabs(r.im)) : std::fabs(r.re)));
@@ -439,6 +439,12 @@ GrowthStep growth_step(qmc_context* c, const qmc_request& q, const qmc_result& r
   uint64_t nn = 0;
   std::vector<uint64_t> zn;
   bool found = next_registered(c, wantu, dim, &nn, false, &zn) == QMC_OK && nn <= max_n;
+  if (!found && may_build && c->build_max_n && wantu <= std::min(max_n, c->build_max_n) &&
+      (!q.max_evals || r.evaluations + wantu * (uint64_t)m <= q.max_evals)) {
+    // no registered lattice is large enough: build one (Sec. 2.2)
+    const uint64_t built = build_lattice(c, wantu, dim);
+    found = built && next_registered(c, wantu, dim, &nn, false, &zn) == QMC_OK && nn <= max_n;
+  }
   if (!found) {
     // the largest usable lattice
     uint64_t top = 0;
@@ -492,6 +498,24 @@ GrowthStep growth_step(qmc_context* c, const qmc_request& q, const qmc_result& r
   g.n = n;
   g.m = (uint32_t)m_new;
   return g;
+}
+
+uint64_t build_lattice(qmc_context* c, uint64_t want, uint32_t dim) {
+  auto prime = [](uint64_t v) {
+    if (v < 2) return false;
+    for (uint64_t p = 2; p * p <= v; ++p)
+      if (v % p == 0) return false;
+    return true;
+  };
+  uint64_t n = std::max<uint64_t>(want, 3);
+  while (!prime(n)) ++n;
+  if (n >= (1ull << 31)) return 0;
+  const uint32_t d = std::max<uint32_t>(dim, 10);
+  std::vector<uint64_t> z(d);
+  if (qmc_cbc(c, n, d, nullptr, z.data()) != QMC_OK) return 0;
+  std::lock_guard<std::mutex> g(c->lat_mu);
+  c->lattices[n] = z;
+  return n;
 }
 
 int integrate_request(qmc_context* c, const qmc_request& q, qmc_result* out, double* shift_sums) {
@@ -559,7 +583,7 @@ int integrate_request(qmc_context* c, const qmc_request& q, qmc_result* out, dou
       r.flags |= QMC_CONVERGED;
       break;
     }
-    GrowthStep g = growth_step(c, q, r, n, mcur, dim, cplx, UINT64_MAX, QMC_MAX_SHIFTS);
+    GrowthStep g = growth_step(c, q, r, n, mcur, dim, cplx, UINT64_MAX, QMC_MAX_SHIFTS, true);
     if (g.kind == GrowthStep::STOP) {
       r.flags |= QMC_MAXEVAL_HIT;
       break;
@@ -737,6 +761,14 @@ int qmc_context_destroy(qmc_context* c) {
     }
   }
   free_context(c);
+  return QMC_OK;
+}
+
+int qmc_set_lattice_builder(qmc_context* c, uint64_t max_n) {
+  if (!c) return fail(QMC_EINVAL, "context is NULL");
+  if (max_n >= (1ull << 31)) return fail(QMC_EINVAL, "max_n must be below 2^31");
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  c->build_max_n = max_n;
   return QMC_OK;
 }
 

@@ -542,6 +542,22 @@ def test_maxeval_takes_the_largest_affordable_lattice():
     assert res["maxeval_hit"] and res["evaluations"] <= cap
 
 
+def test_growth_builds_missing_lattices_when_allowed():
+    """With build_max, a wanted size the table lacks becomes the next prime
+    at or above it (generating vector by CBC), so the goal is met without
+    the Monte Carlo fallback."""
+    desc = W.product_of_linear([1.0, 1.0], [0.8, 0.5], -1.5)
+    table = [cbc.next_prime(500)]
+    BAKER = (oracle.T_BAKER, 0, 0)
+    z_of = lambda n: cbc.fast_cbc(n, 2)
+    first = oracle.integrate(desc, table[0], z_of, 8, 5, BAKER)
+    goal = first["err_re"] / abs(first["re"]) / 12.0
+    res = oracle.integrate(desc, table[0], z_of, 8, 5, BAKER, rel_tol=goal, table_ns=table, build_max=10 ** 6)
+    ns = [v[0] for v in res["visited"]]
+    assert res["converged"] and res["m"] == 8 and len(ns) >= 2
+    assert all(cbc.is_prime(v) for v in ns) and ns == sorted(ns)
+
+
 def test_fallback_stops_at_maxeval():
     desc = W.product_of_linear([1.0, 1.0], [0.8, 0.5], -1.5)
     table = [cbc.next_prime(500)]

@@ -261,6 +261,32 @@ def test_growth_fallback_adds_shifts_like_the_oracle(ctx):
     c2.close()
 
 
+def test_growth_builds_missing_lattices(ctx):
+    """With the lattice builder on, the device loop builds (device CBC) the
+    next prime lattice the goal asks for; sizes, iterations and convergence
+    follow the oracle's mirror, and the estimate meets the closed form."""
+    a, b = np.array([1.0, 1.0]), np.array([0.8, 0.5])
+    desc = W.product_of_linear(a, b, -1.5)
+    exact = float(np.prod(((a + b) ** -0.5 - a ** -0.5) / (b * -0.5)))
+    n0 = cbc.next_prime(500)
+    z0 = cbc.fast_cbc(n0, 2)
+    BAKER = (W.T_BAKER, 0, 0)
+    first = oracle.integrate(desc, n0, lambda n: cbc.fast_cbc(n, 2), 8, 5, BAKER)
+    goal = first["err_re"] / abs(first["re"]) / 12.0
+    o = oracle.integrate(desc, n0, lambda n: cbc.fast_cbc(n, 2), 8, 5, BAKER, rel_tol=goal, table_ns=[n0],
+                         build_max=10 ** 6, threads=THREADS)
+    c2 = make_ctx("specialised" if ctx.path else "generic")
+    c2.register_lattice(n0, z0)
+    c2.set_lattice_builder(10 ** 6)
+    f = c2.integrand(desc)
+    g = c2.integrate(f, n0, z0, 8, 5, BAKER, rel_tol=goal)
+    assert g["n"] == o["n"] and g["iterations"] == o["iterations"] and g["evaluations"] == o["evaluations"]
+    assert bool(g["flags"] & 1) == o["converged"] and g["m"] == 8
+    assert abs(g["re"] - exact) <= 6 * g["err_re"] + 1e-13
+    f.close()
+    c2.close()
+
+
 def test_growth_loop_matches_oracle(ctx):
     desc = W.product_of_linear([1.0, 1.0, 1.0], [0.8, 0.5, 0.3], -1.5)
     table_ns = [cbc.next_prime(v) for v in (1000, 2000, 4000, 8000, 16000, 32000, 64000, 128000)]
