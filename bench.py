@@ -389,6 +389,59 @@ def bench_cbc(a, Q, W, torch):
     return 0
 
 
+def bench_sector_complex(a, Q, W, torch):
+    """The complex sector integrand under contour deformation (d=8, |U|=12,
+    |F|=30, lambda=0.5): VR map fitted from 1024-bin histograms on one shifted
+    lattice of 100003 points (Sec. 2.4), then the Case-1 loop to relative
+    error 1e-8 (errormode largest), m = 32, lattices beyond the table built on
+    the device up to 2^31-1."""
+    table = W.lattice_table()
+    ctx = Q.Context(0)
+    ctx.register_table(table)
+    ctx.set_lattice_builder((1 << 31) - 1)
+    job = W.job_sector_complex(100003)
+    f = ctx.integrand(job.desc)
+    t0 = time.perf_counter()
+    params, mask = ctx.fit_vr(f, 100003, W.z_for(100003, 8), job.seed)
+    t_fit = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    r = ctx.integrate_request(dict(f=f, n=100003, z=W.z_for(100003, 8), m=32, seed=job.seed,
+                                   transform=job.transform, rel_tol=a.rel_tol, max_evals=a.max_evals_complex))
+    wall = time.perf_counter() - t0
+    fl = flops_per_eval_complex(job.desc, job.transform)
+    f.close()
+    ctx.close()
+    out = {
+        "metric": "lattice-point integrand evals/s (FP64) + p50/p99 request latency at rel err",
+        "value": r["evaluations"] / wall,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 0,
+        "ms_per_step": wall * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"sector_complex d=8 |U|=12 |F|=30 lambda=0.5 U^-2 F^-1.5, VR fit at n=100003, "
+                               f"Korobov r=3, m=32, rel {a.rel_tol:g} (largest), growth through the table and "
+                               f"device-built lattices"},
+        "result": {"re": r["re"], "im": r["im"], "err_re": r["err_re"], "err_im": r["err_im"], "n": r["n"],
+                   "iterations": r["iterations"], "evaluations": r["evaluations"], "flags": r["flags"],
+                   "path": r["path"], "vr_fallback_mask": mask},
+        "fit_seconds": t_fit,
+        "device_evals_per_s": r["evaluations"] / r["device_seconds"],
+        "roofline": {"bound": "alu", "kernel": "qmc_jit_eval32 (complex, run-time specialised)",
+                     "achieved": fl * r["evaluations"] / r["device_seconds"] / 1e12,
+                     "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": fl * r["evaluations"] / r["device_seconds"] / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
+                     "traffic": None, "flops_per_eval": fl},
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def bench_serve(a, Q, W, torch):
     """Serving: requests of 10-500 integrands from the batch pool, each with a
     relative target log-uniform in [1e-8, 1e-4], arriving as a Poisson process
@@ -504,8 +557,10 @@ def main():
     ap.add_argument("--m", type=int, default=32)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--workload", choices=["sector_real", "batch", "serve", "genz", "cbc", "copy"],
+    ap.add_argument("--workload", choices=["sector_real", "sector_complex", "batch", "serve", "genz", "cbc", "copy"],
                     default="sector_real")
+    ap.add_argument("--rel-tol", type=float, default=1e-8, help="sector_complex: relative goal")
+    ap.add_argument("--max-evals-complex", type=int, default=2 ** 37, help="sector_complex: evaluation cap")
     ap.add_argument("--cbc-dim", type=int, default=10, help="cbc: components")
     ap.add_argument("--reps", type=int, default=10, help="genz: parameter sets per family and dimension")
     ap.add_argument("--baker", action="store_true", help="genz: baker transform instead of Korobov r=3")
@@ -541,6 +596,8 @@ def main():
         return bench_genz(a, Q, W, torch)
     if a.workload == "cbc":
         return bench_cbc(a, Q, W, torch)
+    if a.workload == "sector_complex":
+        return bench_sector_complex(a, Q, W, torch)
     job = W.job_sector_real(a.n)
     job.m = a.m
     ctx = Q.Context(0)
