@@ -179,6 +179,14 @@ def eval_point(desc, x) -> complex:
     return complex(re.value, im.value)
 
 
+def deform_sign(desc, x) -> bool:
+    """True when Im F(z(x)) > 0 on the deformed contour (the wrong side)."""
+    d, keep = _mk_desc(desc)
+    xx = np.ascontiguousarray(x, dtype=np.float64)
+    re, im = C.c_double(), C.c_double()
+    return bool(lib().oracle_eval_point(C.byref(d), _dp(xx), C.byref(re), C.byref(im)))
+
+
 # ---------------------------------------------------------------- sums
 
 

@@ -315,7 +315,7 @@ __device__ __forceinline__ uint32_t mono_exp(uint32_t w0, uint32_t w1, int j) {
 __device__ __forceinline__ double vr_map(double y, cptr<double> p, double& w) {
   double p0 = p[0], p1 = p[1], p2 = __builtin_fabs(p[2]), p3 = __builtin_fabs(p[3]), p4 = p[4], p5 = p[5];
   double c3 = 1.0 - p2 - p3 - p4 - p5;
-  double i0 = 1.0 / (p0 - y), i1 = 1.0 / (p1 - y);
+  double i0 = fast_rcp(p0 - y), i1 = fast_rcp(p1 - y);  // poles stay outside [0, 1]
   double x = p2 * y * (p0 - 1.0) * i0 + p3 * y * (p1 - 1.0) * i1 + y * (p4 + y * (p5 + y * c3));
   double dx = p2 * p0 * (p0 - 1.0) * i0 * i0 + p3 * p1 * (p1 - 1.0) * i1 * i1 + p4 +
               y * (2.0 * p5 + 3.0 * c3 * y);
