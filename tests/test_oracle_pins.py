@@ -296,6 +296,15 @@ def test_genz_exact_values_by_quadrature():
         assert float(q) == pytest.approx(W.genz_exact(desc), rel=1e-10)
 
 
+def test_complex_sector_workload_passes_the_sign_probe():
+    """Input recipe of the complex sector integrand: fewer than 1% of 4096
+    probe points may have Im F(z) > 0 on the deformed contour."""
+    desc = W.sector_complex()
+    rng = np.random.default_rng(12345)
+    bad = sum(oracle.deform_sign(desc, x) for x in rng.uniform(0.0, 1.0, (4096, desc.dim)))
+    assert bad / 4096 < 0.01
+
+
 def test_plain_product_workload_integrates_to_one():
     job = W.job_plain_product()
     sh = oracle.shifts(job.seed, job.m, job.desc.dim)
