@@ -327,6 +327,7 @@ int run_requests(qmc_context* c, const qmc_request* reqs, uint32_t count, qmc_re
       }
       s.r.flags &= ~(uint32_t)(QMC_NONFINITE | QMC_DEFORM_SIGN);
       if (s.signs) s.r.flags |= QMC_DEFORM_SIGN;
+      if (s.f->has_vr && s.f->vr_fallback) s.r.flags |= QMC_VR_FALLBACK;
       const bool finite = std::isfinite(s.r.re) && std::isfinite(s.r.im);
       if (!finite) s.r.flags |= QMC_NONFINITE;
       const bool grow = q.rel_tol > 0 || q.abs_tol > 0;

@@ -72,6 +72,7 @@ struct qmc_integrand {
   std::vector<double> coef;
   std::vector<uint8_t> expo;
   bool has_vr = false;
+  uint32_t vr_fallback = 0;  // dimensions whose fitted map was rejected (identity used)
   std::vector<double> vr;
   char* dmem = nullptr;  // coef | expo (u32 x 2 per monomial) | vr
   double* d_coef = nullptr;

@@ -576,6 +576,7 @@ int integrate_request(qmc_context* c, const qmc_request& q, qmc_result* out, dou
     }
     r.flags &= ~(uint32_t)(QMC_NONFINITE | QMC_DEFORM_SIGN);
     if (signs) r.flags |= QMC_DEFORM_SIGN;
+    if (f->has_vr && f->vr_fallback) r.flags |= QMC_VR_FALLBACK;
     bool finite = std::isfinite(r.re) && std::isfinite(r.im);
     if (!finite) r.flags |= QMC_NONFINITE;
     if (!grow) break;
@@ -906,6 +907,7 @@ int qmc_set_vr(qmc_integrand* f, const double* params) {
   if (!f) return fail(QMC_EINVAL, "integrand is NULL");
   if (!params) {
     f->has_vr = false;
+    f->vr_fallback = 0;
     return QMC_OK;
   }
   for (uint32_t j = 0; j < f->dim; ++j) {
@@ -917,6 +919,7 @@ int qmc_set_vr(qmc_integrand* f, const double* params) {
   }
   std::lock_guard<std::recursive_mutex> g(f->ctx->mu);
   f->vr.assign(params, params + 6 * f->dim);
+  f->vr_fallback = 0;
   (void)hipSetDevice(f->ctx->device);
   (void)hipStreamSynchronize(f->ctx->stream);
   HIPCHK(hipMemcpy(f->d_vr, f->vr.data(), f->vr.size() * 8, hipMemcpyHostToDevice));
@@ -1091,7 +1094,9 @@ int qmc_fit_vr(qmc_context* c, qmc_integrand* f, uint64_t n, const uint64_t* z, 
   if (rc) return rc;
   if (params) std::memcpy(params, p.data(), p.size() * sizeof(double));
   if (fallback_mask) *fallback_mask = mask;
-  return qmc_set_vr(f, p.data());
+  rc = qmc_set_vr(f, p.data());
+  if (rc == QMC_OK) f->vr_fallback = mask;  // reported as QMC_VR_FALLBACK in results
+  return rc;
 }
 
 }  // extern "C"

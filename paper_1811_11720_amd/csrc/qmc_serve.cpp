@@ -162,6 +162,7 @@ static void scheduler(qmc_context* c, qmc_serve_state* s) {
       }
       r.r.flags &= ~(uint32_t)(QMC_NONFINITE | QMC_DEFORM_SIGN);
       if (r.job.sign_points) r.r.flags |= QMC_DEFORM_SIGN;
+      if (r.f->has_vr && r.f->vr_fallback) r.r.flags |= QMC_VR_FALLBACK;
       const bool finite = std::isfinite(r.r.re) && std::isfinite(r.r.im);
       if (!finite) r.r.flags |= QMC_NONFINITE;
       const bool grow = r.q.rel_tol > 0 || r.q.abs_tol > 0;

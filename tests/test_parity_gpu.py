@@ -141,6 +141,15 @@ def test_power_classes(ctx, pu, pf):
     _check_sums(g["sums_re"], o, label=f"p{pu},{pf}")
 
 
+def test_maximum_shift_count(ctx):
+    """m = QMC_MAX_SHIFTS (1024): every shift group, including the ragged last one."""
+    desc = W.random_real_small(seed=12, dim=5, n_u=3, n_f=4)
+    n = 1009
+    z = cbc.fast_cbc(n, 5)
+    g, o, _ = _run_both(ctx, desc, n, z, 1024, 3, KOR3)
+    _check_sums(g["sums_re"], o, label="m1024")
+
+
 def test_composite_lattice_and_tiny_sizes(ctx):
     desc = W.random_real_small(seed=3, dim=2, n_u=2, n_f=3)
     for n, z in [(55, [1, 34]), (2, [1, 1]), (7, [1, 3]), (11, [1, 7])]:

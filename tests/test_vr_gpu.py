@@ -81,3 +81,21 @@ def test_fitted_map_keeps_the_integral_and_cuts_the_error(ctx):
     o = oracle.shift_sums(desc, n, z, 32, sh, NONE, vr=params, ids=[0, 31], threads=THREADS)
     for i, s in enumerate(o.ids):
         assert abs(vr["sums_re"][s] - o.re[i]) <= 1e-12 * o.abs_re[i]
+
+
+def test_rejected_fit_is_reported_in_the_result_flags(ctx):
+    """An integrand that vanishes everywhere gives empty histograms: every
+    dimension falls back to the identity map, and results carry VR_FALLBACK."""
+    desc = W.random_real_small(seed=4, dim=3)
+    desc.prefactor = 0.0
+    f = ctx.integrand(desc)
+    n = 2003
+    z = cbc.fast_cbc(n, 3)
+    params, mask = ctx.fit_vr(f, n, z, 5)
+    assert mask == 0b111
+    r = ctx.integrate(f, n, z, 4, 5, KOR3)
+    assert r["flags"] & 8 and r["re"] == 0.0
+    f.set_vr(None)
+    r = ctx.integrate(f, n, z, 4, 5, KOR3)
+    assert not r["flags"] & 8
+    f.close()
