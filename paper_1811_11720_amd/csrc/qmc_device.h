@@ -165,6 +165,17 @@ __device__ __forceinline__ double fast_rsqrt(double x) {
   return __builtin_fma(y, t, y);
 }
 
+// a * b + c as one three-address v_fma_f64 reading c from a scalar register
+// pair, so c must be uniform across the wave (a coefficient, a constant).  For
+// an fp64 multiply-add the compiler prefers the two-address v_fmac_f64 and
+// first copies a scalar or still-live addend into the destination: two VALU
+// moves per multiply-add in the evaluation loops that this form does not need.
+__device__ __forceinline__ double fma_s(double a, double b, double c) {
+  double r;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+  return r;
+}
+
 // ------------------------------------------------------------------ transforms
 
 // Korobov r0 = r1 = 3 with the polynomial written out (eq. korobov):
@@ -172,7 +183,7 @@ __device__ __forceinline__ double fast_rsqrt(double x) {
 // The weight is returned as s = u (1-u); the caller multiplies 140^d (prod s)^3.
 __device__ __forceinline__ double korobov3(double u, double& s) {
   s = __builtin_fma(-u, u, u);  // u (1-u)
-  double t = __builtin_fma(-20.0, u, 70.0);
+  double t = fma_s(u, -20.0, 70.0);
   t = __builtin_fma(t, u, -84.0);
   t = __builtin_fma(t, u, 35.0);
   double u2 = u * u;
@@ -841,6 +852,19 @@ __device__ __forceinline__ void neumaier(double& s, double& c, double v) {
   s = t;
 }
 
+// An integrand functor may declare `static constexpr bool kBounded = true` when
+// it is finite on all of [0, 1]^d; a zero transform weight then needs no guard
+// (0 * f is 0), otherwise such points are skipped so that f = inf there cannot
+// turn the sum into NaN.
+template <class Fn, class = void>
+struct bounded_fn {
+  static constexpr bool value = false;
+};
+template <class Fn>
+struct bounded_fn<Fn, decltype(void(Fn::kBounded))> {
+  static constexpr bool value = Fn::kBounded;
+};
+
 template <int DMAX, int TK, bool IDX32, int S, bool EXACT, class Fn, int VRM = VRM_RUNTIME, bool COMP = false>
 __device__ __forceinline__ void eval_real_sched(const EvalArgs& a, const Fn& fn, const Sched& sc) {
   const uint32_t s0 = sc.s0;
@@ -882,7 +906,7 @@ __device__ __forceinline__ void eval_real_sched(const EvalArgs& a, const Fn& fn,
           wt = a.wscale * (wt * wt * wt);  // 140^d (prod s_j)^3
         double w = wt * wv;
         double f = fn(x, a);
-        double v = (w == 0.0) ? 0.0 : w * f;
+        double v = (bounded_fn<Fn>::value || w != 0.0) ? w * f : 0.0;
         if (COMP)
           neumaier(acc[s], cmp[s], v);
         else

@@ -86,8 +86,108 @@ class Emitter {
   std::ostringstream pre_, body_;
 };
 
-// Greedy multivariate Horner: returns the name holding sum_i c_i prod_j x_j^e_ij.
-std::string horner(std::vector<Term> terms, Emitter& em) {
+// Choice of the factor at each step of the multivariate Horner scheme.  A
+// step takes x_j^e out of the terms whose exponent of x_j is at least e and
+// joins them to the remaining terms with one fma (a multiply when none
+// remain).  The splits of least total operation count are found by an
+// exhaustive search memoised over term sets (power formation not counted);
+// a set of more than kMaxTerms terms, or one not yet solved once `max_states`
+// sets are stored, takes the greedy split instead: the variable that occurs
+// in most terms, at its smallest exponent among them.
+class HornerPlan {
+ public:
+  explicit HornerPlan(int dim, size_t max_states = 1u << 14) : d_(dim), max_(max_states) {}
+
+  template <class T>
+  void split(const std::vector<T>& terms, int& j, int& e) {
+    std::vector<Ex> ex;
+    ex.reserve(terms.size());
+    for (auto& t : terms) ex.push_back(t.e);
+    std::sort(ex.begin(), ex.end());
+    cost(ex);
+    auto it = memo_.find(key(ex));
+    if (it != memo_.end()) {
+      j = it->second.j;
+      e = it->second.e;
+      return;
+    }
+    int cnt = -1;
+    for (int v = 0; v < d_; ++v) {
+      int c = 0, lo = 255;
+      for (auto& t : ex)
+        if (t[v]) {
+          ++c;
+          lo = std::min<int>(lo, t[v]);
+        }
+      if (c > cnt) {
+        cnt = c;
+        j = v;
+        e = lo;
+      }
+    }
+  }
+
+ private:
+  using Ex = std::array<uint8_t, QMCD_MAXD>;
+  struct Best {
+    int cost, j, e;
+  };
+  static constexpr int kUnsolved = 1 << 30;
+  static constexpr size_t kMaxTerms = 48;  // larger sets split greedily
+
+  std::string key(const std::vector<Ex>& ex) const {
+    std::string k;
+    k.reserve(ex.size() * d_);
+    for (auto& t : ex) k.append(reinterpret_cast<const char*>(t.data()), d_);
+    return k;
+  }
+  // least operation count for the (sorted) term set, kUnsolved past the budget
+  int cost(const std::vector<Ex>& ex) {
+    bool all_const = true;
+    for (auto& t : ex)
+      for (int v = 0; v < d_; ++v)
+        if (t[v]) all_const = false;
+    if (all_const) return (int)ex.size() - 1;
+    if (ex.size() > kMaxTerms) return kUnsolved;
+    std::string k = key(ex);
+    auto it = memo_.find(k);
+    if (it != memo_.end()) return it->second.cost;
+    if (memo_.size() >= max_) return kUnsolved;
+    Best best{kUnsolved, -1, 0};
+    for (int v = 0; v < d_; ++v) {
+      std::set<int> levels;
+      for (auto& t : ex)
+        if (t[v]) levels.insert(t[v]);
+      for (int lv : levels) {
+        std::vector<Ex> A, B;
+        for (auto& t : ex) {
+          if (t[v] >= lv) {
+            Ex u = t;
+            u[v] = (uint8_t)(u[v] - lv);
+            A.push_back(u);
+          } else {
+            B.push_back(t);
+          }
+        }
+        std::sort(A.begin(), A.end());
+        const int ca = cost(A);
+        const int cb = B.empty() ? 0 : cost(B);
+        if (ca >= kUnsolved || cb >= kUnsolved) return kUnsolved;
+        if (ca + cb + 1 < best.cost) best = Best{ca + cb + 1, v, lv};
+      }
+    }
+    if (memo_.size() >= max_) return kUnsolved;
+    memo_.emplace(std::move(k), best);
+    return best.cost;
+  }
+
+  int d_;
+  size_t max_;
+  std::map<std::string, Best> memo_;
+};
+
+// Multivariate Horner: returns the name holding sum_i c_i prod_j x_j^e_ij.
+std::string horner(std::vector<Term> terms, Emitter& em, HornerPlan& plan) {
   const int d = em.dim();
   bool all_const = true;
   for (auto& t : terms)
@@ -102,34 +202,24 @@ std::string horner(std::vector<Term> terms, Emitter& em) {
     em.line("const double " + v + " = " + expr + ";");
     return v;
   }
-  int best = -1, cnt = -1;
-  for (int j = 0; j < d; ++j) {
-    int c = 0;
-    for (auto& t : terms) c += t.e[j] ? 1 : 0;
-    if (c > cnt) {
-      cnt = c;
-      best = j;
-    }
-  }
+  int best = -1, emin = 0;
+  plan.split(terms, best, emin);
   std::vector<Term> A, B;
-  int emin = 255;
-  for (auto& t : terms) {
-    if (t.e[best]) {
-      A.push_back(t);
-      emin = std::min<int>(emin, t.e[best]);
-    } else {
-      B.push_back(t);
-    }
-  }
+  for (auto& t : terms) (t.e[best] >= emin ? A : B).push_back(t);
   for (auto& t : A) t.e[best] = (uint8_t)(t.e[best] - emin);
-  std::string va = horner(A, em);
+  std::string va = horner(A, em, plan);
   std::string p = em.power(best, emin);
   std::string v = em.tmp();
   if (B.empty()) {
     em.line("const double " + v + " = " + p + " * " + va + ";");
   } else {
-    std::string vb = horner(B, em);
-    em.line("const double " + v + " = __builtin_fma(" + p + ", " + va + ", " + vb + ");");
+    // coefficients (c*) live in scalar registers: a scalar addend with a
+    // vector multiplicand takes the three-address fma
+    std::string vb = horner(B, em, plan);
+    if (vb[0] == 'c' && va[0] != 'c')
+      em.line("const double " + v + " = fma_s(" + p + ", " + va + ", " + vb + ");");
+    else
+      em.line("const double " + v + " = __builtin_fma(" + p + ", " + va + ", " + vb + ");");
   }
   return v;
 }
@@ -201,8 +291,8 @@ class CEmitter {
   std::ostringstream pre_, body_;
 };
 
-// Greedy multivariate Horner over a real (x) or complex (z) variable vector.
-Val chorner(std::vector<CTerm> terms, CEmitter& em) {
+// Multivariate Horner over a real (x) or complex (z) variable vector.
+Val chorner(std::vector<CTerm> terms, CEmitter& em, HornerPlan& plan) {
   const int d = em.dim();
   if (terms.empty()) return Val{"0.0", true};
   bool all_const = true;
@@ -217,34 +307,19 @@ Val chorner(std::vector<CTerm> terms, CEmitter& em) {
     em.line("const double " + v + " = " + expr + ";");
     return Val{v, true};
   }
-  int best = -1, cnt = -1;
-  for (int j = 0; j < d; ++j) {
-    int c = 0;
-    for (auto& t : terms) c += t.e[j] ? 1 : 0;
-    if (c > cnt) {
-      cnt = c;
-      best = j;
-    }
-  }
+  int best = -1, emin = 0;
+  plan.split(terms, best, emin);
   std::vector<CTerm> A, B;
-  int emin = 255;
-  for (auto& t : terms) {
-    if (t.e[best]) {
-      A.push_back(t);
-      emin = std::min<int>(emin, t.e[best]);
-    } else {
-      B.push_back(t);
-    }
-  }
+  for (auto& t : terms) (t.e[best] >= emin ? A : B).push_back(t);
   for (auto& t : A) t.e[best] = (uint8_t)(t.e[best] - emin);
-  Val va = chorner(A, em);
+  Val va = chorner(A, em, plan);
   std::string p = em.power(best, emin);
   std::string v = em.tmp();
   if (!em.cx()) {
     if (B.empty()) {
       em.line("const double " + v + " = " + p + " * " + va.name + ";");
     } else {
-      Val vb = chorner(B, em);
+      Val vb = chorner(B, em, plan);
       em.line("const double " + v + " = __builtin_fma(" + p + ", " + va.name + ", " + vb.name + ");");
     }
     return Val{v, true};
@@ -257,7 +332,7 @@ Val chorner(std::vector<CTerm> terms, CEmitter& em) {
       em.line("const cplx " + v + " = cmul(" + p + ", " + va.name + ");");
     return Val{v, false};
   }
-  Val vb = chorner(B, em);
+  Val vb = chorner(B, em, plan);
   std::string cb = vb.real ? "cmk(" + vb.name + ", 0.0)" : vb.name;
   if (va.real)
     em.line("const cplx " + v + " = cfmar(" + va.name + ", " + p + ", " + cb + ");");
@@ -356,7 +431,8 @@ std::string generate_complex_fn(const qmcj::Spec& s) {
   }
   for (int which = 0; which < 2; ++which) {
     CEmitter em(d, true);
-    Val v = chorner(which == 0 ? tu : tf, em);
+    HornerPlan plan(d, 0);  // greedy: complex products make the operation count a poor cost model
+    Val v = chorner(which == 0 ? tu : tf, em, plan);
     o << "  __device__ __forceinline__ cplx " << (which == 0 ? "U" : "F") << "(const cplx (&z)[" << d
       << "], const EvalArgs& a) const {\n";
     o << em.decls() << em.pre() << em.body();
@@ -411,18 +487,50 @@ std::string generate(const Spec& s) {
     for (int j = 0; j < d; ++j) t.e[j] = s.expo[(size_t)i * d + j];
     (i < s.n_u ? tu : tf).push_back(t);
   }
-  std::string U = horner(tu, em);
-  std::string F = s.n_f ? horner(tf, em) : std::string();
+  HornerPlan plan(d);
+  std::string U = horner(tu, em, plan);
+  std::string F = s.n_f ? horner(tf, em, plan) : std::string();
   std::ostringstream o;
   o << "#define QMC_RTC 1\n" << kDeviceSrc << "\n";
   o << "namespace qmcd {\nstruct JitReal {\n";
+  // the single-root form is only chosen when U and F are bounded away from 0
+  // and infinity on [0, 1]^d, so f is finite there
+  if (s.ru > 0 && s.rf > 0 && s.n_f) o << "  static constexpr bool kBounded = true;\n";
   o << "  __device__ __forceinline__ double operator()(const double (&x)[" << d
     << "], const EvalArgs& a) const {\n";
   o << em.header() << em.pre() << em.body();
-  o << "    double num = a.prefactor, den = 1.0;\n";
-  o << "    apply_pow<double>(" << U << ", " << s.pu_mode << ", " << s.pu_k << ", a.pow_u, num, den);\n";
-  if (s.n_f) o << "    apply_pow<double>(" << F << ", " << s.pf_mode << ", " << s.pf_k << ", a.pow_f, num, den);\n";
-  o << "    return num * fast_rcp(den);\n  }\n};\n}  // namespace qmcd\n";
+  if (s.ru > 0 && s.rf > 0 && s.n_f) {
+    // U^ru F^rf by binary powering, then one reciprocal square root
+    int nt = 0;
+    auto power = [&](const std::string& base, int e) {
+      std::string acc, b = base;
+      while (e) {
+        if (e & 1) {
+          if (acc.empty()) {
+            acc = b;
+          } else {
+            std::string t = "r" + std::to_string(nt++);
+            o << "    const double " << t << " = " << acc << " * " << b << ";\n";
+            acc = t;
+          }
+        }
+        e >>= 1;
+        if (e) {
+          std::string t = "r" + std::to_string(nt++);
+          o << "    const double " << t << " = " << b << " * " << b << ";\n";
+          b = t;
+        }
+      }
+      return acc;
+    };
+    std::string pu = power(U, s.ru), pf = power(F, s.rf);
+    o << "    return a.prefactor * fast_rsqrt(" << pu << " * " << pf << ");\n  }\n};\n}  // namespace qmcd\n";
+  } else {
+    o << "    double num = a.prefactor, den = 1.0;\n";
+    o << "    apply_pow<double>(" << U << ", " << s.pu_mode << ", " << s.pu_k << ", a.pow_u, num, den);\n";
+    if (s.n_f) o << "    apply_pow<double>(" << F << ", " << s.pf_mode << ", " << s.pf_k << ", a.pow_f, num, den);\n";
+    o << "    return num * fast_rcp(den);\n  }\n};\n}  // namespace qmcd\n";
+  }
   for (int w = 0; w < 2; ++w) {
     o << "extern \"C\" __global__ __launch_bounds__(QMCD_BLOCK) void qmc_jit_eval" << (w ? "64" : "32")
       << "(qmcd::EvalArgs a) {\n  qmcd::eval_real_body<" << d << ", " << tk << ", " << (w ? "false" : "true")

@@ -19,6 +19,9 @@ struct Spec {
   int S;   // shifts per thread group
   int vr;  // variance-reduction map compiled in (1) or out (0)
   int cplx = 0;  // deformed (complex) integrand
+  // > 0: real f = prefactor (U^ru F^rf)^(-1/2), one reciprocal square root for
+  // both powers (pow_u = -ru/2, pow_f = -rf/2); 0: the separate powers
+  int ru = 0, rf = 0;
 };
 
 struct Kernel {

@@ -89,6 +89,41 @@ void classify_power(double p, int& mode, int& k) {
   }
 }
 
+// One reciprocal square root for both powers of a real integrand when
+// pow_u, pow_f are non-positive multiples of 1/2, at least one not an
+// integer, and U^ru F^rf (ru = -2 pow_u, rf = -2 pow_f) stays a normal
+// double on [0, 1]^d.  With non-negative coefficients and a constant term c0,
+// c0 <= U <= sum c_U there (likewise F); any other polynomial keeps the
+// separate powers.  Returns false when the separate powers are kept.
+bool combined_root(uint32_t dim, uint32_t n_u, uint32_t n_f, const double* coef, const uint8_t* expo,
+                   double pow_u, double pow_f, int& ru, int& rf) {
+  ru = rf = 0;
+  if (!n_f || pow_u > 0 || pow_f > 0) return false;
+  const double tu = -2.0 * pow_u, tf = -2.0 * pow_f;
+  if (tu != std::floor(tu) || tf != std::floor(tf) || tu < 1 || tf < 1 || tu + tf > 24) return false;
+  if (std::fmod(tu, 2.0) == 0.0 && std::fmod(tf, 2.0) == 0.0) return false;  // integer powers: one reciprocal already
+  auto bounds = [&](uint32_t first, uint32_t count, double& lo, double& hi) {
+    lo = 0.0;
+    hi = 0.0;
+    for (uint32_t i = first; i < first + count; ++i) {
+      if (!(coef[i] >= 0.0)) return false;
+      hi += coef[i];
+      bool constant = true;
+      for (uint32_t j = 0; j < dim; ++j) constant = constant && expo[(size_t)i * dim + j] == 0;
+      if (constant) lo += coef[i];
+    }
+    return lo > 0.0;
+  };
+  double lu, hu, lf, hf;
+  if (!bounds(0, n_u, lu, hu) || !bounds(n_u, n_f, lf, hf)) return false;
+  const double top = tu * std::log(hu) + tf * std::log(hf);
+  const double bottom = tu * std::log(lu) + tf * std::log(lf);
+  if (top > std::log(1e300) || bottom < std::log(1e-300)) return false;
+  ru = (int)tu;
+  rf = (int)tf;
+  return true;
+}
+
 // carve `bytes` (256-aligned) from the context scratch, growing it if owned
 int scratch(qmc_context* c, size_t need, char** out) {
   need = (need + 255) & ~(size_t)255;
@@ -225,6 +260,7 @@ int run_lattice(qmc_context* c, qmc_integrand* f, uint64_t n, const uint64_t* z,
     if (it == f->jit.end()) {
       qmcj::Spec sp{dim, f->n_u, f->n_f, f->expo.data(), f->pu_mode, f->pu_k, f->pf_mode, f->pf_k, tsel,
                     cplx ? qmck::S_COMPLEX_JIT : c->jit_S, f->has_vr ? 1 : 0, cplx ? 1 : 0};
+      if (!cplx) combined_root(dim, f->n_u, f->n_f, f->coef.data(), f->expo.data(), f->pow_u, f->pow_f, sp.ru, sp.rf);
       if (qmcj::get(c->device, sp, &jk) == 0) {
         f->jit[jkey] = jk;
         use_jit = true;
@@ -1049,6 +1085,7 @@ int qmc_specialize_check(const qmc_integrand_desc* d, qmc_transform t, size_t* c
   if (const char* v = std::getenv("QMC_JIT_S")) S = atoi(v);
   const int cx = (d->flags & QMC_DEFORM) ? 1 : 0;
   qmcj::Spec sp{d->dim, d->n_u, d->n_f, d->expo, pu_mode, pu_k, pf_mode, pf_k, tsel, cx ? qmck::S_COMPLEX_JIT : S, 0, cx};
+  if (!cx) combined_root(d->dim, d->n_u, d->n_f, d->coef, d->expo, d->pow_u, d->pow_f, sp.ru, sp.rf);
   if (qmcj::compile_only(sp, code_bytes) != 0) return fail(QMC_EINVAL, "%s", qmcj::last_error());
   return QMC_OK;
 }

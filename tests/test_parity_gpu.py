@@ -132,7 +132,9 @@ def test_sidi_transform(ctx, dim, r):
     _check_sums(g["sums_re"], o, label=f"d{dim} r{r}")
 
 
-@pytest.mark.parametrize("pu,pf", [(1.0, 0.0), (-3.0, 2.0), (-2.5, 0.5), (-1.3, -2.0), (0.0, -1.0), (2.0, -0.5)])
+# the last three take the specialised kernel's single reciprocal square root of U^ru F^rf
+@pytest.mark.parametrize("pu,pf", [(1.0, 0.0), (-3.0, 2.0), (-2.5, 0.5), (-1.3, -2.0), (0.0, -1.0), (2.0, -0.5),
+                                   (-1.5, -2.5), (-3.5, -0.5), (-1.0, -1.5)])
 def test_power_classes(ctx, pu, pf):
     desc = W.random_real_small(seed=7, dim=4, n_u=4, n_f=5, pow_u=pu, pow_f=pf)
     n = 2003
