@@ -132,7 +132,11 @@ def cpu_baseline(job, target_seconds: float, threads: int):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_qmc_jit_eval32_sector_real_n100000007_m32.json")
-KERNEL_SOURCES = ["paper_1811_11720_amd/csrc/qmc_device.h", "paper_1811_11720_amd/csrc/qmc_jit.cpp"]
+KERNEL_SOURCES = [
+    "paper_1811_11720_amd/csrc/qmc_device.h",
+    "paper_1811_11720_amd/csrc/qmc_jit.cpp",
+    "paper_1811_11720_amd/csrc/qmc_runtime.cpp",  # specialisation choices and launch shape
+]
 
 
 def kernel_source_hash() -> str:
