@@ -54,7 +54,7 @@ int run_batch(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_secon
     const qmc_integrand* f = b.f;
     const bool cplx = (f->flags & QMC_DEFORM) != 0, fp32 = (f->flags & QMC_EVAL_FP32) != 0;
     Plan& p = plan[i];
-    const int dclass = qmck::dim_class(f->dim);
+    const int dclass = qmck::dim_class(f->dim, cplx);
     qmcd::EvalArgs probe;
     int tsel = 0;
     int trc = set_transform(probe, b.t, tsel);
@@ -385,23 +385,26 @@ static int variant_of(const qmc_request& q, qmck::BatchVariant& v) {
   int tsel = 0;
   int rc = set_transform(probe, q.t, tsel);
   if (rc) return rc;
-  v = qmck::BatchVariant{qmck::dim_class(f->dim), qmck::batch_tkc(tsel, f->has_vr), (f->flags & QMC_DEFORM) != 0,
+  const bool cplx = (f->flags & QMC_DEFORM) != 0;
+  v = qmck::BatchVariant{qmck::dim_class(f->dim, cplx), qmck::batch_tkc(tsel, f->has_vr), cplx,
                          (f->flags & QMC_EVAL_FP32) != 0};
   return QMC_OK;
 }
 
-// Cache lines: "gfx950 <dclass> <tkc> <complex> <fp32> <sv index> <tile points>".
+// Cache lines: "gfx950 <class's largest dimension> <tkc> <complex> <fp32> <sv index> <tile points>".
 void load_tune_cache(qmc_context* c) {
   if (c->tune_cache.empty()) return;
   FILE* fh = std::fopen(c->tune_cache.c_str(), "r");
   if (!fh) return;
-  int dc, tkc, cx, f32, sv;
+  int dmax, tkc, cx, f32, sv;
   unsigned long long tile;
   char arch[64];
-  while (std::fscanf(fh, "%63s %d %d %d %d %d %llu", arch, &dc, &tkc, &cx, &f32, &sv, &tile) == 7) {
-    if (std::strcmp(arch, "gfx950") != 0 || dc < 0 || dc > 3 || tkc < 0 || tkc >= qmck::TKC_COUNT || cx < 0 ||
-        cx > 1 || f32 < 0 || f32 > 1)
+  while (std::fscanf(fh, "%63s %d %d %d %d %d %llu", arch, &dmax, &tkc, &cx, &f32, &sv, &tile) == 7) {
+    if (std::strcmp(arch, "gfx950") != 0 || tkc < 0 || tkc >= qmck::TKC_COUNT || cx < 0 || cx > 1 || f32 < 0 ||
+        f32 > 1 || dmax < 1 || dmax > (int)QMC_MAX_DIM)
       continue;
+    const int dc = qmck::dim_class((uint32_t)dmax, cx != 0);
+    if (qmck::dim_class_max(dc, cx != 0) != dmax) continue;  // not a class boundary
     const int v = qmck::BatchVariant{dc, tkc, cx != 0, f32 != 0}.index();
     if (sv >= 0 && sv < qmck::BATCH_SV_VARIANTS) c->batch_sv[v] = sv;
     if (tile >= 256 && tile <= (1ull << 24)) c->batch_tile[v] = tile;
@@ -462,7 +465,8 @@ int autotune(qmc_context* c, const qmc_request* reqs, uint32_t count, uint32_t* 
     c->batch_tile[vi] = best_tile;
     if (!c->tune_cache.empty()) {
       if (FILE* fh = std::fopen(c->tune_cache.c_str(), "a")) {
-        std::fprintf(fh, "gfx950 %d %d %d %d %d %llu\n", var.dclass, var.tkc, var.cplx ? 1 : 0, var.fp32 ? 1 : 0,
+        std::fprintf(fh, "gfx950 %d %d %d %d %d %llu\n", qmck::dim_class_max(var.dclass, var.cplx), var.tkc,
+                     var.cplx ? 1 : 0, var.fp32 ? 1 : 0,
                      best_sv, (unsigned long long)best_tile);
         std::fclose(fh);
       }

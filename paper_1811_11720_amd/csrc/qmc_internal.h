@@ -9,9 +9,18 @@
 namespace qmck {
 
 // dimension classes of the ahead-of-time kernels (register arrays are sized
-// by the class; the unused tail dimensions are skipped by uniform branches)
-inline int dim_class(uint32_t dim) { return dim <= 4 ? 0 : dim <= 8 ? 1 : dim <= 12 ? 2 : 3; }
-inline int dim_class_max(int c) { return 4 * (c + 1); }
+// by the class; the unused tail dimensions are skipped by uniform branches):
+// real kernels up to 4, 8, 12, 16 variables, complex ones up to 4, 8, 10, 12
+// (a 12-variable Jacobian no longer fits in registers, so 9 and 10 variables
+// get a class of their own)
+constexpr int DIM_CLASSES = 4;
+inline int dim_class(uint32_t dim, bool cplx) {
+  return dim <= 4 ? 0 : dim <= 8 ? 1 : dim <= (cplx ? 10u : 12u) ? 2 : 3;
+}
+inline int dim_class_max(int c, bool cplx) {
+  static const int real[DIM_CLASSES] = {4, 8, 12, 16}, complex[DIM_CLASSES] = {4, 8, 10, 12};
+  return (cplx ? complex : real)[c];
+}
 
 enum Kind { KIND_REAL = 0 };
 
@@ -58,13 +67,13 @@ struct BatchVariant {
   bool cplx, fp32;
   int index() const { return ((dclass * TKC_COUNT + tkc) * 2 + (cplx ? 1 : 0)) * 2 + (fp32 ? 1 : 0); }
 };
-constexpr int BATCH_VARIANTS = 4 * TKC_COUNT * 2 * 2;
+constexpr int BATCH_VARIANTS = DIM_CLASSES * TKC_COUNT * 2 * 2;
 inline int batch_tkc(int tsel, bool has_vr) {
   if (has_vr) return TKC_ANY;
   return tsel == TSEL_KOROBOV3 ? TKC_KOROBOV3 : tsel == TSEL_BAKER ? TKC_BAKER : TKC_ANY;
 }
 // Real kernels come with sv index i = 0, 1, 2 (2^i points per decoded
-// monomial); complex kernels exist for classes up to 12 variables, sv index 0.
+// monomial); complex kernels have sv index 0 only.
 constexpr int BATCH_SV_VARIANTS = 3;
 BatchFn batch_kernel(const BatchVariant& v, int sv);
 int occupancy_batch(const BatchVariant& v, int sv);

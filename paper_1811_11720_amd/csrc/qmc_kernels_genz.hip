@@ -12,7 +12,7 @@ __global__ __launch_bounds__(QMCD_BLOCK) void k_eval_genz(qmcd::EvalArgs a) {
 }
 
 using EvalFn = void (*)(qmcd::EvalArgs);
-static EvalFn g_genz[4][2] = {
+static EvalFn g_genz[DIM_CLASSES][2] = {
     {k_eval_genz<4, false>, k_eval_genz<4, true>},
     {k_eval_genz<8, false>, k_eval_genz<8, true>},
     {k_eval_genz<12, false>, k_eval_genz<12, true>},

@@ -10,10 +10,10 @@ __global__ __launch_bounds__(QMCD_BLOCK) void k_hist(qmcd::EvalArgs a, qmcd::His
 
 using HistFn = void (*)(qmcd::EvalArgs, qmcd::HistArgs);
 
-#define QMC_HROW(D) {{k_hist<D, false, 0>, k_hist<D, false, 1>}, {k_hist<D, true, 0>, k_hist<D, true, 1>}}
-// complex histograms exist for the classes up to 12 variables (index 3 is real only)
-static HistFn g_hist[4][2][2] = {QMC_HROW(4), QMC_HROW(8), QMC_HROW(12),
-                                 {{k_hist<16, false, 0>, k_hist<16, false, 1>}, {nullptr, nullptr}}};
+#define QMC_HROW(DR, DC) {{k_hist<DR, false, 0>, k_hist<DR, false, 1>}, {k_hist<DC, true, 0>, k_hist<DC, true, 1>}}
+// [class][complex][pass]; the real and complex classes differ above 8 variables
+static HistFn g_hist[DIM_CLASSES][2][2] = {
+    QMC_HROW(4, 4), QMC_HROW(8, 8), QMC_HROW(12, 10), QMC_HROW(16, 12)};
 #undef QMC_HROW
 
 hipError_t launch_hist(const qmcd::EvalArgs& a, const qmcd::HistArgs& h, int dclass, bool cplx, int pass, dim3 grid,

@@ -248,7 +248,7 @@ int run_lattice(qmc_context* c, qmc_integrand* f, uint64_t n, const uint64_t* z,
   const uint32_t rows = cplx ? 2 * m : m;
   const uint64_t npts = k1 - k0;
   const bool idx32 = n <= (1ull << 31);
-  const int dclass = qmck::dim_class(dim);
+  const int dclass = qmck::dim_class(dim, cplx);
 
   // specialised kernel for large jobs (compiled once per integrand structure)
   qmcj::Kernel jk;
@@ -399,7 +399,7 @@ int run_histogram(qmc_context* c, const qmc_integrand* f, uint64_t n, const uint
   h.hist = (unsigned long long*)(ws + off_h);
   h.bins = bins;
   h.scale = 0.0;
-  const int dclass = qmck::dim_class(dim);
+  const int dclass = qmck::dim_class(dim, cplx);
   HIPCHK(qmck::launch_hist(a, h, dclass, cplx, 0, dim3(nb), c->stream));
   HIPCHK(hipMemcpyAsync(c->h_stage, ws + off_part, sz_part, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));

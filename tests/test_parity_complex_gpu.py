@@ -95,7 +95,7 @@ def test_u_on_the_contour(ctx):
 
 @pytest.mark.parametrize("tr", [KOR3, (W.T_BAKER, 0, 0), (W.T_KOROBOV, 2, 2), (W.T_NONE, 0, 0), (W.T_SIDI, 3, 0)],
                          ids=lambda t: f"T{t[0]}_{t[1]}_{t[2]}")
-@pytest.mark.parametrize("dim", [2, 3, 5, 8, 12])
+@pytest.mark.parametrize("dim", [2, 3, 5, 8, 9, 10, 11, 12])
 def test_random_complex_integrands(ctx, dim, tr):
     desc = W.sector(seed=300 + dim, dim=dim, n_u=3, n_f=6, pow_u=-2.0, pow_f=-1.5, complex_=True, lam=0.5,
                     neg_frac=0.3)
