@@ -10,15 +10,16 @@ namespace qmck {
 
 // dimension classes of the ahead-of-time kernels (register arrays are sized
 // by the class; the unused tail dimensions are skipped by uniform branches):
-// real kernels up to 4, 8, 12, 16 variables, complex ones up to 4, 8, 10, 12
-// (a 12-variable Jacobian no longer fits in registers, so 9 and 10 variables
-// get a class of their own)
-constexpr int DIM_CLASSES = 4;
+// real kernels up to 4, 8, 12, 16 variables (index 4 unused), complex ones
+// up to 4, 6, 8, 10, 12: the complex kernels hold the d x d Jacobian in
+// registers, so their cost and register footprint grow with the class
+constexpr int DIM_CLASSES = 5;
 inline int dim_class(uint32_t dim, bool cplx) {
-  return dim <= 4 ? 0 : dim <= 8 ? 1 : dim <= (cplx ? 10u : 12u) ? 2 : 3;
+  if (cplx) return dim <= 4 ? 0 : dim <= 6 ? 1 : dim <= 8 ? 2 : dim <= 10 ? 3 : 4;
+  return dim <= 4 ? 0 : dim <= 8 ? 1 : dim <= 12 ? 2 : 3;
 }
 inline int dim_class_max(int c, bool cplx) {
-  static const int real[DIM_CLASSES] = {4, 8, 12, 16}, complex[DIM_CLASSES] = {4, 8, 10, 12};
+  static const int real[DIM_CLASSES] = {4, 8, 12, 16, 16}, complex[DIM_CLASSES] = {4, 6, 8, 10, 12};
   return (cplx ? complex : real)[c];
 }
 
@@ -32,6 +33,11 @@ constexpr int sv_real(int dmax, bool fp32) { return (fp32 || dmax <= 8) ? 2 : 1;
 constexpr int S_COMPLEX = 2;
 // ... of the specialised complex kernels (register pressure: one point's Jacobian at a time)
 constexpr int S_COMPLEX_JIT = 1;
+// Waves per SIMD the table-driven complex kernels are compiled for.  They are
+// latency bound (scalar table loads, dependent fp64 chains), so more waves pay
+// even at the price of some spilled registers, up to 8 variables; the 10- and
+// 12-variable classes would spill most of the Jacobian and stay at one wave.
+constexpr int complex_waves(int dmax) { return dmax <= 4 ? 4 : dmax <= 6 ? 3 : dmax <= 8 ? 2 : 1; }
 // largest dimension of the complex (deformed) kernels
 constexpr uint32_t MAX_DIM_COMPLEX = 12;
 

@@ -29,13 +29,13 @@ using EvalFn = void (*)(qmcd::EvalArgs);
         {k_eval_real<D, qmcd::TK_SIDI, false>, k_eval_real<D, qmcd::TK_SIDI, true>},             \
   }
 
-static EvalFn g_real[DIM_CLASSES][TSEL_COUNT][2] = {QMC_ROW(4), QMC_ROW(8), QMC_ROW(12), QMC_ROW(16)};
+static EvalFn g_real[DIM_CLASSES][TSEL_COUNT][2] = {QMC_ROW(4), QMC_ROW(8), QMC_ROW(12), QMC_ROW(16), QMC_ROW(16)};
 #undef QMC_ROW
 
-// complex kernels: one table per dimension class, defined in qmc_kernels_c{4,8,10,12}.hip
+// complex kernels: one table per dimension class, defined in qmc_kernels_c{4,6,8,10,12}.hip
 using EvalTable = EvalFn[TSEL_COUNT][2];
-extern EvalTable g_complex4, g_complex8, g_complex10, g_complex12;
-static EvalTable* const g_complex[DIM_CLASSES] = {&g_complex4, &g_complex8, &g_complex10, &g_complex12};
+extern EvalTable g_complex4, g_complex6, g_complex8, g_complex10, g_complex12;
+static EvalTable* const g_complex[DIM_CLASSES] = {&g_complex4, &g_complex6, &g_complex8, &g_complex10, &g_complex12};
 
 int occupancy_eval(bool cplx, int dclass, int tsel, bool idx32) {
   int occ = 0;
@@ -127,15 +127,15 @@ hipError_t launch_finalize_rows(const RowRef* rows, uint32_t nrows, double* out,
   return hipLaunchKernel((const void*)k_finalize_rows, dim3(nrows), dim3(QMCD_BLOCK), args, 0, st);
 }
 
-extern BatchFn g_batch4[TKC_COUNT][2][2][3], g_batch8[TKC_COUNT][2][2][3], g_batch10[TKC_COUNT][2][2][3],
-    g_batch12[TKC_COUNT][2][2][3], g_batch16[TKC_COUNT][2][2][3];
+extern BatchFn g_batch4[TKC_COUNT][2][2][3], g_batch6[TKC_COUNT][2][2][3], g_batch8[TKC_COUNT][2][2][3],
+    g_batch10[TKC_COUNT][2][2][3], g_batch12[TKC_COUNT][2][2][3], g_batch16[TKC_COUNT][2][2][3];
 
 BatchFn batch_kernel(const BatchVariant& v, int sv) {
   if (sv < 0 || sv >= BATCH_SV_VARIANTS || v.tkc < 0 || v.tkc >= TKC_COUNT || v.dclass < 0 || v.dclass >= DIM_CLASSES)
     return nullptr;
   using Table = BatchFn[TKC_COUNT][2][2][3];
-  static Table* const real[DIM_CLASSES] = {&g_batch4, &g_batch8, &g_batch12, &g_batch16};
-  static Table* const complex[DIM_CLASSES] = {&g_batch4, &g_batch8, &g_batch10, &g_batch12};
+  static Table* const real[DIM_CLASSES] = {&g_batch4, &g_batch8, &g_batch12, &g_batch16, &g_batch16};
+  static Table* const complex[DIM_CLASSES] = {&g_batch4, &g_batch6, &g_batch8, &g_batch10, &g_batch12};
   return (*(v.cplx ? complex : real)[v.dclass])[v.tkc][v.cplx ? 1 : 0][v.fp32 ? 1 : 0][sv];
 }
 

@@ -17,6 +17,7 @@ static EvalFn g_genz[DIM_CLASSES][2] = {
     {k_eval_genz<8, false>, k_eval_genz<8, true>},
     {k_eval_genz<12, false>, k_eval_genz<12, true>},
     {k_eval_genz<16, false>, k_eval_genz<16, true>},
+    {k_eval_genz<16, false>, k_eval_genz<16, true>},  // real classes stop at index 3
 };
 
 int occupancy_genz(int dclass, bool idx32) {

@@ -13,7 +13,7 @@ using HistFn = void (*)(qmcd::EvalArgs, qmcd::HistArgs);
 #define QMC_HROW(DR, DC) {{k_hist<DR, false, 0>, k_hist<DR, false, 1>}, {k_hist<DC, true, 0>, k_hist<DC, true, 1>}}
 // [class][complex][pass]; the real and complex classes differ above 8 variables
 static HistFn g_hist[DIM_CLASSES][2][2] = {
-    QMC_HROW(4, 4), QMC_HROW(8, 8), QMC_HROW(12, 10), QMC_HROW(16, 12)};
+    QMC_HROW(4, 4), QMC_HROW(8, 6), QMC_HROW(12, 8), QMC_HROW(16, 10), QMC_HROW(16, 12)};
 #undef QMC_HROW
 
 hipError_t launch_hist(const qmcd::EvalArgs& a, const qmcd::HistArgs& h, int dclass, bool cplx, int pass, dim3 grid,
