@@ -569,6 +569,12 @@ __device__ __forceinline__ cplx uf_fp64(const Fn& fn, const cplx (&z)[D], const 
   return cmul(num, crcp(den));
 }
 
+// Keeps a branch on a uniform condition a branch.  Left alone, the compiler
+// evaluates both sides of a short conditional block and selects, which for
+// exponents read from a table means doing the work of every variable of every
+// monomial.
+__device__ __forceinline__ void keep_branch() { asm volatile(""); }
+
 // Generic (table-driven) polynomial pieces for the deformed integrand.
 template <int DMAX>
 struct GenericComplex {
@@ -592,13 +598,18 @@ struct GenericComplex {
       for (int j = 0; j < DMAX; ++j) {
         // x^e, e x^(e-1), e (e-1) x^(e-2)
         double pe = 1.0, pe1 = 0.0, pe2 = 0.0;
-        if (e[j] >= 1u) {
+        if (e[j] == 1u) {
+          keep_branch();
+          pe = x[j];
+          pe1 = 1.0;
+        } else if (e[j] >= 2u) {
+          keep_branch();
           double q2 = 1.0;  // x^(e-2)
           for (uint32_t t = 2; t < e[j]; ++t) q2 *= x[j];
-          double q1 = e[j] >= 2u ? q2 * x[j] : 1.0;  // x^(e-1)
+          const double q1 = q2 * x[j];  // x^(e-1)
           pe = q1 * x[j];
           pe1 = (double)e[j] * q1;
-          pe2 = e[j] >= 2u ? (double)(e[j] * (e[j] - 1u)) * q2 : 0.0;
+          pe2 = (double)(e[j] * (e[j] - 1u)) * q2;
         }
         P[j] = pe;
         D1[j] = pe1;
@@ -614,13 +625,20 @@ struct GenericComplex {
 #pragma unroll
       for (int j = 0; j < DMAX; ++j) {
         if (e[j] == 0u) continue;
+        keep_branch();
         g[j] = __builtin_fma(pre[j] * D1[j], suf[j + 1], g[j]);
-        if (e[j] >= 2u) H[Tri<DMAX>::at(j, j)] = __builtin_fma(pre[j] * D2[j], suf[j + 1], H[Tri<DMAX>::at(j, j)]);
+        if (e[j] >= 2u) {
+          keep_branch();
+          H[Tri<DMAX>::at(j, j)] = __builtin_fma(pre[j] * D2[j], suf[j + 1], H[Tri<DMAX>::at(j, j)]);
+        }
         double mid = pre[j] * D1[j];  // c prod_{q<j} P_q * D1_j * prod_{j<q<l} P_q
 #pragma unroll
         for (int l = j + 1; l < DMAX; ++l) {
-          if (e[l] != 0u) H[Tri<DMAX>::at(l, j)] = __builtin_fma(mid * D1[l], suf[l + 1], H[Tri<DMAX>::at(l, j)]);
-          mid *= P[l];
+          if (e[l] != 0u) {  // P_l = 1 otherwise
+            keep_branch();
+            H[Tri<DMAX>::at(l, j)] = __builtin_fma(mid * D1[l], suf[l + 1], H[Tri<DMAX>::at(l, j)]);
+            mid *= P[l];
+          }
         }
       }
     }
