@@ -446,6 +446,90 @@ def bench_sector_complex(a, Q, W, torch):
     return 0
 
 
+def bench_plain(a, Q, W, torch):
+    """The d=3 product integrand (exact integral 1) at n=10007, m=10: the
+    single-job latency, the same job as 1024 replicas with distinct shift
+    seeds in one batch launch (QMC_SPECIALISE: the kernel generated for the
+    integrand), and one job at n ~ 1e7 (the small lattice alone cannot fill
+    the GPU)."""
+    job = W.job_plain_product()
+    flops = desc_flops(job.desc, job.transform)
+    ctx = Q.Context(0)
+    f = ctx.integrand(job.desc)
+    for _ in range(a.warmup):
+        ctx.integrate(f, job.n, job.z, job.m, job.seed, job.transform)
+    torch.cuda.synchronize()
+    lat, dev = [], []
+    for _ in range(max(a.steps, 20)):
+        t0 = time.perf_counter()
+        r = ctx.integrate(f, job.n, job.z, job.m, job.seed, job.transform)
+        lat.append(time.perf_counter() - t0)
+        dev.append(r["device_seconds"])
+    single = {"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+              "device_ms": float(np.median(dev) * 1e3), "estimate": r["re"], "error": r["err_re"]}
+    print(f"[plain] n={job.n}: p50 {single['p50_ms']:.3f} ms", file=sys.stderr, flush=True)
+    reps = 1024
+    # the replicas share one integrand, run in the kernel generated for it
+    spec = copy.copy(job.desc)
+    spec.specialise = True
+    fs = ctx.integrand(spec)
+    reqs = [dict(f=fs, n=job.n, z=job.z, m=job.m, seed=job.seed + 1 + i, transform=job.transform) for i in range(reps)]
+    for _ in range(a.warmup):
+        ctx.integrate_batch(reqs)
+    torch.cuda.synchronize()
+    bdev = []
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        res = ctx.integrate_batch(reqs)
+        bdev.append(res[0]["device_seconds"])
+    el = (time.perf_counter() - t0) / a.steps
+    ev = reps * job.n * job.m
+    kern = float(np.median(bdev))
+    worst = max(abs(x["re"] - 1.0) for x in res)
+    replicas = {"replicas": reps, "evals": ev, "evals_per_s": ev / el, "device_ms": kern * 1e3,
+                "evals_per_s_device": ev / kern, "tflops": flops * ev / kern / 1e12,
+                "frac": flops * ev / kern / 1e12 / FP64_VECTOR_PEAK_TFLOPS, "max_abs_error_vs_exact": worst}
+    print(f"[plain] {reps} replicas: {ev / kern:.3e} evals/s on the device", file=sys.stderr, flush=True)
+    fs.close()
+    nl = W.next_table_n(10 ** 7)
+    z = W.z_for(nl, job.desc.dim)
+    for _ in range(a.warmup):
+        ctx.integrate(f, nl, z, job.m, job.seed, job.transform)
+    torch.cuda.synchronize()
+    ldev = []
+    for _ in range(a.steps):
+        r = ctx.integrate(f, nl, z, job.m, job.seed, job.transform)
+        ldev.append(r["device_seconds"])
+    kl = float(np.median(ldev))
+    large = {"n": nl, "path": "specialised" if r["path"] == 1 else "table-driven",
+             "evals_per_s_device": nl * job.m / kl, "tflops": flops * nl * job.m / kl / 1e12,
+             "frac": flops * nl * job.m / kl / 1e12 / FP64_VECTOR_PEAK_TFLOPS, "estimate": r["re"], "error": r["err_re"]}
+    print(f"[plain] n={nl}: {nl * job.m / kl:.3e} evals/s on the device", file=sys.stderr, flush=True)
+    f.close()
+    ctx.close()
+    out = {
+        "metric": "lattice-point integrand evals/s (FP64) + p50/p99 request latency at rel err",
+        "value": ev / el,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": el * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"plain_product d=3, n={job.n}, m={job.m}, Korobov r=3, {reps} replicas per batch",
+                   "flops_per_eval": flops},
+        "single": single,
+        "replicas": replicas,
+        "large_n": large,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def bench_serve(a, Q, W, torch):
     """Serving: requests of 10-500 integrands from the batch pool, each with a
     relative target log-uniform in [1e-8, 1e-4], arriving as a Poisson process
@@ -561,7 +645,8 @@ def main():
     ap.add_argument("--m", type=int, default=32)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--workload", choices=["sector_real", "sector_complex", "batch", "serve", "genz", "cbc", "copy"],
+    ap.add_argument("--workload", choices=["sector_real", "sector_complex", "batch", "serve", "genz", "cbc", "copy",
+                                           "plain"],
                     default="sector_real")
     ap.add_argument("--rel-tol", type=float, default=1e-8, help="sector_complex: relative goal")
     ap.add_argument("--max-evals-complex", type=int, default=2 ** 37, help="sector_complex: evaluation cap")
@@ -602,6 +687,8 @@ def main():
         return bench_cbc(a, Q, W, torch)
     if a.workload == "sector_complex":
         return bench_sector_complex(a, Q, W, torch)
+    if a.workload == "plain":
+        return bench_plain(a, Q, W, torch)
     job = W.job_sector_real(a.n)
     job.m = a.m
     ctx = Q.Context(0)

@@ -132,8 +132,13 @@ int qmc_set_lattice_builder(qmc_context* ctx, uint64_t max_n);
 typedef struct qmc_integrand qmc_integrand;
 
 enum {
-  QMC_DEFORM = 1u,    /* complex result: contour deformation with parameter lambda */
-  QMC_EVAL_FP32 = 2u  /* evaluate U, F and the powers in fp32, accumulate in fp64 */
+  QMC_DEFORM = 1u,     /* complex result: contour deformation with parameter lambda */
+  QMC_EVAL_FP32 = 2u,  /* evaluate U, F and the powers in fp32, accumulate in fp64 */
+  QMC_SPECIALISE = 4u  /* batches and serving: run the real fp64 jobs of this integrand in a kernel generated
+                          for its structure (compiled at first use, a few seconds; shared by integrands of the
+                          same structure) instead of the table-driven kernels.  The per-shift sums of a job
+                          then come from that kernel, still the same alone or in any batch.  Single
+                          qmc_integrate calls choose by size and ignore the flag. */
 };
 
 /*
@@ -151,7 +156,7 @@ typedef struct {
   const double* coef;    /* host [n_u + n_f], finite */
   const uint8_t* expo;   /* host [(n_u + n_f) * dim], row-major, each <= QMC_MAX_EXP */
   double pow_u, pow_f, prefactor; /* finite */
-  uint32_t flags;        /* QMC_DEFORM | QMC_EVAL_FP32 */
+  uint32_t flags;        /* QMC_DEFORM | QMC_EVAL_FP32 | QMC_SPECIALISE */
   double lambda;         /* deformation parameter, used iff QMC_DEFORM */
 } qmc_integrand_desc;
 

@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libqmc.so")
 QMC_OK, QMC_PENDING = 0, 1
 QMC_EINVAL, QMC_ENOMEM, QMC_EDEVICE, QMC_EBUSY, QMC_ENOTFOUND, QMC_ECANCELED, QMC_EUNSUPPORTED = (
     -1, -2, -3, -4, -5, -6, -7)
-QMC_DEFORM, QMC_EVAL_FP32 = 1, 2
+QMC_DEFORM, QMC_EVAL_FP32, QMC_SPECIALISE = 1, 2, 4
 T_NONE, T_KOROBOV, T_BAKER, T_SIDI = 0, 1, 2, 3
 QMC_CONVERGED, QMC_MAXEVAL_HIT, QMC_NONFINITE, QMC_VR_FALLBACK, QMC_DEFORM_SIGN = 1, 2, 4, 8, 16
 ERRMODE_ALL, ERRMODE_LARGEST = 0, 1
@@ -186,7 +186,8 @@ def _desc_struct(desc, keep):
     coef = np.ascontiguousarray(desc.coef, dtype=np.float64)
     expo = np.ascontiguousarray(desc.expo, dtype=np.uint8)
     keep.extend([coef, expo])
-    flags = (QMC_DEFORM if getattr(desc, "deform", False) else 0) | (QMC_EVAL_FP32 if getattr(desc, "fp32", False) else 0)
+    flags = ((QMC_DEFORM if getattr(desc, "deform", False) else 0) | (QMC_EVAL_FP32 if getattr(desc, "fp32", False) else 0)
+             | (QMC_SPECIALISE if getattr(desc, "specialise", False) else 0))
     return IntegrandDesc(desc.dim, desc.n_u, desc.n_f, _dp(coef), expo.ctypes.data_as(C.POINTER(C.c_uint8)),
                          desc.pow_u, desc.pow_f, desc.prefactor, flags, float(getattr(desc, "lam", 0.0)))
 

@@ -46,8 +46,11 @@ int run_batch(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_secon
     uint64_t tile_points;
     size_t part_off, sh_off, row0;
     double cost;
+    bool use_jit = false;  // the integrand's specialised batch kernel (QMC_SPECIALISE)
+    qmcj::Kernel jk;
   };
   std::vector<Plan> plan(J);
+  std::vector<hipFunction_t> jit_fns;  // distinct specialised kernels of this round
   size_t n_part = 0, n_sh = 0, n_rows = 0;
   for (uint32_t i = 0; i < J; ++i) {
     BatchJob& b = *jobs[i];
@@ -61,8 +64,16 @@ int run_batch(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_secon
     if (trc) return trc;
     p.var = qmck::BatchVariant{dclass, qmck::batch_tkc(tsel, f->has_vr), cplx, fp32};
     p.variant = p.var.index();
+    if (!cplx && !fp32 && (f->flags & QMC_SPECIALISE) && c->jit && specialised_kernel(c, b.f, tsel, &p.jk) == 0 &&
+        p.jk.batch) {
+      // jobs of one specialised kernel form a launch of their own
+      p.use_jit = true;
+      auto it = std::find(jit_fns.begin(), jit_fns.end(), p.jk.batch);
+      p.variant = qmck::BATCH_VARIANTS + (int)(it - jit_fns.begin());
+      if (it == jit_fns.end()) jit_fns.push_back(p.jk.batch);
+    }
     const uint32_t S = cplx ? qmck::S_COMPLEX : qmck::S_REAL;
-    const uint64_t tuned = c->batch_tile[p.variant];
+    const uint64_t tuned = p.use_jit ? 0 : c->batch_tile[p.variant];
     const uint64_t tmin = tuned ? tuned : (cplx ? c->batch_tile_complex : c->batch_tile_real);
     uint64_t tp = std::max<uint64_t>(tmin, (b.n + c->batch_max_ktiles - 1) / c->batch_max_ktiles);
     tp = (tp + QMCD_BLOCK - 1) / QMCD_BLOCK * QMCD_BLOCK;
@@ -152,6 +163,8 @@ int run_batch(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_secon
     qmck::BatchVariant var;
     int variant;
     uint32_t first, count, prefix_off;
+    bool jit;
+    qmcj::Kernel jk;
   };
   std::vector<Launch> launches;
   uint32_t pos = 0, ppos = 0;
@@ -159,6 +172,8 @@ int run_batch(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_secon
     Launch L;
     L.var = plan[kv.second.front()].var;
     L.variant = kv.first;
+    L.jit = plan[kv.second.front()].use_jit;
+    L.jk = plan[kv.second.front()].jk;
     L.first = pos;
     L.count = (uint32_t)kv.second.size();
     L.prefix_off = ppos;
@@ -182,6 +197,13 @@ int run_batch(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_secon
     HIPCHK(qmck::launch_fill_u64(d_sign, J, 0ull, st));
     for (uint32_t v = 0; v < (uint32_t)launches.size(); ++v) {
       const Launch& L = launches[v];
+      if (L.jit) {
+        const uint32_t blocks = (uint32_t)std::max(1, L.jk.occ_batch) * (uint32_t)c->cus;
+        HIPCHK(qmcj::launch_batch(L.jk, (const qmcd::EvalArgs*)(ws + o_items), (const uint32_t*)(ws + o_order) + L.first,
+                                  (const uint32_t*)(ws + o_prefix) + L.prefix_off, L.count,
+                                  (uint32_t*)(ws + o_cnt) + v, blocks, st));
+        continue;
+      }
       const int sv = L.var.cplx ? 0 : c->batch_sv[L.variant];
       int occ = qmck::occupancy_batch(L.var, sv);
       uint32_t blocks = (uint32_t)std::max(1, occ) * (uint32_t)c->cus;

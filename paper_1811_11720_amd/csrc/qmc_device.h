@@ -1243,6 +1243,51 @@ __device__ __forceinline__ void eval_complex_body(const EvalArgs& a, const Fn& f
   eval_complex_sched<DMAX, TK, IDX32, S, EXACT, Fn, VRM, false>(a, fn, grid_sched(a, S));
 }
 
+// ------------------------------------------------------------------ persistent tile loop of the batch kernels
+// Workgroups pop tile numbers from an atomic counter until the list is
+// exhausted.  Tile t belongs to the item i with prefix[i] <= t < prefix[i+1]
+// (items in `order`, heaviest first); within the item, t - prefix[i] =
+// group * ktiles + kt.  A tile (points [kt*T, kt*T + T), shifts of the group)
+// is summed by one workgroup into column kt of the item's partial[][], so
+// per-shift sums depend only on the integral's own tiling, never on the rest
+// of the batch.  body(a, sched) evaluates one tile.
+template <int S, class Body>
+__device__ __forceinline__ void batch_tiles(const EvalArgs* __restrict__ items, const uint32_t* __restrict__ order,
+                                            const uint32_t* __restrict__ prefix, uint32_t nitems,
+                                            uint32_t* __restrict__ counter, const Body& body) {
+  __shared__ uint32_t next;
+  const uint32_t total = prefix[nitems];
+  for (;;) {
+    if (threadIdx.x == 0) next = atomicAdd(counter, 1u);
+    __syncthreads();
+    const uint32_t t = __builtin_amdgcn_readfirstlane(next);
+    __syncthreads();
+    if (t >= total) return;  // every wave reaches this once the list is drained
+    // item i with prefix[i] <= t < prefix[i+1] (uniform binary search)
+    uint32_t lo = 0, hi = nitems;
+    while (hi - lo > 1) {
+      uint32_t mid = (lo + hi) >> 1;
+      if (prefix[mid] <= t)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    const EvalArgs& a = items[order[lo]];
+    const uint32_t local = t - prefix[lo];
+    const uint32_t kt = local % a.ktiles, g = local / a.ktiles;
+    const uint64_t k0 = (uint64_t)kt * a.tile_points;
+    Sched sc;
+    sc.k = k0 + threadIdx.x;
+    sc.k_end = (k0 + a.tile_points < a.n) ? k0 + a.tile_points : a.n;
+    sc.stride = QMCD_BLOCK;
+    sc.step = a.step;
+    sc.col = kt;
+    sc.s0 = g * S;
+    body(a, sc);
+    __syncthreads();  // the reduction's LDS is reused by the next tile
+  }
+}
+
 // ------------------------------------------------------------------ histograms for the VR fit (Sec. 2.4)
 
 // |f| at the raw points x = {k z/n + Delta} of one shifted lattice (no

@@ -124,6 +124,9 @@ GrowthStep growth_step(qmc_context* c, const qmc_request& q, const qmc_result& r
 // Builds (qmc_cbc) and registers the lattice of the smallest prime >= want
 // with max(dim, 10) components; returns its size (0 on failure).
 uint64_t build_lattice(qmc_context* c, uint64_t want, uint32_t dim);
+// The integrand's specialised kernels for transform selector tsel (compiled
+// on first use, shared by integrands of the same structure); 0 on success.
+int specialised_kernel(qmc_context* c, qmc_integrand* f, int tsel, qmcj::Kernel* out);
 // fill the integrand/transform part of an EvalArgs
 int fill_integrand_args(qmcd::EvalArgs& a, const qmc_integrand* f, const qmc_transform& t, int& tsel);
 

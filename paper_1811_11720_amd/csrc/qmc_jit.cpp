@@ -25,6 +25,7 @@
 #include <string>
 #include <vector>
 
+#include "qmc_internal.h"
 #include "qmc_jit.h"
 
 namespace {
@@ -446,8 +447,8 @@ std::string generate_complex_fn(const qmcj::Spec& s) {
 
 struct Module {
   hipModule_t mod = nullptr;
-  hipFunction_t f32 = nullptr, f64 = nullptr;
-  int occ_blocks = 0;
+  hipFunction_t f32 = nullptr, f64 = nullptr, batch = nullptr;
+  int occ_blocks = 0, occ_batch = 0;
 };
 
 std::mutex g_mu;
@@ -531,6 +532,12 @@ std::string generate(const Spec& s) {
     if (s.n_f) o << "    apply_pow<double>(" << F << ", " << s.pf_mode << ", " << s.pf_k << ", a.pow_f, num, den);\n";
     o << "    return num * fast_rcp(den);\n  }\n};\n}  // namespace qmcd\n";
   }
+  o << "extern \"C\" __global__ __launch_bounds__(QMCD_BLOCK) void qmc_jit_batch(const qmcd::EvalArgs* __restrict__ "
+       "items, const uint32_t* __restrict__ order, const uint32_t* __restrict__ prefix, uint32_t nitems, "
+       "uint32_t* __restrict__ counter) {\n  qmcd::batch_tiles<"
+    << qmck::S_REAL << ">(items, order, prefix, nitems, counter, [&](const qmcd::EvalArgs& a, const qmcd::Sched& sc) {\n"
+    << "    qmcd::eval_real_sched<" << d << ", " << tk << ", false, " << qmck::S_REAL << ", true, qmcd::JitReal, "
+    << (s.vr ? "qmcd::VRM_ON" : "qmcd::VRM_OFF") << ">(a, qmcd::JitReal(), sc);\n  });\n}\n";
   for (int w = 0; w < 2; ++w) {
     o << "extern \"C\" __global__ __launch_bounds__(QMCD_BLOCK) void qmc_jit_eval" << (w ? "64" : "32")
       << "(qmcd::EvalArgs a) {\n  qmcd::eval_real_body<" << d << ", " << tk << ", " << (w ? "false" : "true")
@@ -591,6 +598,8 @@ int get(int device, const Spec& s, Kernel* out) {
       out->f32 = it->second->f32;
       out->f64 = it->second->f64;
       out->occ_blocks = it->second->occ_blocks;
+      out->batch = it->second->batch;
+      out->occ_batch = it->second->occ_batch;
       return 0;
     }
   }
@@ -600,6 +609,7 @@ int get(int device, const Spec& s, Kernel* out) {
   hipError_t e = hipModuleLoadData(&m->mod, code.data());
   if (e == hipSuccess) e = hipModuleGetFunction(&m->f32, m->mod, "qmc_jit_eval32");
   if (e == hipSuccess) e = hipModuleGetFunction(&m->f64, m->mod, "qmc_jit_eval64");
+  if (e == hipSuccess && !s.cplx) e = hipModuleGetFunction(&m->batch, m->mod, "qmc_jit_batch");
   if (e != hipSuccess) {
     g_jit_err = std::string("module load failed: ") + hipGetErrorString(e);
     return -2;
@@ -607,13 +617,17 @@ int get(int device, const Spec& s, Kernel* out) {
   int occ = 0;
   if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&occ, m->f32, QMCD_BLOCK, 0) != hipSuccess) occ = 0;
   m->occ_blocks = occ;
+  if (m->batch && hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&occ, m->batch, QMCD_BLOCK, 0) == hipSuccess)
+    m->occ_batch = occ;
   {
     std::lock_guard<std::mutex> g(g_mu);
     g_cache[key] = m;
   }
   out->f32 = m->f32;
   out->f64 = m->f64;
-  out->occ_blocks = occ;
+  out->occ_blocks = m->occ_blocks;
+  out->batch = m->batch;
+  out->occ_batch = m->occ_batch;
   return 0;
 }
 
@@ -622,6 +636,13 @@ hipError_t launch(const Kernel& k, bool idx32, const qmcd::EvalArgs& a, dim3 gri
   void* params[] = {&copy};
   return hipModuleLaunchKernel(idx32 ? k.f32 : k.f64, grid.x, grid.y, grid.z, QMCD_BLOCK, 1, 1, 0, st, params,
                                nullptr);
+}
+
+hipError_t launch_batch(const Kernel& k, const qmcd::EvalArgs* items, const uint32_t* order, const uint32_t* prefix,
+                        uint32_t nitems, uint32_t* counter, uint32_t blocks, hipStream_t st) {
+  if (!k.batch) return hipErrorInvalidValue;
+  void* params[] = {(void*)&items, (void*)&order, (void*)&prefix, (void*)&nitems, (void*)&counter};
+  return hipModuleLaunchKernel(k.batch, blocks, 1, 1, QMCD_BLOCK, 1, 1, 0, st, params, nullptr);
 }
 
 }  // namespace qmcj

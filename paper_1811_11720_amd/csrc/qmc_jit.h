@@ -27,6 +27,10 @@ struct Spec {
 struct Kernel {
   hipFunction_t f32 = nullptr, f64 = nullptr;  // 32-bit / 64-bit index stepping
   int occ_blocks = 0;                           // resident blocks per CU
+  // real integrands: persistent batch kernel over a tile list (the
+  // arguments of the table-driven batch kernels), S_REAL shifts per group
+  hipFunction_t batch = nullptr;
+  int occ_batch = 0;
 };
 
 std::string generate(const Spec& s);
@@ -35,6 +39,8 @@ int get(int device, const Spec& s, Kernel* out);
 // Generate and compile only (no device needed); code size in bytes.
 int compile_only(const Spec& s, size_t* code_bytes);
 hipError_t launch(const Kernel& k, bool idx32, const qmcd::EvalArgs& a, dim3 grid, hipStream_t st);
+hipError_t launch_batch(const Kernel& k, const qmcd::EvalArgs* items, const uint32_t* order, const uint32_t* prefix,
+                        uint32_t nitems, uint32_t* counter, uint32_t blocks, hipStream_t st);
 const char* last_error();
 
 }  // namespace qmcj

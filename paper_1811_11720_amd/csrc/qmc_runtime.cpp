@@ -236,6 +236,30 @@ uint32_t plan_blocks(const qmc_context* c, int occ, uint32_t groups, uint64_t np
 }
 
 // One lattice (n, z), m shifts from `shift_tab`, points [k0, k1): per-shift sums.
+// The integrand's specialised kernels for transform `tsel` (compiled on first
+// use, shared through the module cache by integrands of the same structure).
+// Returns 0, or nonzero when compilation failed (remembered: never retried).
+int specialised_kernel(qmc_context* c, qmc_integrand* f, int tsel, qmcj::Kernel* out) {
+  const bool cplx = (f->flags & QMC_DEFORM) != 0;
+  const int jkey = tsel * 2 + (f->has_vr ? 1 : 0);
+  if (f->genz || f->jit_failed.count(jkey)) return -1;
+  auto it = f->jit.find(jkey);
+  if (it != f->jit.end()) {
+    *out = it->second;
+    return 0;
+  }
+  qmcj::Spec sp{f->dim, f->n_u, f->n_f, f->expo.data(), f->pu_mode, f->pu_k, f->pf_mode, f->pf_k, tsel,
+                cplx ? qmck::S_COMPLEX_JIT : c->jit_S, f->has_vr ? 1 : 0, cplx ? 1 : 0};
+  if (!cplx) combined_root(f->dim, f->n_u, f->n_f, f->coef.data(), f->expo.data(), f->pow_u, f->pow_f, sp.ru, sp.rf);
+  if (qmcj::get(c->device, sp, out) != 0) {
+    f->jit_failed[jkey] = 1;
+    if (std::getenv("QMC_JIT_VERBOSE")) std::fprintf(stderr, "qmc: specialisation failed: %s\n", qmcj::last_error());
+    return -1;
+  }
+  f->jit[jkey] = *out;
+  return 0;
+}
+
 int run_lattice(qmc_context* c, qmc_integrand* f, uint64_t n, const uint64_t* z, uint32_t m,
                 const double* shift_tab, const qmc_transform& t, uint64_t k0, uint64_t k1, LatticeRun& out) {
   const bool cplx = (f->flags & QMC_DEFORM) != 0;
@@ -254,25 +278,9 @@ int run_lattice(qmc_context* c, qmc_integrand* f, uint64_t n, const uint64_t* z,
   qmcj::Kernel jk;
   bool use_jit = false;
   int S = cplx ? qmck::S_COMPLEX : qmck::S_REAL;
-  const int jkey = tsel * 2 + (f->has_vr ? 1 : 0);
-  if (!f->genz && c->jit && npts * (uint64_t)m >= c->jit_min_evals && !f->jit_failed.count(jkey)) {
-    auto it = f->jit.find(jkey);
-    if (it == f->jit.end()) {
-      qmcj::Spec sp{dim, f->n_u, f->n_f, f->expo.data(), f->pu_mode, f->pu_k, f->pf_mode, f->pf_k, tsel,
-                    cplx ? qmck::S_COMPLEX_JIT : c->jit_S, f->has_vr ? 1 : 0, cplx ? 1 : 0};
-      if (!cplx) combined_root(dim, f->n_u, f->n_f, f->coef.data(), f->expo.data(), f->pow_u, f->pow_f, sp.ru, sp.rf);
-      if (qmcj::get(c->device, sp, &jk) == 0) {
-        f->jit[jkey] = jk;
-        use_jit = true;
-      } else {
-        f->jit_failed[jkey] = 1;
-        if (std::getenv("QMC_JIT_VERBOSE")) std::fprintf(stderr, "qmc: specialisation failed: %s\n", qmcj::last_error());
-      }
-    } else {
-      jk = it->second;
-      use_jit = true;
-    }
-    if (use_jit) S = cplx ? qmck::S_COMPLEX_JIT : c->jit_S;
+  if (!f->genz && c->jit && npts * (uint64_t)m >= c->jit_min_evals && specialised_kernel(c, f, tsel, &jk) == 0) {
+    use_jit = true;
+    S = cplx ? qmck::S_COMPLEX_JIT : c->jit_S;
   }
   const uint32_t groups = (m + S - 1) / S;
   const int occ = use_jit     ? jk.occ_blocks
@@ -664,7 +672,8 @@ int validate_desc(const qmc_integrand_desc* d) {
   if ((d->flags & QMC_DEFORM) && d->dim > qmck::MAX_DIM_COMPLEX)
     return fail(QMC_EINVAL, "deformed integrands support at most %u variables", qmck::MAX_DIM_COMPLEX);
   if ((d->flags & QMC_DEFORM) && d->n_f == 0) return fail(QMC_EINVAL, "deformation needs a polynomial F");
-  if (d->flags & ~(uint32_t)(QMC_DEFORM | QMC_EVAL_FP32)) return fail(QMC_EINVAL, "unknown flags 0x%x", d->flags);
+  if (d->flags & ~(uint32_t)(QMC_DEFORM | QMC_EVAL_FP32 | QMC_SPECIALISE))
+    return fail(QMC_EINVAL, "unknown flags 0x%x", d->flags);
   return QMC_OK;
 }
 

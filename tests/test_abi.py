@@ -37,7 +37,8 @@ def test_header_constants_match_binding():
     src = open(os.path.join(ROOT, "include", "qmc.h")).read()
     for name, val in [("QMC_EINVAL", Q.QMC_EINVAL), ("QMC_ENOMEM", Q.QMC_ENOMEM), ("QMC_EDEVICE", Q.QMC_EDEVICE),
                       ("QMC_EUNSUPPORTED", Q.QMC_EUNSUPPORTED), ("QMC_DEFORM", Q.QMC_DEFORM),
-                      ("QMC_EVAL_FP32", Q.QMC_EVAL_FP32), ("QMC_T_BAKER", Q.T_BAKER), ("QMC_T_SIDI", Q.T_SIDI),
+                      ("QMC_EVAL_FP32", Q.QMC_EVAL_FP32), ("QMC_SPECIALISE", Q.QMC_SPECIALISE),
+                      ("QMC_T_BAKER", Q.T_BAKER), ("QMC_T_SIDI", Q.T_SIDI),
                       ("QMC_NONFINITE", Q.QMC_NONFINITE), ("QMC_ERRMODE_LARGEST", Q.ERRMODE_LARGEST)]:
         m = re.search(rf"\b{name}\s*=\s*(-?\d+)", src)
         assert m and int(m.group(1)) == val, name

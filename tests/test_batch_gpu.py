@@ -227,3 +227,36 @@ def test_autotune_keeps_parity_and_writes_its_cache(tmp_path):
         f.close()
     c.close()
     c2.close()
+
+
+def test_specialised_batch_matches_oracle_alone_and_in_a_mix():
+    """QMC_SPECIALISE: real fp64 jobs run in the kernel generated for their
+    integrand's structure.  Per-shift sums match the oracle; a job gives the
+    same sums alone as in a mix with table-driven jobs; a repeated batch
+    (a replayed graph) gives the same sums again."""
+    c = make_ctx("specialised")
+    d1 = W.random_real_small(seed=11, dim=4, n_u=3, n_f=5)
+    d2 = W.random_real_small(seed=12, dim=6, n_u=4, n_f=7, pow_u=-1.5, pow_f=-2.5)
+    d3 = W.plain_product(seed=1)
+    for d in (d1, d2, d3):
+        d.specialise = True
+    jobs = [W.Job(d1, 1009, cbc.fast_cbc(1009, 4), 8, seed=901, transform=KOR3),
+            W.Job(d1, 4099, cbc.fast_cbc(4099, 4), 11, seed=902, transform=(W.T_BAKER, 0, 0)),
+            W.Job(d2, 10007, cbc.fast_cbc(10007, 6), 5, seed=903, transform=KOR3),
+            W.Job(d3, 10007, W.z_for(10007, 3), 10, seed=904, transform=KOR3)]
+    table = _mix(6, 9)
+    keep = []
+    mixed = _run(c, jobs + table, keep=keep)
+    for j, r in zip(jobs + table, mixed):
+        sh = oracle.shifts(j.seed, j.m, j.desc.dim)
+        o = oracle.shift_sums(j.desc, j.n, j.z, j.m, sh, j.transform, threads=THREADS)
+        _check_sums(r["sums_re"], o, r["sums_im"] if j.desc.deform else None, label=f"d{j.desc.dim}")
+    for k in range(len(jobs)):
+        alone = _run(c, [jobs[k]], keep=keep)[0]
+        assert np.array_equal(alone["sums_re"], mixed[k]["sums_re"])
+    again = _run(c, jobs + table, keep=keep)
+    for a, b in zip(mixed, again):
+        assert np.array_equal(a["sums_re"], b["sums_re"]) and np.array_equal(a["sums_im"], b["sums_im"])
+    for f in keep:
+        f.close()
+    c.close()
