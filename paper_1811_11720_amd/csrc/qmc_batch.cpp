@@ -50,7 +50,7 @@ int run_batch(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_secon
     qmcj::Kernel jk;
   };
   std::vector<Plan> plan(J);
-  std::vector<hipFunction_t> jit_fns;  // distinct specialised kernels of this round
+  std::vector<hipFunction_t> jit_fns;  // distinct specialised kernels in this call
   size_t n_part = 0, n_sh = 0, n_rows = 0;
   for (uint32_t i = 0; i < J; ++i) {
     BatchJob& b = *jobs[i];
