@@ -143,6 +143,19 @@ def test_power_classes(ctx, pu, pf):
     _check_sums(g["sums_re"], o, label=f"p{pu},{pf}")
 
 
+def test_half_integer_powers_of_signed_polynomials(ctx):
+    """U = 3 - x0 x1 + x2^2 and F = 2 + x0 - x1 x2 are positive on the cube but
+    have negative coefficients, so the specialised kernel keeps the separate
+    powers (the single-root form needs provable bounds); both paths match the
+    oracle."""
+    desc = W.monomial([3.0, -1.0, 1.0, 2.0, 1.0, -1.0],
+                      [[0, 0, 0], [1, 1, 0], [0, 0, 2], [0, 0, 0], [1, 0, 0], [0, 1, 1]], 3, n_u=3,
+                      pow_u=-1.5, pow_f=-2.5, prefactor=0.7)
+    n = 4099
+    g, o, _ = _run_both(ctx, desc, n, cbc.fast_cbc(n, 3), 6, 77, KOR3)
+    _check_sums(g["sums_re"], o, label="signed")
+
+
 def test_maximum_shift_count(ctx):
     """m = QMC_MAX_SHIFTS (1024): every shift group, including the ragged last one."""
     desc = W.random_real_small(seed=12, dim=5, n_u=3, n_f=4)
