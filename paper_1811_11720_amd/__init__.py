@@ -168,6 +168,14 @@ def _up(a):
     return a.ctypes.data_as(C.POINTER(C.c_uint64))
 
 
+def _result_dicts(res):
+    """Result array -> list of dicts, column by column (one pass per field)."""
+    view = np.ctypeslib.as_array(res)
+    names = [k for k, _ in Result._fields_]
+    cols = [view[k].tolist() for k in names]
+    return [dict(zip(names, vals)) for vals in zip(*cols)]
+
+
 def _tr(t):
     if isinstance(t, Transform):
         return t
@@ -380,21 +388,27 @@ class Context:
         arr = (Request * len(reqs))()
         keep = []
         total = 0
+        zcache, tcache = {}, {}  # requests often share one generating vector / transform object
         for i, r in enumerate(reqs):
             z = r.get("z")
             zp = None
             if z is not None:
-                zz = np.ascontiguousarray(z, dtype=np.uint64)
-                keep.append(zz)
-                zp = _up(zz)
-            arr[i] = Request(r["f"].handle, r["n"], zp, r["m"], r.get("errormode", ERRMODE_LARGEST), r["seed"],
-                             _tr(r.get("transform", (T_KOROBOV, 3, 3))), r.get("rel_tol", 0.0),
-                             r.get("abs_tol", 0.0), r.get("max_evals", 0))
+                zp = zcache.get(id(z))
+                if zp is None:
+                    zz = np.ascontiguousarray(z, dtype=np.uint64)
+                    keep.append(zz)
+                    zp = zcache[id(z)] = _up(zz)
+            t = r.get("transform", (T_KOROBOV, 3, 3))
+            tt = tcache.get(id(t))
+            if tt is None:
+                tt = tcache[id(t)] = _tr(t)
+            arr[i] = Request(r["f"].handle, r["n"], zp, r["m"], r.get("errormode", ERRMODE_LARGEST), r["seed"], tt,
+                             r.get("rel_tol", 0.0), r.get("abs_tol", 0.0), r.get("max_evals", 0))
             total += r["m"] * (2 if r["f"].complex else 1)
         res = (Result * len(reqs))()
         out = np.zeros(max(total, 1))
         _check(lib().qmc_integrate_batch(self.handle, arr, len(reqs), res, _dp(out)))
-        outs = [x.as_dict() for x in res]
+        outs = _result_dicts(res)
         if sums:
             off = 0
             for r, d in zip(reqs, outs):
