@@ -319,7 +319,9 @@ int qmc_integrate_batch(qmc_context* ctx, const qmc_request* reqs, uint32_t coun
  * environment variable QMC_TUNE_CACHE, read at context creation).  The
  * points-per-decode choice never changes results; the tile size fixes the
  * summation order, so tune before integrating, not between calls whose sums
- * must match bitwise.  *configs_tried (optional) counts timed schedules.
+ * must match bitwise.  Requests whose real fp64 jobs run in a specialised
+ * kernel (QMC_SPECIALISE) are left out.  *configs_tried (optional) counts
+ * timed schedules.
  */
 int qmc_autotune_batch(qmc_context* ctx, const qmc_request* reqs, uint32_t count, uint32_t* configs_tried);
 

@@ -444,6 +444,8 @@ int autotune(qmc_context* c, const qmc_request* reqs, uint32_t count, uint32_t* 
     qmck::BatchVariant v;
     int rc = variant_of(reqs[i], v);
     if (rc) return rc;
+    // jobs that run in a specialised kernel would time that kernel, not the variant's
+    if (!v.cplx && !v.fp32 && (reqs[i].f->flags & QMC_SPECIALISE) && c->jit) continue;
     by_var[v.index()].push_back(i);
     vars[v.index()] = v;
   }
