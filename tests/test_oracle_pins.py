@@ -451,6 +451,90 @@ def test_deformation_evaluates_u_on_the_contour():
     assert abs(val - exact) < 1e-10 * abs(exact)
 
 
+def _pivot_row_exchange_fraction(a, b, lam, points=2000, seed=1):
+    """Fraction of points x in the cube at which Gaussian elimination with
+    partial pivoting of dz/dx for F = prod_j (a_j + b_j x_j) exchanges rows.
+    The Jacobian is formed here from the closed-form derivatives of the
+    product, independently of the oracle."""
+    rng = np.random.default_rng(seed)
+    d = len(a)
+    hits = 0
+    for _ in range(points):
+        x = rng.random(d)
+        lin = a + b * x
+        F = np.prod(lin)
+        g = b * F / lin
+        H = np.outer(b, b) * F / np.outer(lin, lin)
+        np.fill_diagonal(H, 0.0)
+        A = np.eye(d) - 1j * lam * (np.diag((1 - 2 * x) * g) + (x * (1 - x))[:, None] * H)
+        swapped = False
+        for c in range(d):
+            p = c + int(np.argmax(np.abs(A[c:, c])))
+            if p != c:
+                swapped = True
+                A[[c, p]] = A[[p, c]]
+            A[c + 1:] -= np.outer(A[c + 1:, c] / A[c, c], A[c])
+        hits += swapped
+    return hits / points
+
+
+@pytest.mark.parametrize("b,p", [((5.0, 4.5, 5.5), -1.0), ((5.0, 4.5, 5.5), -2.0),
+                                 ((2.0, 1.5, 2.5, 1.8), -2.0)])
+def test_deformation_cauchy_invariance_three_and_four_dimensions(b, p):
+    """F = prod_j (1 + b_j x_j) has no root in the half-plane Re z >= 0 that
+    the contour sweeps, so deforming it (lambda = 0.5) leaves the integral at
+    the real closed form and the imaginary part at zero. With b_j of a few
+    units the off-diagonal terms x_j(1-x_j) d2F/dx_j dx_l outgrow the unit
+    diagonal, so the determinant's elimination exchanges rows and every
+    Hessian entry carries the factors of the remaining variables."""
+    a = np.ones(len(b))
+    b = np.array(b)
+    assert _pivot_row_exchange_fraction(a, b, 0.5) > 0.2
+    desc = W.product_of_linear(a, b, p)
+    desc.deform, desc.lam = True, 0.5
+    if p == -1.0:
+        exact = float(np.prod(np.log1p(b / a) / b))
+    else:
+        exact = float(np.prod(((a + b) ** (p + 1) - a ** (p + 1)) / (b * (p + 1))))
+    val, er, ei, _ = _integrate(desc, cbc.next_prime(300000), m=8)
+    rel = 1e-9 if len(b) == 3 else 1e-7
+    assert abs(val.real - exact) < max(6 * er, 1e-14) and abs(val.real - exact) < rel * exact
+    assert abs(val.imag) < max(6 * ei, 1e-14) and abs(val.imag) < rel * exact
+
+
+@pytest.mark.parametrize("a,b,p", [(1.0, (0.5, 0.7, 0.6), -1.5), (1.2, (0.8, 0.6, 0.9), -2.5)])
+def test_deformation_three_dimensional_linear_root_crossing(a, b, p):
+    """F = a - sum_j b_j x_j crosses zero inside the cube. Integrating
+    (a - sum b_j x_j - i0)^p one variable at a time gives the third finite
+    difference of the antiderivative:
+    sum over subsets S of (-1)^|S| (a - b_S - i0)^(p+3) / (b_1 b_2 b_3 (p+1)(p+2)(p+3))."""
+    desc = W.monomial([1.0, a, -b[0], -b[1], -b[2]],
+                      [[0, 0, 0], [0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], 3, n_u=1, pow_f=p,
+                      deform=True, lam=0.5)
+    tot = 0
+    for S in range(8):
+        bs = sum(b[j] for j in range(3) if S >> j & 1)
+        tot += (-1) ** bin(S).count("1") * _G(mp.mpf(a) - mp.mpf(bs), p + 3)
+    exact = complex(tot / (b[0] * b[1] * b[2] * (p + 1) * (p + 2) * (p + 3)))
+    val, er, ei, s = _integrate(desc, cbc.next_prime(300000), m=8)
+    assert abs(val - exact) < 1e-6 * abs(exact)
+    assert abs(val.real - exact.real) < 6 * er and abs(val.imag - exact.imag) < 6 * ei
+    assert int(s.sign_points.sum()) == 0
+
+
+@pytest.mark.parametrize("a,b", [(1.0, 2.5), (1.0, 4.0)])
+def test_deformation_trilinear_root_crossing(a, b):
+    """F = a - b x y z with b > a: expanding 1/(a - b x y z) in powers of
+    x y z gives int 1/(a - b xyz - i0) = Li3(b/a + i0) / b. Every
+    off-diagonal Hessian entry is -b times the third variable."""
+    desc = W.monomial([1.0, a, -b], [[0, 0, 0], [0, 0, 0], [1, 1, 1]], 3, n_u=1, pow_f=-1.0,
+                      deform=True, lam=0.5)
+    exact = complex(mp.polylog(3, mp.mpc(b / a, 1e-60)) / b)
+    val, er, ei, s = _integrate(desc, cbc.next_prime(300000), m=8)
+    assert abs(val - exact) < 1e-13 * abs(exact)
+    assert int(s.sign_points.sum()) == 0
+
+
 # ------------------------------------------------------------------ histogram
 
 
