@@ -190,8 +190,13 @@ int qmc_set_vr(qmc_integrand* f, const double* params);
  * (n, z) shifted by the first shift of SplitMix64(seed), with no transform
  * and no VR map, hist[j*bins + b] = sum of |f(x)| over points with
  * floor(x_j * bins) = b (|f| = modulus for complex integrands; non-finite
- * values count 0).  Each |f| is rounded to max|f| * 2^-40 and summed as an
- * integer, so the result is bitwise reproducible.  hist: host [dim * bins].
+ * values count 0).  Each |f| is rounded to an integer multiple of 2^-s,
+ * with s the largest integer such that n * max|f| * 2^s <= 2^127, and the
+ * multiples are summed exactly as 128-bit integers: the result is bitwise
+ * reproducible, no bin can overflow, every |f| >= n * max|f| * 2^-74 keeps
+ * full double precision, and each bin is that exact sum rounded once to a
+ * double.  hist: host [dim * bins].  2 <= bins <= 65536; device scratch 16 * dim *
+ * bins bytes.
  */
 int qmc_histogram(qmc_context* ctx, const qmc_integrand* f, uint64_t n, const uint64_t* z, uint64_t seed,
                   uint32_t bins, double* hist);
@@ -335,8 +340,15 @@ int qmc_autotune_batch(qmc_context* ctx, const qmc_request* reqs, uint32_t count
  * 8 GiB), and runs rounds of the batch kernels over every admitted request's
  * current lattice; each request applies its own goal and growth rule
  * (Sec. 3.3.1) between rounds, so requests arriving while others run join the
- * next round.  Results equal qmc_integrate_batch's for the same request.
- * QMC_ENOMEM if the ticket alone exceeds the budget.  Integrands of a
+ * next round.  A request's memory is reserved for the largest lattice it may
+ * reach and the smallest tiles any schedule may give it, and returns to the
+ * budget when that request finishes.  With a caller-owned workspace the
+ * budget is also capped by the workspace size.  Results equal
+ * qmc_integrate_batch's for the same request, except that a served request
+ * never adds shifts at the largest lattice (the Monte Carlo fallback of
+ * qmc_integrate_batch): it stops there with QMC_MAXEVAL_HIT, so its memory
+ * stays within its reservation.  QMC_ENOMEM if the ticket alone exceeds the
+ * budget.  Integrands of a
  * pending ticket cannot be destroyed (QMC_EBUSY).  result.queue_seconds is
  * submit-to-admission, result.wall_seconds submit-to-completion.
  */

@@ -35,6 +35,24 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 }  // namespace
 
+uint64_t batch_tile_points(const qmc_context* c, uint64_t tuned, bool cplx, uint64_t n) {
+  const uint64_t tmin = tuned ? tuned : (cplx ? c->batch_tile_complex : c->batch_tile_real);
+  const uint64_t tp = std::max<uint64_t>(tmin, (n + c->batch_max_ktiles - 1) / c->batch_max_ktiles);
+  return (tp + QMCD_BLOCK - 1) / QMCD_BLOCK * QMCD_BLOCK;
+}
+
+uint64_t batch_ktiles_bound(const qmc_context* c, uint64_t n) {
+  // every tile holds a whole number (>= 1) of blocks and at least n / batch_max_ktiles points
+  const uint64_t tp = batch_tile_points(c, QMCD_BLOCK, false, n);
+  return (n + tp - 1) / tp;
+}
+
+size_t batch_job_bytes(size_t rows, uint64_t ktiles, uint32_t m, uint32_t dim) {
+  // arena entries of one job (run_batch's layout) plus its share of the alignment padding
+  return sizeof(qmcd::EvalArgs) + 4 + 8 + rows * (sizeof(qmck::RowRef) + 8 * ktiles + 8) + (size_t)m * dim * 8 + 8 +
+         256;
+}
+
 int run_batch(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_seconds) {
   const uint32_t J = (uint32_t)jobs.size();
   if (kernel_seconds) *kernel_seconds = 0.0;
@@ -73,10 +91,7 @@ int run_batch(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_secon
       if (it == jit_fns.end()) jit_fns.push_back(p.jk.batch);
     }
     const uint32_t S = cplx ? qmck::S_COMPLEX : qmck::S_REAL;
-    const uint64_t tuned = p.use_jit ? 0 : c->batch_tile[p.variant];
-    const uint64_t tmin = tuned ? tuned : (cplx ? c->batch_tile_complex : c->batch_tile_real);
-    uint64_t tp = std::max<uint64_t>(tmin, (b.n + c->batch_max_ktiles - 1) / c->batch_max_ktiles);
-    tp = (tp + QMCD_BLOCK - 1) / QMCD_BLOCK * QMCD_BLOCK;
+    const uint64_t tp = batch_tile_points(c, p.use_jit ? 0 : c->batch_tile[p.variant], cplx, b.n);
     p.tile_points = tp;
     p.ktiles = (uint32_t)((b.n + tp - 1) / tp);
     p.groups = (b.m + S - 1) / S;
@@ -216,7 +231,6 @@ int run_batch(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_secon
     return QMC_OK;
   };
 
-  HIPCHK(hipEventRecord(c->ev0, c->stream));
   if (c->batch_graph) {
     if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     hipGraph_t g = nullptr;
@@ -232,7 +246,9 @@ int run_batch(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_secon
     hipError_t ei = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (ei != hipSuccess) return fail(QMC_EDEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(ei));
-    hipError_t el = hipGraphLaunch(ge, c->stream);
+    // the device interval starts here, after the host has built the graph
+    hipError_t er = hipEventRecord(c->ev0, c->stream);
+    hipError_t el = er != hipSuccess ? er : hipGraphLaunch(ge, c->stream);
     if (el != hipSuccess) {
       (void)hipGraphExecDestroy(ge);
       return fail(QMC_EDEVICE, "hipGraphLaunch failed: %s", hipGetErrorString(el));
@@ -242,6 +258,7 @@ int run_batch(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_secon
     HIPCHK(hipStreamSynchronize(c->stream));
     (void)hipGraphExecDestroy(ge);
   } else {
+    HIPCHK(hipEventRecord(c->ev0, c->stream));
     rc = enqueue(c->stream);
     if (rc) return rc;
     HIPCHK(hipEventRecord(c->ev1, c->stream));

@@ -1292,12 +1292,15 @@ __device__ __forceinline__ void batch_tiles(const EvalArgs* __restrict__ items, 
 
 // |f| at the raw points x = {k z/n + Delta} of one shifted lattice (no
 // periodizing transform, no VR map).  PASS 0: per-block max of |f| into
-// a.partial[block].  PASS 1: hist[j][floor(x_j * bins)] += rint(|f| * scale)
-// as 64-bit integers (exact, order-independent sums).
+// a.partial[block].  PASS 1: hist[j][floor(x_j * bins)] += rint(|f| 2^s) as
+// 128-bit fixed-point integers (two 64-bit words, the carry of the low word
+// added to the high word), so every bin is an exact, order-independent sum.
+// The host picks s so that n max|f| 2^s <= 2^127: no bin can overflow, and
+// every |f| >= n max|f| 2^-74 keeps its full 53-bit precision.
 struct HistArgs {
-  unsigned long long* hist;  // [dim][bins]
+  unsigned long long* hist;  // [dim][bins][2]: low word, high word
   uint32_t bins;
-  double scale;              // 2^40 / max|f|
+  double scale, scale2;      // 2^s as two factors (s may lie outside the range of one double)
 };
 
 template <int DMAX, bool CPLX, int PASS>
@@ -1328,14 +1331,27 @@ __device__ __forceinline__ void hist_body(const EvalArgs& a, const HistArgs& h) 
     if (PASS == 0) {
       mx = v > mx ? v : mx;
     } else {
-      unsigned long long c = (unsigned long long)__builtin_rint(v * h.scale);
-      if (c) {
+      // v 2^s < 2^127 as an integer hi 2^64 + lo; from 2^63 up every double is an integer
+      const double vs = (v * h.scale) * h.scale2;
+      unsigned long long lo, hi;
+      if (vs < 0x1p64) {
+        hi = 0ull;
+        lo = (unsigned long long)__builtin_rint(vs);
+      } else {
+        const double t = __builtin_floor(vs * 0x1p-64);
+        hi = (unsigned long long)t;
+        lo = (unsigned long long)(vs - t * 0x1p64);  // exact: fewer significant bits than vs
+      }
+      if (lo | hi) {
 #pragma unroll
         for (int j = 0; j < DMAX; ++j) {
           if (j < (int)dim) {
             uint32_t b = (uint32_t)(x[j] * (double)h.bins);
             b = b < h.bins ? b : h.bins - 1;
-            atomicAdd(h.hist + (size_t)j * h.bins + b, c);
+            unsigned long long* w = h.hist + 2 * ((size_t)j * h.bins + b);
+            const unsigned long long old = atomicAdd(w, lo);
+            const unsigned long long up = hi + (old + lo < old ? 1ull : 0ull);
+            if (up) atomicAdd(w + 1, up);
           }
         }
       }

@@ -141,6 +141,14 @@ struct BatchJob {
   std::vector<double> sums;  // out: rows (m or 2m)
   uint64_t sign_points = 0;  // out
 };
+// Points per tile of a batch job of n points: the variant's tuned minimum
+// (0 = the default for real or complex jobs), at least n / batch_max_ktiles,
+// rounded up to whole blocks.  A job's tiling depends only on this.
+uint64_t batch_tile_points(const qmc_context* c, uint64_t tuned, bool cplx, uint64_t n);
+// Most tiles any schedule can give a job of n points.
+uint64_t batch_ktiles_bound(const qmc_context* c, uint64_t n);
+// Upper bound of the batch scratch one job of `rows` rows and `ktiles` tiles takes.
+size_t batch_job_bytes(size_t rows, uint64_t ktiles, uint32_t m, uint32_t dim);
 // Evaluate all jobs with the persistent batch kernels (one round).
 int run_batch(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_seconds);
 // Requests through rounds of run_batch (growth loop per request).

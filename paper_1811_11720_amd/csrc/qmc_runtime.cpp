@@ -359,7 +359,8 @@ int run_lattice(qmc_context* c, qmc_integrand* f, uint64_t n, const uint64_t* z,
 }
 
 // Histograms of |f| over the lattice (n, z) shifted by the first shift of
-// SplitMix64(seed), raw points (Sec. 2.4): two passes (max, then integer sums).
+// SplitMix64(seed), raw points (Sec. 2.4): two passes (max, then exact
+// 128-bit fixed-point sums at the scale 2^s, n max|f| 2^s <= 2^127).
 int run_histogram(qmc_context* c, const qmc_integrand* f, uint64_t n, const uint64_t* z, uint64_t seed,
                   uint32_t bins, std::vector<double>& hist) {
   const bool cplx = (f->flags & QMC_DEFORM) != 0;
@@ -371,7 +372,7 @@ int run_histogram(qmc_context* c, const qmc_integrand* f, uint64_t n, const uint
   make_shifts(seed, 1, dim, shift.data());
   size_t off_sh = 0, sz_sh = dim * sizeof(double);
   size_t off_part = 256, sz_part = (size_t)nb * sizeof(double);
-  size_t off_h = (off_part + sz_part + 255) & ~(size_t)255, sz_h = (size_t)dim * bins * 8;
+  size_t off_h = (off_part + sz_part + 255) & ~(size_t)255, sz_h = (size_t)dim * bins * 16;
   char* ws = nullptr;
   int rc = scratch(c, off_h + sz_h, &ws);
   if (rc) return rc;
@@ -406,7 +407,7 @@ int run_histogram(qmc_context* c, const qmc_integrand* f, uint64_t n, const uint
   qmcd::HistArgs h;
   h.hist = (unsigned long long*)(ws + off_h);
   h.bins = bins;
-  h.scale = 0.0;
+  h.scale = h.scale2 = 0.0;
   const int dclass = qmck::dim_class(dim, cplx);
   HIPCHK(qmck::launch_hist(a, h, dclass, cplx, 0, dim3(nb), c->stream));
   HIPCHK(hipMemcpyAsync(c->h_stage, ws + off_part, sz_part, hipMemcpyDeviceToHost, c->stream));
@@ -415,14 +416,23 @@ int run_histogram(qmc_context* c, const qmc_integrand* f, uint64_t n, const uint
   for (uint32_t b = 0; b < nb; ++b) mx = std::max(mx, c->h_stage[b]);
   hist.assign((size_t)dim * bins, 0.0);
   if (!(mx > 0.0)) return QMC_OK;
-  h.scale = std::ldexp(1.0, 40) / mx;
-  HIPCHK(qmck::launch_fill_u64(h.hist, dim * bins, 0ull, c->stream));
+  // n <= 2^en and max|f| < 2^em, so each rounded term is below 2^(127 - en)
+  // and a bin, a sum of at most n of them, stays below 2^127
+  int en = 0;
+  while ((1ull << en) < n) ++en;
+  const int em = std::ilogb(mx) + 1;
+  const int s = 127 - en - em;
+  h.scale = std::ldexp(1.0, s / 2);
+  h.scale2 = std::ldexp(1.0, s - s / 2);
+  HIPCHK(qmck::launch_fill_u64(h.hist, 2 * dim * bins, 0ull, c->stream));
   HIPCHK(qmck::launch_hist(a, h, dclass, cplx, 1, dim3(nb), c->stream));
   HIPCHK(hipMemcpyAsync(c->h_stage, ws + off_h, sz_h, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
-  const unsigned long long* cnt = (const unsigned long long*)c->h_stage;
-  const double unit = mx * std::ldexp(1.0, -40);
-  for (size_t i = 0; i < (size_t)dim * bins; ++i) hist[i] = (double)cnt[i] * unit;
+  const unsigned long long* w = (const unsigned long long*)c->h_stage;
+  for (size_t i = 0; i < (size_t)dim * bins; ++i) {
+    const unsigned __int128 v = ((unsigned __int128)w[2 * i + 1] << 64) | w[2 * i];
+    hist[i] = std::ldexp(std::ldexp((double)v, -(s / 2)), -(s - s / 2));  // one rounding of the exact sum
+  }
   return QMC_OK;
 }
 

@@ -7,8 +7,9 @@
 // admitted, unfinished request with the persistent batch kernels
 // (run_batch), then applies each request's own error goal and growth rule
 // (Sec. 3.3.1; at the largest lattice a request stops instead of adding
-// shifts, so its memory stays within what admission reserved).  Requests that finish free their memory at once, so tickets
-// that arrive while others are on the GPU join the next round.  A request's
+// shifts, so its memory stays within what admission reserved).  A request
+// that finishes returns its reserved memory to the budget at once, so
+// tickets that arrive while others are on the GPU join the next round.  A request's
 // results do not depend on what it was batched with (its tiling depends only
 // on its own n and m).  Descriptors stay resident on the device between
 // rounds; a request's state between rounds is (n, z, shifts, round count).
@@ -42,7 +43,8 @@ struct Ticket {
   clk::time_point t_submit, t_admit;
   bool admitted = false, finished = false, cancelled = false;
   int status = QMC_OK;
-  size_t bytes = 0;
+  size_t bytes = 0;  // reservation of all requests (admission test)
+  size_t held = 0;   // part of the reservation still counted in in_use
 };
 
 }  // namespace
@@ -62,23 +64,36 @@ struct qmc_serve_state {
 
 namespace qmch {
 
-size_t serve_budget(const qmc_context* c) { return c->serve_mem_limit; }
+// Device bytes admitted requests may hold: QMC_SERVE_MEM, and no more than a
+// caller-owned workspace (which cannot grow), less the per-round arena
+// headers (launch counters, prefix tables, alignment).
+size_t serve_budget(const qmc_context* c) {
+  const size_t cap = c->own_ws ? c->serve_mem_limit : std::min(c->serve_mem_limit, c->ws_bytes);
+  const size_t reserve = 64 * 1024;
+  return cap > reserve ? cap - reserve : 0;
+}
 
-// device bytes one request needs during a round at its largest lattice
+// Device bytes one request can need in a round at lattice size n, whatever
+// schedule run_batch picks (tuned, cached or default tiles, specialised or
+// table-driven kernel): batch_ktiles_bound bounds its tile count.
 static size_t request_bytes(const qmc_integrand* f, uint64_t n, uint32_t m, const qmc_context* c) {
   const bool cplx = (f->flags & QMC_DEFORM) != 0;
-  uint64_t tmin = cplx ? c->batch_tile_complex : c->batch_tile_real;
-  uint64_t tp = std::max<uint64_t>(tmin, (n + c->batch_max_ktiles - 1) / c->batch_max_ktiles);
-  uint64_t kt = (n + tp - 1) / tp;
-  size_t rows = cplx ? 2 * m : m;
-  return sizeof(qmcd::EvalArgs) + rows * (kt * 8 + sizeof(qmck::RowRef) + 8) + (size_t)m * f->dim * 8 + 64;
+  const uint64_t kt = batch_ktiles_bound(c, n);
+  const size_t rows = cplx ? 2 * (size_t)m : m;
+  return batch_job_bytes(rows, kt, m, f->dim);
+}
+
+static void release(qmc_serve_state* s, Ticket& t, size_t bytes) {
+  bytes = std::min(bytes, t.held);
+  t.held -= bytes;
+  s->in_use -= bytes;
 }
 
 static void finish_ticket(qmc_serve_state* s, Ticket& t, int status) {
   t.finished = true;
   t.status = status;
   for (auto& r : t.reqs) r.f->refs -= 1;
-  s->in_use -= t.bytes;
+  release(s, t, t.held);  // nothing is held by a ticket that was never admitted
   s->cv_done.notify_all();
 }
 
@@ -97,6 +112,7 @@ static void scheduler(qmc_context* c, qmc_serve_state* s) {
       t->admitted = true;
       t->t_admit = clk::now();
       s->in_use += t->bytes;
+      t->held = t->bytes;
       s->active.push_back(t);
       s->queue.pop_front();
     }
@@ -146,6 +162,7 @@ static void scheduler(qmc_context* c, qmc_serve_state* s) {
     }
     for (auto& pr : refs) {
       Req& r = *pr.second;
+      Ticket& tk = *pr.first;
       const bool cplx = (r.f->flags & QMC_DEFORM) != 0;
       const uint32_t m = r.q.m;
       r.r.iterations += 1;
@@ -168,11 +185,13 @@ static void scheduler(qmc_context* c, qmc_serve_state* s) {
       const bool grow = r.q.rel_tol > 0 || r.q.abs_tol > 0;
       if (!grow) {
         r.done = true;
+        release(s, tk, r.bytes);
         continue;
       }
       if (finite && goal_met(r.r, r.q.rel_tol, r.q.abs_tol, r.q.errormode, cplx)) {
         r.r.flags |= QMC_CONVERGED;
         r.done = true;
+        release(s, tk, r.bytes);
         continue;
       }
       // no added shifts here (max_m = m): a request's device memory stays
@@ -181,6 +200,7 @@ static void scheduler(qmc_context* c, qmc_serve_state* s) {
       if (g.kind != GrowthStep::LATTICE) {
         r.r.flags |= QMC_MAXEVAL_HIT;
         r.done = true;
+        release(s, tk, r.bytes);
         continue;
       }
       r.n = g.n;

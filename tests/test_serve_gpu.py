@@ -160,3 +160,92 @@ def test_cancel_and_busy_integrand(ctx):
     with pytest.raises(Q.QmcError) as e:
         ctx.poll(t2, 4)
     assert e.value.code == Q.QMC_ENOTFOUND
+
+
+def _complex_request(ctx, keep, seed, n_target):
+    """One complex request of about n_target points and 32 shifts."""
+    j = [x for x in W.batch_mix(count=40, seed=seed, n_lo=n_target, n_hi=n_target * 1.2, m=32) if x.desc.deform][0]
+    f = ctx.integrand(j.desc)
+    keep.append(f)
+    return dict(f=f, n=j.n, z=j.z, m=j.m, seed=j.seed, transform=j.transform)
+
+
+def test_cancelling_a_queued_ticket_returns_no_memory():
+    """A ticket cancelled before admission never held memory: cancelling it
+    must leave the admitted-bytes count alone (it returns to 0 once the
+    running ticket ends), and later tickets still run."""
+    import paper_1811_11720_amd as Q
+
+    c = _serve_ctx(mem=1_200_000)
+    keep = []
+    a = _complex_request(c, keep, 38, 1.5e6)
+    t_a = c.submit([a])
+    t_b = c.submit([a])  # does not fit beside t_a: stays queued
+    st = c.serve_stats()
+    assert st["queued"] + st["active"] == 2
+    c.cancel(t_b)
+    assert c.wait(t_a, 1, timeout=300) is not None
+    with pytest.raises(Q.QmcError) as e:
+        c.wait(t_b, 1, timeout=300)
+    assert e.value.code == Q.QMC_ECANCELED
+    t_c = c.submit([a])
+    assert c.wait(t_c, 1, timeout=300) is not None
+    st = c.serve_stats()
+    assert st["bytes_in_use"] == 0 and st["queued"] == 0 and st["active"] == 0
+    for f in keep:
+        f.close()
+    c.close()
+
+
+def test_admission_covers_the_smallest_tiles_with_a_caller_workspace(tmp_path):
+    """With a caller-owned workspace the serving budget is the workspace; a
+    tune cache that forces the smallest tiles (256 points) multiplies the
+    partial sums a request needs, and admission must still reserve enough
+    for every round (no QMC_ENOMEM), returning to 0 bytes at the end."""
+    import torch
+
+    import paper_1811_11720_amd as Q
+
+    cache = tmp_path / "tiles.txt"
+    lines = []
+    for cx, dmaxes in ((0, (4, 8, 12, 16)), (1, (4, 6, 8, 10, 12))):
+        for dmax in dmaxes:
+            for tkc in range(3):
+                for f32 in (0, 1):
+                    lines.append(f"gfx950 {dmax} {tkc} {cx} {f32} 0 256")
+    cache.write_text("\n".join(lines) + "\n")
+    old = {k: os.environ.get(k) for k in ("QMC_TUNE_CACHE", "QMC_JIT")}
+    os.environ["QMC_TUNE_CACHE"] = str(cache)
+    os.environ["QMC_JIT"] = "0"
+    ws = torch.empty(3 << 20, dtype=torch.uint8, device="cuda")
+    try:
+        c = Q.Context(0, workspace=ws)
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    c.register_table({n: z for n, z in W.lattice_table().items() if n <= 2_000_000})
+    keep = []
+    pool = W.batch_mix(count=24, seed=39, n_lo=1e5, n_hi=4e5, m=32)
+    reqs = []
+    for j in pool:
+        f = c.integrand(j.desc)
+        keep.append(f)
+        reqs.append(dict(f=f, n=j.n, z=j.z, m=j.m, seed=j.seed, transform=j.transform))
+    tickets = [c.submit(reqs[i:i + 3]) for i in range(0, len(reqs), 3)]
+    served = []
+    for t in tickets:
+        served += c.wait(t, 3, timeout=300)
+    direct = []
+    for i in range(0, len(reqs), 3):  # the workspace holds one ticket's batch at a time
+        direct += c.integrate_batch(reqs[i:i + 3])
+    for a, b in zip(served, direct):
+        assert a["re"] == b["re"] and a["im"] == b["im"]
+    st = c.serve_stats()
+    assert st["bytes_in_use"] == 0 and st["queued"] == 0 and st["active"] == 0
+    for f in keep:
+        f.close()
+    c.close()
+    del ws

@@ -331,3 +331,28 @@ def serving_requests(count: int, seed: int = 5, lo: int = 10, hi: int = 500, poo
 def random_real_small(seed: int, dim: int, n_u: int = 3, n_f: int = 5, pow_u=-2.0, pow_f=-1.5) -> Desc:
     """Small sector-like integrand for parity sweeps."""
     return sector(seed, dim, n_u, n_f, pow_u, pow_f)
+
+
+def high_exponents(seed: int, dim: int, n_u: int, n_f: int, complex_: bool = False, pow_u=-2.0, pow_f=-1.5,
+                   hi_frac: float = 0.04) -> Desc:
+    """Sector-like integrand whose exponents per variable are uniform in
+    {0..6}, with a fraction hi_frac of them set to 15 (the largest exponent the
+    descriptor accepts); monomial 0 of U and of F is constant, and complex
+    integrands get 30% negative non-constant F coefficients and lambda = 0.5."""
+    rng = np.random.default_rng(seed)
+
+    def poly(n_terms, neg_frac):
+        coef = rng.lognormal(0.0, 1.0, size=n_terms)
+        expo = rng.integers(0, 7, size=(n_terms, dim))
+        expo[rng.random(size=(n_terms, dim)) < hi_frac] = 15
+        expo[0, :] = 0
+        if neg_frac > 0 and n_terms > 1:
+            idx = rng.choice(np.arange(1, n_terms), size=int(round(neg_frac * (n_terms - 1))), replace=False)
+            coef[idx] = -coef[idx]
+        return coef, expo
+
+    cu, eu = poly(n_u, 0.0)
+    cf, ef = poly(n_f, 0.3 if complex_ else 0.0)
+    return Desc(dim=dim, coef=np.concatenate([cu, cf]), expo=np.concatenate([eu, ef]).astype(np.uint8).reshape(-1),
+                n_u=n_u, n_f=n_f, pow_u=pow_u, pow_f=pow_f, prefactor=1.0, deform=complex_,
+                lam=0.5 if complex_ else 0.0)
