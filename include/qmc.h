@@ -368,6 +368,35 @@ int qmc_cancel(qmc_context* ctx, uint64_t ticket);
 int qmc_serve_stats(qmc_context* ctx, uint64_t* rounds, uint64_t* queued, uint64_t* active,
                     uint64_t* bytes_in_use);
 
+/* ---------------------------------------------------------------- no allocation */
+
+/* Bytes of the static device scratch of qmc_integrate_noalloc (one copy per device). */
+#define QMC_NOALLOC_SCRATCH_BYTES (4 << 20)
+
+/*
+ * For callers that cannot allocate device or pinned host memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * qmc_integrate with rel_tol <= 0 (one lattice, the paper's "Case 2") that
+ * calls no hipMalloc, hipFree, hipHostMalloc or other allocating routine.
+ * Its scratch (shift table, per-block partial sums, the sums) is a static
+ * device array of QMC_NOALLOC_SCRATCH_BYTES per device, found when the
+ * context is created; the shift table SplitMix64(seed) is generated on the
+ * device.  Arguments, result and shift_sums ([m] or [2m], optional) as for
+ * qmc_integrate; the sums are bitwise those of qmc_integrate for the same
+ * call whenever both run the same kernel: the table-driven kernels, or an
+ * integrand's specialised kernel when qmc_integrate has already compiled it
+ * (none is compiled here).  Errors as qmc_integrate, plus QMC_ENOMEM when
+ * the launch needs more scratch than the static array holds (large m with
+ * many blocks) and QMC_EUNSUPPORTED for QMC_EVAL_FP32 integrands.  Every
+ * call on one device shares that device's array: calls that overlap on one
+ * device, from different contexts or threads, race and give wrong results;
+ * calls on one context are serialised.  The array keeps the last call's
+ * contents; nothing in it needs clearing between calls.
+ */
+int qmc_integrate_noalloc(qmc_context* ctx, const qmc_integrand* f, uint32_t dim, uint64_t n,
+                          const uint64_t* z, uint32_t m, uint64_t seed, qmc_transform t,
+                          qmc_result* out, double* shift_sums);
+
 /* ---------------------------------------------------------------- debug / parity */
 
 /* The shifts SplitMix64(seed) gives: out[s*dim + j], s < m, j < dim; each

@@ -117,6 +117,8 @@ def _declare(L):
         "qmc_integrate": ([vp, vp, C.c_uint32, C.c_uint64, up, C.c_uint32, C.c_uint64, Transform, C.c_double,
                            C.POINTER(Result), dp], C.c_int),
         "qmc_integrate_batch": ([vp, C.POINTER(Request), C.c_uint32, C.POINTER(Result), dp], C.c_int),
+        "qmc_integrate_noalloc": ([vp, vp, C.c_uint32, C.c_uint64, up, C.c_uint32, C.c_uint64, Transform,
+                                   C.POINTER(Result), dp], C.c_int),
         "qmc_shifts": ([C.c_uint64, C.c_uint32, C.c_uint32, dp], C.c_int),
         "qmc_lattice_indices": ([vp, C.c_uint64, C.c_uint32, up, C.c_uint64, C.c_uint64, up], C.c_int),
         "qmc_shift_sums_range": ([vp, vp, C.c_uint64, up, C.c_uint32, C.c_uint64, Transform, C.c_uint64,
@@ -301,6 +303,20 @@ class Context:
         out = np.zeros(m * (2 if f.complex else 1))
         _check(lib().qmc_integrate(self.handle, f.handle, f.dim, n, _up(zz), m, seed, _tr(transform), rel_tol,
                                    C.byref(res), _dp(out)))
+        d = res.as_dict()
+        if sums:
+            d["sums_re"] = out[:m].copy()
+            d["sums_im"] = out[m:].copy() if f.complex else np.zeros(m)
+        return d
+
+    def integrate_noalloc(self, f: Integrand, n: int, z, m: int, seed: int, transform=(T_KOROBOV, 3, 3),
+                          sums: bool = False):
+        """One lattice through qmc_integrate_noalloc (static device scratch)."""
+        zz = np.ascontiguousarray(z, dtype=np.uint64)
+        res = Result()
+        out = np.zeros(m * (2 if f.complex else 1))
+        _check(lib().qmc_integrate_noalloc(self.handle, f.handle, f.dim, n, _up(zz), m, seed, _tr(transform),
+                                           C.byref(res), _dp(out)))
         d = res.as_dict()
         if sums:
             d["sums_re"] = out[:m].copy()

@@ -130,6 +130,22 @@ int specialised_kernel(qmc_context* c, qmc_integrand* f, int tsel, qmcj::Kernel*
 // fill the integrand/transform part of an EvalArgs
 int fill_integrand_args(qmcd::EvalArgs& a, const qmc_integrand* f, const qmc_transform& t, int& tsel);
 
+// Launch plan of one lattice on the single-integral kernels (plan_lattice),
+// then enqueued on the context stream with its scratch (launch_lattice).
+struct LatticePlan {
+  qmcd::EvalArgs a;
+  qmcj::Kernel jk;
+  bool use_jit = false, cplx = false, idx32 = true;
+  int tsel = 0, dclass = 0;
+  uint32_t nb = 0, groups = 0, rows = 0;
+  size_t off_sh = 0, sz_sh = 0, off_part = 0, off_out = 0, sz_out = 0, bytes = 0;
+};
+int plan_lattice(qmc_context* c, qmc_integrand* f, uint64_t n, const uint64_t* z, uint32_t m, const qmc_transform& t,
+                 uint64_t k0, uint64_t k1, bool may_compile, LatticePlan& p);
+int launch_lattice(qmc_context* c, const qmc_integrand* f, LatticePlan& p, char* ws);
+// Finds the current device's copy of the static scratch of qmc_integrate_noalloc.
+int noalloc_init(int device);
+
 // one integral's current lattice in a batch round
 struct BatchJob {
   qmc_integrand* f = nullptr;

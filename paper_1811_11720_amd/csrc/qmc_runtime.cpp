@@ -260,60 +260,64 @@ int specialised_kernel(qmc_context* c, qmc_integrand* f, int tsel, qmcj::Kernel*
   return 0;
 }
 
-int run_lattice(qmc_context* c, qmc_integrand* f, uint64_t n, const uint64_t* z, uint32_t m,
-                const double* shift_tab, const qmc_transform& t, uint64_t k0, uint64_t k1, LatticeRun& out) {
+// Launch plan of one lattice (n, z), m shifts, points [k0, k1): kernel
+// choice (the integrand's specialised kernel for large jobs, compiled once per
+// structure, or only an already compiled one when may_compile is false),
+// grid, and the scratch layout [shifts | block partials | sums, sign count].
+int plan_lattice(qmc_context* c, qmc_integrand* f, uint64_t n, const uint64_t* z, uint32_t m, const qmc_transform& t,
+                 uint64_t k0, uint64_t k1, bool may_compile, LatticePlan& p) {
   const bool cplx = (f->flags & QMC_DEFORM) != 0;
-  qmcd::EvalArgs a;
+  qmcd::EvalArgs& a = p.a;
   std::memset(&a, 0, sizeof a);
   int tsel = 0;
   int rc = set_transform(a, t, tsel);
   if (rc) return rc;
   const uint32_t dim = f->dim;
-  const uint32_t rows = cplx ? 2 * m : m;
+  p.cplx = cplx;
+  p.rows = cplx ? 2 * m : m;
   const uint64_t npts = k1 - k0;
-  const bool idx32 = n <= (1ull << 31);
-  const int dclass = qmck::dim_class(dim, cplx);
-
-  // specialised kernel for large jobs (compiled once per integrand structure)
-  qmcj::Kernel jk;
-  bool use_jit = false;
+  p.idx32 = n <= (1ull << 31);
+  p.dclass = qmck::dim_class(dim, cplx);
+  p.tsel = tsel;
+  p.use_jit = false;
   int S = cplx ? qmck::S_COMPLEX : qmck::S_REAL;
-  if (!f->genz && c->jit && npts * (uint64_t)m >= c->jit_min_evals && specialised_kernel(c, f, tsel, &jk) == 0) {
-    use_jit = true;
-    S = cplx ? qmck::S_COMPLEX_JIT : c->jit_S;
+  if (!f->genz && c->jit && npts * (uint64_t)m >= c->jit_min_evals) {
+    const int jkey = tsel * 2 + (f->has_vr ? 1 : 0);
+    auto it = f->jit.find(jkey);
+    if (it != f->jit.end()) {
+      p.jk = it->second;
+      p.use_jit = true;
+    } else if (may_compile && specialised_kernel(c, f, tsel, &p.jk) == 0) {
+      p.use_jit = true;
+    }
+    if (p.use_jit) S = cplx ? qmck::S_COMPLEX_JIT : c->jit_S;
   }
-  const uint32_t groups = (m + S - 1) / S;
-  const int occ = use_jit     ? jk.occ_blocks
-                  : f->genz ? qmck::occupancy_genz(dclass, idx32)
-                            : qmck::occupancy_eval(cplx, dclass, tsel, idx32);
-  const uint32_t nb = plan_blocks(c, occ, groups, npts);
-
-  size_t off_sh = 0, sz_sh = (size_t)m * dim * sizeof(double);
-  size_t off_part = (sz_sh + 255) & ~(size_t)255, sz_part = (size_t)rows * nb * sizeof(double);
-  size_t off_out = (off_part + sz_part + 255) & ~(size_t)255, sz_out = (rows + 1) * sizeof(double);
-  char* ws = nullptr;
-  rc = scratch(c, off_out + sz_out, &ws);
-  if (rc) return rc;
-  rc = stage(c, std::max(sz_sh, sz_out));
-  if (rc) return rc;
-  std::memcpy(c->h_stage, shift_tab, sz_sh);
-  HIPCHK(hipMemcpyAsync(ws + off_sh, c->h_stage, sz_sh, hipMemcpyHostToDevice, c->stream));
+  p.groups = (m + S - 1) / S;
+  const int occ = p.use_jit  ? p.jk.occ_blocks
+                  : f->genz ? qmck::occupancy_genz(p.dclass, p.idx32)
+                            : qmck::occupancy_eval(cplx, p.dclass, tsel, p.idx32);
+  p.nb = plan_blocks(c, occ, p.groups, npts);
+  p.off_sh = 0;
+  p.sz_sh = (size_t)m * dim * sizeof(double);
+  p.off_part = (p.sz_sh + 255) & ~(size_t)255;
+  const size_t sz_part = (size_t)p.rows * p.nb * sizeof(double);
+  p.off_out = (p.off_part + sz_part + 255) & ~(size_t)255;
+  p.sz_out = (p.rows + 1) * sizeof(double);
+  p.bytes = p.off_out + p.sz_out;
 
   a.n = n;
   a.n_d = (double)n;
   a.inv_n = 1.0 / (double)n;
   a.k_begin = k0;
   a.k_end = k1;
-  a.stride = (uint64_t)nb * QMCD_BLOCK;
+  a.stride = (uint64_t)p.nb * QMCD_BLOCK;
   for (uint32_t j = 0; j < dim; ++j) {
     a.z[j] = z[j] % n;
     a.step[j] = mulmod(a.stride % n, a.z[j], n);
   }
   a.dim = dim;
   a.m = m;
-  a.shifts = (const double*)(ws + off_sh);
-  a.partial = (double*)(ws + off_part);
-  a.nblocks = nb;
+  a.nblocks = p.nb;
   a.coef = f->d_coef;
   a.expo = f->d_expo;
   a.n_u = f->n_u;
@@ -330,31 +334,59 @@ int run_lattice(qmc_context* c, qmc_integrand* f, uint64_t n, const uint64_t* z,
   a.wscale = std::pow(140.0, (double)dim);
   a.tk = tsel;  // TSEL_* and TK_* share their numbering
   a.genz = f->genz;
-  // the sign counter sits right after the per-shift sums
-  a.sign_count = (unsigned long long*)(ws + off_out + rows * sizeof(double));
+  return QMC_OK;
+}
+
+// Enqueue a planned lattice on the context stream with its scratch at ws (the
+// shift table already at ws + off_sh): clear the sign counter, the evaluation
+// kernel between the context's two events, the fixed-order finalize into
+// ws + off_out (rows sums, then the count of points with Im F(z) > 0).
+int launch_lattice(qmc_context* c, const qmc_integrand* f, LatticePlan& p, char* ws) {
+  qmcd::EvalArgs& a = p.a;
+  a.shifts = (const double*)(ws + p.off_sh);
+  a.partial = (double*)(ws + p.off_part);
+  a.sign_count = (unsigned long long*)(ws + p.off_out + p.rows * sizeof(double));
+  const dim3 grid(p.nb, p.groups);
   HIPCHK(qmck::launch_fill_u64(a.sign_count, 1, 0ull, c->stream));
   HIPCHK(hipEventRecord(c->ev0, c->stream));
-  if (use_jit) {
-    HIPCHK(qmcj::launch(jk, idx32, a, dim3(nb, groups), c->stream));
+  if (p.use_jit) {
+    HIPCHK(qmcj::launch(p.jk, p.idx32, a, grid, c->stream));
   } else if (f->genz) {
-    HIPCHK(qmck::launch_eval_genz(a, dclass, idx32, dim3(nb, groups), c->stream));
-  } else if (cplx) {
-    HIPCHK(qmck::launch_eval_complex(a, dclass, tsel, idx32, dim3(nb, groups), c->stream));
+    HIPCHK(qmck::launch_eval_genz(a, p.dclass, p.idx32, grid, c->stream));
+  } else if (p.cplx) {
+    HIPCHK(qmck::launch_eval_complex(a, p.dclass, p.tsel, p.idx32, grid, c->stream));
   } else {
-    HIPCHK(qmck::launch_eval_real(a, dclass, tsel, idx32, dim3(nb, groups), c->stream));
+    HIPCHK(qmck::launch_eval_real(a, p.dclass, p.tsel, p.idx32, grid, c->stream));
   }
   HIPCHK(hipEventRecord(c->ev1, c->stream));
-  HIPCHK(qmck::launch_finalize(a.partial, nb, rows, (double*)(ws + off_out), c->stream));
-  HIPCHK(hipMemcpyAsync(c->h_stage, ws + off_out, sz_out, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(qmck::launch_finalize(a.partial, p.nb, p.rows, (double*)(ws + p.off_out), c->stream));
+  return QMC_OK;
+}
+
+int run_lattice(qmc_context* c, qmc_integrand* f, uint64_t n, const uint64_t* z, uint32_t m,
+                const double* shift_tab, const qmc_transform& t, uint64_t k0, uint64_t k1, LatticeRun& out) {
+  LatticePlan p;
+  int rc = plan_lattice(c, f, n, z, m, t, k0, k1, true, p);
+  if (rc) return rc;
+  char* ws = nullptr;
+  rc = scratch(c, p.bytes, &ws);
+  if (rc) return rc;
+  rc = stage(c, std::max(p.sz_sh, p.sz_out));
+  if (rc) return rc;
+  std::memcpy(c->h_stage, shift_tab, p.sz_sh);
+  HIPCHK(hipMemcpyAsync(ws + p.off_sh, c->h_stage, p.sz_sh, hipMemcpyHostToDevice, c->stream));
+  rc = launch_lattice(c, f, p, ws);
+  if (rc) return rc;
+  HIPCHK(hipMemcpyAsync(c->h_stage, ws + p.off_out, p.sz_out, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   float ms = 0;
   HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
   out.kernel_seconds = ms * 1e-3;
-  out.sums.assign(c->h_stage, c->h_stage + rows);
+  out.sums.assign(c->h_stage, c->h_stage + p.rows);
   uint64_t sp;
-  std::memcpy(&sp, c->h_stage + rows, sizeof sp);
+  std::memcpy(&sp, c->h_stage + p.rows, sizeof sp);
   out.sign_points = sp;
-  out.path = use_jit ? 1u : 0u;
+  out.path = p.use_jit ? 1u : 0u;
   return QMC_OK;
 }
 
@@ -799,6 +831,10 @@ int qmc_context_create(int device, void* hip_stream, void* workspace, size_t wor
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
     c->cus = cus;
+  // the static scratch of qmc_integrate_noalloc on this device; a failure
+  // here is reported by that entry point, which looks it up again
+  (void)noalloc_init(device);
+  g_err.clear();
   *out = c;
   return QMC_OK;
 }
