@@ -67,8 +67,10 @@ def flops_per_eval(desc, transform) -> float:
 def flops_per_eval_complex(desc, transform) -> float:
     """Algorithmic flops of one deformed complex evaluation: the real
     x-generation and transform; per F monomial 3 nnz + 2 nnz (nnz + 1) for its
-    gradient and Hessian terms; 4d for z; 3d^2 to form the matrix whose
-    determinant is the Jacobian and 8 d^3 / 3 for its complex elimination;
+    gradient and Hessian terms; 4d for z; 3d^2 to form the real symmetric
+    matrix A with det(dz/dx) = det(I - i lambda A); sum over m = 2..d-1 of
+    4 m^2 + 6 m + 6 for its Householder reduction to tridiagonal form and 8d
+    for the continuant of I - i lambda T;
     6 nnz + 4 per complex monomial of U(z) and F(z); complex powers at six
     flops per complex product (plus 10 for a square root, 8 for a reciprocal);
     12 for the final products, 2 for the weight and 4 to accumulate."""
@@ -85,7 +87,7 @@ def flops_per_eval_complex(desc, transform) -> float:
         if i >= desc.n_u:
             fl += 3 * nnz + 2 * nnz * (nnz + 1)
         fl += 6 * nnz + 4
-    fl += 4.0 * d + 3.0 * d * d + 8.0 * d ** 3 / 3.0
+    fl += 4.0 * d + 3.0 * d * d + sum(4.0 * k * k + 6.0 * k + 6.0 for k in range(2, d)) + 8.0 * d
 
     def pw(p):
         if p == 0:
@@ -106,28 +108,80 @@ def desc_flops(desc, transform) -> float:
     return flops_per_eval_complex(desc, transform) if desc.deform else flops_per_eval(desc, transform)
 
 
-def cpu_baseline(job, target_seconds: float, threads: int):
-    """The oracle, as it stands, on all m shifts of a prefix [0, k) of the same
-    lattice; k grows until one run takes at least half the target time."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads() -> int:
+    """Threads the oracle may use: the cores this process may run on, at most 16."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _oracle_rate(jobs, k, threads):
+    """Oracle evals/s over all shifts of the points [0, min(k, n)) of each job."""
     import oracle
 
-    sh = oracle.shifts(job.seed, job.m, job.desc.dim)
-    k = 8192
-    oracle.shift_sums(job.desc, job.n, job.z, job.m, sh, job.transform, k0=0, k1=k, threads=threads)  # warm
-    while True:
-        t0 = time.perf_counter()
-        oracle.shift_sums(job.desc, job.n, job.z, job.m, sh, job.transform, k0=0, k1=k, threads=threads)
-        dt = time.perf_counter() - t0
-        if dt >= 0.5 * target_seconds or k >= job.n:
-            break
-        k = int(min(job.n, max(2 * k, k * target_seconds / max(dt, 1e-6))))
+    ev = 0
+    t0 = time.perf_counter()
+    for j in jobs:
+        kk = min(k, j.n)
+        sh = oracle.shifts(j.seed, j.m, j.desc.dim)
+        oracle.shift_sums(j.desc, j.n, j.z, j.m, sh, j.transform, k0=0, k1=kk, threads=threads)
+        ev += kk * j.m
+    return ev, time.perf_counter() - t0
+
+
+def cpu_baseline(jobs, target_seconds: float, what: str):
+    """The oracle, as it stands, on a bounded sample of the workload: all m
+    shifts of the points [0, k) of each job in `jobs`, k doubled until a run
+    takes about target_seconds, timed on every available thread (at most 16)
+    and then on one core (a third of the time budget)."""
+    if not isinstance(jobs, (list, tuple)):
+        jobs = [jobs]
+    threads = host_threads()
+
+    def timed(th, budget):
+        k = 1024
+        _oracle_rate(jobs, min(k, 256), th)  # warm
+        while True:
+            ev, dt = _oracle_rate(jobs, k, th)
+            whole = all(k >= j.n for j in jobs)
+            if dt >= 0.5 * budget or whole:
+                break
+            k = int(max(2 * k, k * budget / max(dt, 1e-6) * 0.9))
+        reps = 1
+        if whole and dt < 0.5 * budget:  # small jobs: repeat them whole
+            reps = int(math.ceil(0.5 * budget / max(dt, 1e-6)))
+            ev = dt = 0
+            for _ in range(reps):
+                e, d = _oracle_rate(jobs, k, th)
+                ev += e
+                dt += d
+        return min(k, max(j.n for j in jobs)), reps, ev, dt
+
+    k, reps, ev, dt = timed(threads, target_seconds)
+    k1, reps1, ev1, dt1 = timed(1, target_seconds / 3.0)
     return {
-        "value": k * job.m / dt,
+        "value": ev / dt,
         "unit": "evals/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": f"all {job.m} shifts over lattice points [0, {k}) of the same n={job.n} lattice "
-                  f"({k * job.m} evaluations, {dt:.1f} s, plain fp64 C, double-double sums)",
+        "one_core_value": ev1 / dt1,
+        "cpu_model": cpu_model(),
+        "sample": f"{what}: all shifts over lattice points [0, k) of each of {len(jobs)} job(s) "
+                  f"(k={k} x {reps} runs on {threads} threads: {ev} evaluations in {dt:.1f} s; k={k1} x {reps1} runs "
+                  f"on 1 core: {ev1} evaluations in {dt1:.1f} s), plain fp64 C, double-double sums",
     }
 
 
@@ -248,6 +302,59 @@ def bench_batch(a, Q, W, torch):
     modes["fp32"]["rel_diff_max"] = float(np.max(rel))
     modes["fp32"]["diff_over_sigma64_p50"] = float(np.percentile(over_sig, 50))
     modes["fp32"]["diff_over_sigma64_p99"] = float(np.percentile(over_sig, 99))
+    # equal stated error: the first `goal_count` integrals with one relative
+    # goal, grown through the lattice table, as (a) the fp32-evaluation batch,
+    # (b) the fp64 batch, (c) one fp64 qmc_integrate_request per integral
+    # through the default single path (kernels specialised to each integrand
+    # for jobs of >= 2^24 evaluations: a first pass compiles them, the second
+    # runs with them cached)
+    if a.goal_count:
+        gsub = pool[: a.goal_count]
+        gctx = Q.Context(0)
+        gctx.register_table(W.lattice_table())
+        eq = {"goal_rel": a.goal, "integrals": len(gsub), "max_evals": a.goal_max_evals}
+
+        def goal_reqs(fs):
+            return [dict(f=f, n=j.n, z=None, m=j.m, seed=j.seed, transform=j.transform, rel_tol=a.goal,
+                         max_evals=a.goal_max_evals) for f, j in zip(fs, gsub)]
+
+        def summary(res, wall):
+            ev = sum(r["evaluations"] for r in res)
+            conv = sum(1 for r in res if r["flags"] & 1)
+            mags = [max(abs(r["re"]), abs(r["im"])) for r in res]
+            stated = [max(r["err_re"], r["err_im"]) / m for r, m in zip(res, mags) if m > 0]
+            fp32 = [max(r["fp32_err_re"], r["fp32_err_im"]) / m for r, m in zip(res, mags) if m > 0]
+            return {"evals": ev, "seconds": wall, "evals_per_s": ev / wall, "converged": conv,
+                    "rel_err_p50": float(np.percentile(stated, 50)), "rel_err_max": float(np.max(stated)),
+                    "fp32_rel_err_p50": float(np.percentile(fp32, 50)), "fp32_rel_err_max": float(np.max(fp32))}
+
+        for mode in ("fp32", "fp64"):
+            fs = []
+            for j in gsub:
+                d = copy.copy(j.desc)
+                d.fp32 = mode == "fp32"
+                fs.append(gctx.integrand(d))
+            gctx.integrate_batch(goal_reqs(fs))  # warm
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = gctx.integrate_batch(goal_reqs(fs))
+            eq[f"batch_{mode}"] = summary(res, time.perf_counter() - t0)
+            for f in fs:
+                f.close()
+        fs = [gctx.integrand(j.desc) for j in gsub]
+        for pas in ("first_pass", "cached"):
+            t0 = time.perf_counter()
+            res = [gctx.integrate_request(r) for r in goal_reqs(fs)]
+            eq[f"per_integral_fp64_{pas}"] = summary(res, time.perf_counter() - t0)
+        for f in fs:
+            f.close()
+        gctx.close()
+        eq["fp32_batch_over_per_integral_fp64"] = (eq["batch_fp32"]["evals_per_s"]
+                                                   / eq["per_integral_fp64_cached"]["evals_per_s"])
+        print(f"[batch] equal goal {a.goal:g}: fp32 batch {eq['batch_fp32']['evals_per_s']:.3e}, fp64 batch "
+              f"{eq['batch_fp64']['evals_per_s']:.3e}, per-integral fp64 {eq['per_integral_fp64_cached']['evals_per_s']:.3e}"
+              f" evals/s", file=sys.stderr, flush=True)
+        modes["equal_goal"] = eq
     # one launch per integral on a subset, through the table-driven grid
     # kernels (run-time specialisation off: its compile time would dominate)
     sub = pool[: a.per_integral]
@@ -307,6 +414,8 @@ def bench_batch(a, Q, W, torch):
             "traffic": None,
         },
     }
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(pool[:24], a.cpu_seconds, "the first 24 integrals of the same mix")
     print(json.dumps(out), flush=True)
     return 0
 
@@ -365,6 +474,10 @@ def bench_genz(a, Q, W, torch):
         "device_evals_per_s": tot_ev / tot_dev,
         "results": rows,
     }
+    if not a.no_cpu:
+        gj = [W.Job(W.genz(fam, dim, 1000 * fam + 100 * dim), n0, table[n0][:dim], 32, seed=5000, transform=tr)
+              for dim in (5, 8, 10) for fam in range(1, 7)]
+        out["cpu_baseline"] = cpu_baseline(gj, a.cpu_seconds, f"the 18 family/dimension pairs on the n={n0} lattice")
     print(json.dumps(out), flush=True)
     return 0
 
@@ -442,6 +555,9 @@ def bench_sector_complex(a, Q, W, torch):
                      "frac": fl * r["evaluations"] / r["device_seconds"] / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
                      "traffic": None, "flops_per_eval": fl},
     }
+    if not a.no_cpu:
+        cj = W.job_sector_complex(1000003)
+        out["cpu_baseline"] = cpu_baseline(cj, a.cpu_seconds, "the n=1000003 lattice without the VR map")
     print(json.dumps(out), flush=True)
     return 0
 
@@ -474,21 +590,24 @@ def bench_plain(a, Q, W, torch):
     spec.specialise = True
     fs = ctx.integrand(spec)
     reqs = [dict(f=fs, n=job.n, z=job.z, m=job.m, seed=job.seed + 1 + i, transform=job.transform) for i in range(reps)]
+    # marshalled once: the timed call is qmc_integrate_batch itself (host planning, one launch, results)
+    prepared = ctx.prepare_batch(reqs)
     for _ in range(a.warmup):
-        ctx.integrate_batch(reqs)
+        prepared.run()
     torch.cuda.synchronize()
     bdev = []
     t0 = time.perf_counter()
     for _ in range(a.steps):
-        res = ctx.integrate_batch(reqs)
-        bdev.append(res[0]["device_seconds"])
+        res, _ = prepared.run()
+        bdev.append(float(res["device_seconds"][0]))
     el = (time.perf_counter() - t0) / a.steps
     ev = reps * job.n * job.m
     kern = float(np.median(bdev))
-    worst = max(abs(x["re"] - 1.0) for x in res)
+    worst = float(np.max(np.abs(res["re"] - 1.0)))
     replicas = {"replicas": reps, "evals": ev, "evals_per_s": ev / el, "device_ms": kern * 1e3,
                 "evals_per_s_device": ev / kern, "tflops": flops * ev / kern / 1e12,
-                "frac": flops * ev / kern / 1e12 / FP64_VECTOR_PEAK_TFLOPS, "max_abs_error_vs_exact": worst}
+                "frac": flops * ev / kern / 1e12 / FP64_VECTOR_PEAK_TFLOPS, "max_abs_error_vs_exact": worst,
+                "end_to_end_ms": el * 1e3, "end_to_end_over_device": el / kern}
     print(f"[plain] {reps} replicas: {ev / kern:.3e} evals/s on the device", file=sys.stderr, flush=True)
     fs.close()
     nl = W.next_table_n(10 ** 7)
@@ -526,6 +645,8 @@ def bench_plain(a, Q, W, torch):
         "replicas": replicas,
         "large_n": large,
     }
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(job, a.cpu_seconds, f"the n={job.n} job itself")
     print(json.dumps(out), flush=True)
     return 0
 
@@ -632,6 +753,8 @@ def bench_serve(a, Q, W, torch):
         "latency_by_load": rates,
         "serve_rounds": st["rounds"],
     }
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(pool[:24], a.cpu_seconds, "the first 24 integrals of the request pool")
     print(json.dumps(out), flush=True)
     return 0
 
@@ -659,6 +782,9 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="batch: tune the schedules first")
     ap.add_argument("--kind", choices=["all", "real", "complex"], default="all", help="batch: integrands kept")
     ap.add_argument("--per-integral", type=int, default=100, help="batch: integrals timed one launch each")
+    ap.add_argument("--goal", type=float, default=1e-6, help="batch: relative goal of the equal-error comparison")
+    ap.add_argument("--goal-count", type=int, default=32, help="batch: integrals in the equal-error comparison")
+    ap.add_argument("--goal-max-evals", type=int, default=10 ** 9, help="batch: evaluation cap per integral there")
     ap.add_argument("--requests", type=int, default=200, help="serve: requests per load level")
     ap.add_argument("--req-lo", type=int, default=10)
     ap.add_argument("--req-hi", type=int, default=500)
@@ -750,8 +876,7 @@ def main():
         },
     }
     if not a.no_cpu:
-        threads = min(16, os.cpu_count() or 1)
-        out["cpu_baseline"] = cpu_baseline(job, a.cpu_seconds, threads)
+        out["cpu_baseline"] = cpu_baseline(job, a.cpu_seconds, f"the same n={job.n} lattice")
     f.close()
     ctx.close()
     print(json.dumps(out), flush=True)

@@ -138,7 +138,9 @@ enum {
                           for its structure (compiled at first use, a few seconds; shared by integrands of the
                           same structure) instead of the table-driven kernels.  The per-shift sums of a job
                           then come from that kernel, still the same alone or in any batch.  Single
-                          qmc_integrate calls choose by size and ignore the flag. */
+                          integrations ignore the flag: they compile an integrand's specialised kernel
+                          for a job of at least 2^24 evaluations, and once it is compiled it runs every
+                          later single job of that integrand handle, whatever its size. */
 };
 
 /*
@@ -255,6 +257,12 @@ typedef struct {
   double device_seconds;  /* summed duration of the evaluation kernels (HIP events) */
   double queue_seconds;   /* submit-to-start wait (serving); 0 otherwise */
   double wall_seconds;    /* host wall time of the request */
+  double fp32_err_re, fp32_err_im; /* QMC_EVAL_FP32 results: the fp32 evaluation's error in re, im,
+                             estimated on a sample of the last lattice (every 16th tile of the
+                             batch tiling: all points when it has one tile) that is evaluated in
+                             fp64 as well: |sum (w f_fp32 - w f_fp64)| / |sum w f_fp64| over the
+                             sample and all shifts (complex modulus), times |estimate|; 0 for
+                             fp64 evaluation */
 } qmc_result;
 
 /*
@@ -340,7 +348,12 @@ int qmc_autotune_batch(qmc_context* ctx, const qmc_request* reqs, uint32_t count
  * 8 GiB), and runs rounds of the batch kernels over every admitted request's
  * current lattice; each request applies its own goal and growth rule
  * (Sec. 3.3.1) between rounds, so requests arriving while others run join the
- * next round.  A request's memory is reserved for the largest lattice it may
+ * next round.  Rounds are bounded: each unfinished request gets about an equal
+ * share of a round's cost budget (QMC_SERVE_ROUND_COST, default 2^39 units of
+ * evaluations weighted by integrand size, about a tenth of a second of the
+ * device), its whole current lattice when that fits, else the next slice of
+ * the lattice's tiles, whose partial sums stay on the device until the
+ * lattice is done; sliced or not, a lattice's per-shift sums are the same.  A request's memory is reserved for the largest lattice it may
  * reach and the smallest tiles any schedule may give it, and returns to the
  * budget when that request finishes.  With a caller-owned workspace the
  * budget is also capped by the workspace size.  Results equal

@@ -73,6 +73,8 @@ class Result(C.Structure):
         ("device_seconds", C.c_double),
         ("queue_seconds", C.c_double),
         ("wall_seconds", C.c_double),
+        ("fp32_err_re", C.c_double),
+        ("fp32_err_im", C.c_double),
     ]
 
     def as_dict(self):
@@ -434,6 +436,10 @@ class Context:
                 off += m * (2 if r["f"].complex else 1)
         return outs
 
+    def prepare_batch(self, reqs) -> "PreparedBatch":
+        """Marshal a request list once for repeated qmc_integrate_batch calls."""
+        return PreparedBatch(self, reqs)
+
     def lattice_indices(self, n: int, z, k0: int, count: int) -> np.ndarray:
         zz = np.ascontiguousarray(z, dtype=np.uint64)
         out = np.empty(count * zz.size, dtype=np.uint64)
@@ -471,3 +477,36 @@ class Context:
             self.close()
         except Exception:
             pass
+
+
+class PreparedBatch:
+    """A request array marshalled once; run() calls qmc_integrate_batch on it
+    and returns the results as a numpy record array (fields of qmc_result)
+    and, with sums=True, the per-shift sums back to back."""
+
+    def __init__(self, ctx: Context, reqs):
+        self.ctx = ctx
+        self.count = len(reqs)
+        self._keep = []
+        self.arr = (Request * self.count)()
+        zcache = {}
+        total = 0
+        for i, r in enumerate(reqs):
+            z = r.get("z")
+            zp = None
+            if z is not None:
+                zp = zcache.get(id(z))
+                if zp is None:
+                    zz = np.ascontiguousarray(z, dtype=np.uint64)
+                    self._keep.append(zz)
+                    zp = zcache[id(z)] = _up(zz)
+            self.arr[i] = Request(r["f"].handle, r["n"], zp, r["m"], r.get("errormode", ERRMODE_LARGEST), r["seed"],
+                                  _tr(r.get("transform", (T_KOROBOV, 3, 3))), r.get("rel_tol", 0.0),
+                                  r.get("abs_tol", 0.0), r.get("max_evals", 0))
+            total += r["m"] * (2 if r["f"].complex else 1)
+        self.res = (Result * self.count)()
+        self.sums = np.zeros(max(total, 1))
+
+    def run(self):
+        _check(lib().qmc_integrate_batch(self.ctx.handle, self.arr, self.count, self.res, _dp(self.sums)))
+        return np.ctypeslib.as_array(self.res).copy(), self.sums

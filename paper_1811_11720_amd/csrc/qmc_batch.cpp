@@ -18,6 +18,8 @@
 #include <cstring>
 #include <cstdio>
 #include <numeric>
+#include <string>
+#include <unordered_map>
 
 #include "qmc_host.h"
 
@@ -37,7 +39,11 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 uint64_t batch_tile_points(const qmc_context* c, uint64_t tuned, bool cplx, uint64_t n) {
   const uint64_t tmin = tuned ? tuned : (cplx ? c->batch_tile_complex : c->batch_tile_real);
-  const uint64_t tp = std::max<uint64_t>(tmin, (n + c->batch_max_ktiles - 1) / c->batch_max_ktiles);
+  const uint64_t t0 = std::max<uint64_t>(tmin, (n + c->batch_max_ktiles - 1) / c->batch_max_ktiles);
+  // as many tiles as tiles of t0 points need, made even (a short last tile
+  // would leave its workgroup idle for most of a tile's time)
+  const uint64_t kt = std::max<uint64_t>(1, (n + t0 - 1) / t0);
+  const uint64_t tp = (n + kt - 1) / kt;
   return (tp + QMCD_BLOCK - 1) / QMCD_BLOCK * QMCD_BLOCK;
 }
 
@@ -47,13 +53,140 @@ uint64_t batch_ktiles_bound(const qmc_context* c, uint64_t n) {
   return (n + tp - 1) / tp;
 }
 
-size_t batch_job_bytes(size_t rows, uint64_t ktiles, uint32_t m, uint32_t dim) {
+size_t batch_job_bytes(size_t rows, uint64_t ktiles, uint32_t m, uint32_t dim, bool fp32) {
   // arena entries of one job (run_batch's layout) plus its share of the alignment padding
-  return sizeof(qmcd::EvalArgs) + 4 + 8 + rows * (sizeof(qmck::RowRef) + 8 * ktiles + 8) + (size_t)m * dim * 8 + 8 +
-         256;
+  size_t b = sizeof(qmcd::EvalArgs) + 4 + 8 + rows * (sizeof(qmck::RowRef) + 8 * ktiles + 8) + (size_t)m * dim * 8 +
+             8 + 256;
+  if (fp32)  // the fp64 twin over the first tiles, and the rows of the job's own first columns
+    b += sizeof(qmcd::EvalArgs) + 4 + 8 + 8 +
+         rows * (2 * (sizeof(qmck::RowRef) + 8) + 8 * (size_t)batch_fp32_sample_tiles((uint32_t)ktiles));
+  return b;
 }
 
+namespace {
+
+int run_batch_jobs(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_seconds);
+
+// Key of the jobs that can share one item: the integrand, the lattice and the
+// transform (the shifts are what differs).
+std::string merge_key(const BatchJob& b) {
+  std::string k;
+  const uint32_t dim = b.f->dim;
+  k.resize(sizeof(void*) + 8 + 3 * 4 + (size_t)dim * 8);
+  char* w = &k[0];
+  std::memcpy(w, &b.f, sizeof(void*));
+  w += sizeof(void*);
+  std::memcpy(w, &b.n, 8);
+  w += 8;
+  const int32_t t[3] = {b.t.kind, b.t.r0, b.t.r1};
+  std::memcpy(w, t, 12);
+  w += 12;
+  for (uint32_t j = 0; j < dim; ++j) {
+    const uint64_t zj = b.z[j] % b.n;
+    std::memcpy(w + 8 * j, &zj, 8);
+  }
+  return k;
+}
+
+}  // namespace
+
+int batch_job_shape(qmc_context* c, const BatchJob& b, BatchShape& sh) {
+  const qmc_integrand* f = b.f;
+  const bool cplx = (f->flags & QMC_DEFORM) != 0, fp32 = (f->flags & QMC_EVAL_FP32) != 0;
+  qmcd::EvalArgs probe;
+  int tsel = 0;
+  int rc = set_transform(probe, b.t, tsel);
+  if (rc) return rc;
+  sh.var = qmck::BatchVariant{qmck::dim_class(f->dim, cplx), qmck::batch_tkc(tsel, f->has_vr), cplx, fp32};
+  sh.use_jit = false;
+  if (!cplx && !fp32 && (f->flags & QMC_SPECIALISE) && c->jit &&
+      specialised_kernel(c, const_cast<qmc_integrand*>(b.f), tsel, &sh.jk) == 0 && sh.jk.batch)
+    sh.use_jit = true;
+  const uint32_t S = cplx ? qmck::S_COMPLEX : qmck::S_REAL;
+  sh.tile_points = batch_tile_points(c, sh.use_jit ? 0 : c->batch_tile[sh.var.index()], cplx, b.n);
+  sh.ktiles = (uint32_t)((b.n + sh.tile_points - 1) / sh.tile_points);
+  sh.groups = (b.m + S - 1) / S;
+  sh.rows = cplx ? 2 * b.m : b.m;
+  return QMC_OK;
+}
+
+// Real jobs of one integrand on one lattice with one transform (replicas
+// with different shift seeds, or the requests of a served ticket that share a
+// sector) run as one item whose shift table is the concatenation of theirs.
+// A shift's sum depends only on the lattice, the tiling (a function of n and
+// the kernel variant) and the shift itself, never on which shifts share its
+// thread group, so every job's sums are bitwise those it gets alone; merged,
+// the thread groups of S shifts are full instead of each job's last one
+// being partly empty, and the item list is shorter.  Complex jobs are not
+// merged: their count of points with Im F(z) > 0 is kept per job.
 int run_batch(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_seconds) {
+  const uint32_t J = (uint32_t)jobs.size();
+  if (kernel_seconds) *kernel_seconds = 0.0;
+  if (J < 2) return run_batch_jobs(c, jobs, kernel_seconds);
+  std::unordered_map<std::string, uint32_t> slot;  // key -> index into work
+  std::vector<std::vector<uint32_t>> members;
+  std::vector<BatchJob*> work;
+  std::vector<uint32_t> owner(J, UINT32_MAX);
+  for (uint32_t i = 0; i < J; ++i) {
+    const BatchJob& b = *jobs[i];
+    if ((b.f->flags & QMC_DEFORM) || b.ext_partial || b.tile_count) continue;
+    auto ins = slot.emplace(merge_key(b), (uint32_t)members.size());
+    if (ins.second) members.emplace_back();
+    members[ins.first->second].push_back(i);
+  }
+  bool any = false;
+  for (const auto& g : members) any = any || g.size() > 1;
+  if (!any) return run_batch_jobs(c, jobs, kernel_seconds);
+  std::vector<BatchJob> merged;
+  std::vector<std::vector<double>> tabs;
+  merged.reserve(members.size());
+  tabs.reserve(members.size());
+  for (const auto& g : members) {
+    if (g.size() == 1) continue;
+    const BatchJob& first = *jobs[g.front()];
+    const uint32_t dim = first.f->dim;
+    BatchJob mj;
+    mj.f = first.f;
+    mj.n = first.n;
+    mj.z = first.z;
+    mj.t = first.t;
+    std::vector<double> tab;
+    for (uint32_t i : g) {
+      tab.insert(tab.end(), jobs[i]->shifts, jobs[i]->shifts + (size_t)jobs[i]->m * dim);
+      mj.m += jobs[i]->m;
+      owner[i] = (uint32_t)merged.size();
+    }
+    tabs.push_back(std::move(tab));
+    mj.shifts = tabs.back().data();
+    merged.push_back(std::move(mj));
+  }
+  for (uint32_t i = 0; i < J; ++i)
+    if (owner[i] == UINT32_MAX) work.push_back(jobs[i]);
+  for (BatchJob& mj : merged) work.push_back(&mj);
+  int rc = run_batch_jobs(c, work, kernel_seconds);
+  if (rc) return rc;
+  std::vector<uint32_t> at(merged.size(), 0);  // next shift of each merged job
+  for (uint32_t i = 0; i < J; ++i) {
+    if (owner[i] == UINT32_MAX) continue;
+    const BatchJob& mj = merged[owner[i]];
+    const uint32_t s0 = at[owner[i]];
+    jobs[i]->sums.assign(mj.sums.begin() + s0, mj.sums.begin() + s0 + jobs[i]->m);
+    jobs[i]->sign_points = 0;
+    jobs[i]->fp32_dev.clear();
+    jobs[i]->fp32_ref.clear();
+    jobs[i]->fp32_dev_points = mj.fp32_dev_points;
+    if (!mj.fp32_dev.empty()) {
+      jobs[i]->fp32_dev.assign(mj.fp32_dev.begin() + s0, mj.fp32_dev.begin() + s0 + jobs[i]->m);
+      jobs[i]->fp32_ref.assign(mj.fp32_ref.begin() + s0, mj.fp32_ref.begin() + s0 + jobs[i]->m);
+    }
+    at[owner[i]] = s0 + jobs[i]->m;
+  }
+  return QMC_OK;
+}
+
+namespace {
+
+int run_batch_jobs(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_seconds) {
   const uint32_t J = (uint32_t)jobs.size();
   if (kernel_seconds) *kernel_seconds = 0.0;
   if (J == 0) return QMC_OK;
@@ -66,6 +199,11 @@ int run_batch(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_secon
     double cost;
     bool use_jit = false;  // the integrand's specialised batch kernel (QMC_SPECIALISE)
     qmcj::Kernel jk;
+    uint32_t tiles = 0;    // tiles of the job this call evaluates
+    bool finish = true;    // the job's sums are produced (all of its tiles are then evaluated)
+    uint32_t job;          // the job evaluated (a twin evaluates its job's first columns in fp64)
+    int twin = -1;         // fp32 job: index of its fp64 twin plan
+    size_t pref_row0 = 0;  // fp32 job: rows summing its first twin-ktiles columns
   };
   std::vector<Plan> plan(J);
   std::vector<hipFunction_t> jit_fns;  // distinct specialised kernels in this call
@@ -73,40 +211,71 @@ int run_batch(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_secon
   for (uint32_t i = 0; i < J; ++i) {
     BatchJob& b = *jobs[i];
     const qmc_integrand* f = b.f;
-    const bool cplx = (f->flags & QMC_DEFORM) != 0, fp32 = (f->flags & QMC_EVAL_FP32) != 0;
     Plan& p = plan[i];
-    const int dclass = qmck::dim_class(f->dim, cplx);
-    qmcd::EvalArgs probe;
-    int tsel = 0;
-    int trc = set_transform(probe, b.t, tsel);
+    p.job = i;
+    BatchShape sh;
+    int trc = batch_job_shape(c, b, sh);
     if (trc) return trc;
-    p.var = qmck::BatchVariant{dclass, qmck::batch_tkc(tsel, f->has_vr), cplx, fp32};
+    p.var = sh.var;
     p.variant = p.var.index();
-    if (!cplx && !fp32 && (f->flags & QMC_SPECIALISE) && c->jit && specialised_kernel(c, b.f, tsel, &p.jk) == 0 &&
-        p.jk.batch) {
+    if (sh.use_jit) {
       // jobs of one specialised kernel form a launch of their own
       p.use_jit = true;
+      p.jk = sh.jk;
       auto it = std::find(jit_fns.begin(), jit_fns.end(), p.jk.batch);
       p.variant = qmck::BATCH_VARIANTS + (int)(it - jit_fns.begin());
       if (it == jit_fns.end()) jit_fns.push_back(p.jk.batch);
     }
-    const uint32_t S = cplx ? qmck::S_COMPLEX : qmck::S_REAL;
-    const uint64_t tp = batch_tile_points(c, p.use_jit ? 0 : c->batch_tile[p.variant], cplx, b.n);
-    p.tile_points = tp;
-    p.ktiles = (uint32_t)((b.n + tp - 1) / tp);
-    p.groups = (b.m + S - 1) / S;
-    p.rows = cplx ? 2 * b.m : b.m;
-    p.part_off = n_part;
-    n_part += (size_t)p.rows * p.ktiles;
+    p.tile_points = sh.tile_points;
+    p.ktiles = sh.ktiles;
+    p.groups = sh.groups;
+    p.rows = sh.rows;
+    const uint64_t all = (uint64_t)p.ktiles * p.groups;
+    if (b.tile_count && (b.tile_first >= all || b.tile_count > all - b.tile_first))
+      return fail(QMC_EINVAL, "tile range [%u, %u) outside the job's %llu tiles", b.tile_first,
+                  b.tile_first + b.tile_count, (unsigned long long)all);
+    p.tiles = b.tile_count ? b.tile_count : (uint32_t)all;
+    p.finish = b.finish || !b.ext_partial;
+    if (!b.ext_partial) {
+      p.part_off = n_part;
+      n_part += (size_t)p.rows * p.ktiles;
+    }
     p.sh_off = n_sh;
     n_sh += (size_t)b.m * f->dim;
-    p.row0 = n_rows;
-    n_rows += p.rows;
-    p.cost = cost_per_eval(f) * (double)b.n * b.m;
+    if (p.finish) {
+      p.row0 = n_rows;
+      n_rows += p.rows;
+    }
+    p.cost = cost_per_eval(f) * (double)b.n * b.m * ((double)p.tiles / (double)all);
   }
+  // FP32 jobs: an fp64 twin over every kFp32SampleEvery-th tile of the job
+  // (same tiling, same shifts), and rows summing the fp32 job's own columns of
+  // those tiles: their difference is the fp32 evaluation's error over that
+  // strided sample of points
+  for (uint32_t i = 0; i < J; ++i) {
+    if (!(jobs[i]->f->flags & QMC_EVAL_FP32) || !plan[i].finish) continue;
+    Plan t = plan[i];
+    t.job = i;
+    t.tiles = 0;
+    t.var.fp32 = false;
+    t.variant = t.var.index();
+    t.use_jit = false;
+    t.ktiles = batch_fp32_sample_tiles(plan[i].ktiles);
+    t.tiles = t.ktiles * t.groups;
+    t.part_off = n_part;
+    n_part += (size_t)t.rows * t.ktiles;
+    t.row0 = n_rows;
+    n_rows += t.rows;
+    t.cost = plan[i].cost * t.ktiles / plan[i].ktiles;
+    plan[i].twin = (int)plan.size();
+    plan[i].pref_row0 = n_rows;
+    n_rows += plan[i].rows;
+    plan.push_back(t);
+  }
+  const uint32_t JT = (uint32_t)plan.size();
   // variants present, items ordered heaviest first
   std::map<int, std::vector<uint32_t>> by_var;
-  for (uint32_t i = 0; i < J; ++i) by_var[plan[i].variant].push_back(i);
+  for (uint32_t i = 0; i < JT; ++i) by_var[plan[i].variant].push_back(i);
   for (auto& kv : by_var)
     std::stable_sort(kv.second.begin(), kv.second.end(), [&](uint32_t x, uint32_t y) { return plan[x].cost > plan[y].cost; });
   const uint32_t NV = (uint32_t)by_var.size();
@@ -114,11 +283,11 @@ int run_batch(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_secon
   // device layout
   size_t off = 0;
   const size_t o_items = off;
-  off = align256(off + (size_t)J * sizeof(qmcd::EvalArgs));
+  off = align256(off + (size_t)JT * sizeof(qmcd::EvalArgs));
   const size_t o_order = off;
-  off = align256(off + (size_t)J * 4);
+  off = align256(off + (size_t)JT * 4);
   const size_t o_prefix = off;
-  off = align256(off + (size_t)(J + NV) * 4);
+  off = align256(off + (size_t)(JT + NV) * 4);
   const size_t o_rows = off;
   off = align256(off + n_rows * sizeof(qmck::RowRef));
   const size_t o_sh = off;
@@ -127,13 +296,13 @@ int run_batch(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_secon
   const size_t o_part = off;
   off = align256(off + n_part * 8);
   const size_t o_out = off;
-  off = align256(off + n_rows * 8 + (size_t)J * 8);
+  off = align256(off + n_rows * 8 + (size_t)JT * 8);
   const size_t o_cnt = off;
   off = align256(off + (size_t)NV * 4);
   char* ws = nullptr;
   int rc = scratch(c, off, &ws);
   if (rc) return rc;
-  rc = stage(c, std::max(upload, n_rows * 8 + (size_t)J * 8));
+  rc = stage(c, std::max(upload, n_rows * 8 + (size_t)JT * 8));
   if (rc) return rc;
   char* h = (char*)c->h_stage;
   std::memset(h, 0, upload);
@@ -144,10 +313,29 @@ int run_batch(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_secon
   double* d_part = (double*)(ws + o_part);
   double* d_out = (double*)(ws + o_out);
   unsigned long long* d_sign = (unsigned long long*)(ws + o_out + n_rows * 8);
-  for (uint32_t i = 0; i < J; ++i) {
-    BatchJob& b = *jobs[i];
+  for (uint32_t i = 0; i < JT; ++i) {
     const Plan& p = plan[i];
+    BatchJob& b = *jobs[p.job];
     qmcd::EvalArgs& a = items[i];
+    if (i >= J) {  // fp64 twin: its job's arguments (already filled) on its own columns
+      a = items[p.job];
+      a.partial = d_part + p.part_off;
+      a.nblocks = p.ktiles;
+      a.ktiles = p.ktiles;
+      a.tile_skip = kFp32SampleEvery - 1;
+      a.tile_first = 0;
+      a.sign_count = d_sign + i;
+      a.item = i;
+      const double* jp = jobs[p.job]->ext_partial ? jobs[p.job]->ext_partial : d_part + plan[p.job].part_off;
+      for (uint32_t r = 0; r < p.rows; ++r) {
+        rows[p.row0 + r].p = d_part + p.part_off + (size_t)r * p.ktiles;
+        rows[p.row0 + r].ncols = p.ktiles;
+        rows[plan[p.job].pref_row0 + r].p = jp + (size_t)r * plan[p.job].ktiles;
+        rows[plan[p.job].pref_row0 + r].ncols = p.ktiles;
+        rows[plan[p.job].pref_row0 + r].skip = kFp32SampleEvery - 1;
+      }
+      continue;
+    }
     int tsel = 0;
     rc = fill_integrand_args(a, b.f, b.t, tsel);
     if (rc) return rc;
@@ -160,17 +348,20 @@ int run_batch(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_secon
     }
     a.m = b.m;
     a.shifts = (const double*)(ws + o_sh) + p.sh_off;
-    a.partial = d_part + p.part_off;
+    double* part = b.ext_partial ? b.ext_partial : d_part + p.part_off;
+    a.partial = part;
     a.nblocks = p.ktiles;
     a.sign_count = d_sign + i;
     a.tile_points = p.tile_points;
     a.ktiles = p.ktiles;
+    a.tile_first = b.tile_count ? b.tile_first : 0;
     a.item = i;
     std::memcpy(shifts + p.sh_off, b.shifts, (size_t)b.m * b.f->dim * 8);
-    for (uint32_t r = 0; r < p.rows; ++r) {
-      rows[p.row0 + r].p = d_part + p.part_off + (size_t)r * p.ktiles;
-      rows[p.row0 + r].ncols = p.ktiles;
-    }
+    if (p.finish)
+      for (uint32_t r = 0; r < p.rows; ++r) {
+        rows[p.row0 + r].p = part + (size_t)r * p.ktiles;
+        rows[p.row0 + r].ncols = p.ktiles;
+      }
   }
   uint32_t* order = (uint32_t*)(h + o_order);
   uint32_t* prefix = (uint32_t*)(h + o_prefix);
@@ -197,7 +388,7 @@ int run_batch(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_secon
       uint32_t i = kv.second[q];
       order[pos + q] = i;
       prefix[ppos + q] = (uint32_t)acc;
-      acc += (uint64_t)plan[i].ktiles * plan[i].groups;
+      acc += plan[i].tiles;
     }
     if (acc >= 0xFFFFFFFFull) return fail(QMC_EINVAL, "batch has more than 2^32 tiles");
     prefix[ppos + L.count] = (uint32_t)acc;
@@ -207,62 +398,90 @@ int run_batch(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_secon
   }
   HIPCHK(hipMemcpyAsync(ws, h, upload, hipMemcpyHostToDevice, c->stream));
 
+  // launch shapes; with the scratch address they fix every kernel argument of
+  // the round (the tables the kernels read are uploaded before each launch)
+  std::vector<uint64_t> sig = {(uint64_t)(uintptr_t)ws, o_items, o_order, o_prefix, o_rows, o_out, o_cnt, JT, NV,
+                               n_rows};
+  std::vector<uint32_t> blocks_of(launches.size());
+  std::vector<int> sv_of(launches.size());
+  for (uint32_t v = 0; v < (uint32_t)launches.size(); ++v) {
+    const Launch& L = launches[v];
+    if (L.jit) {
+      sv_of[v] = 0;
+      blocks_of[v] = (uint32_t)std::max(1, L.jk.occ_batch) * (uint32_t)c->cus;
+    } else {
+      sv_of[v] = L.var.cplx ? 0 : c->batch_sv[L.variant];
+      blocks_of[v] = (uint32_t)std::max(1, qmck::occupancy_batch(L.var, sv_of[v])) * (uint32_t)c->cus;
+    }
+    sig.insert(sig.end(), {(uint64_t)L.variant, L.jit ? (uint64_t)(uintptr_t)L.jk.batch : 0, (uint64_t)sv_of[v],
+                           L.first, L.count, L.prefix_off, blocks_of[v]});
+  }
   auto enqueue = [&](hipStream_t st) -> int {
     HIPCHK(qmck::launch_fill_u32((uint32_t*)(ws + o_cnt), NV, 0u, st));
-    HIPCHK(qmck::launch_fill_u64(d_sign, J, 0ull, st));
+    HIPCHK(qmck::launch_fill_u64(d_sign, JT, 0ull, st));
     for (uint32_t v = 0; v < (uint32_t)launches.size(); ++v) {
       const Launch& L = launches[v];
       if (L.jit) {
-        const uint32_t blocks = (uint32_t)std::max(1, L.jk.occ_batch) * (uint32_t)c->cus;
         HIPCHK(qmcj::launch_batch(L.jk, (const qmcd::EvalArgs*)(ws + o_items), (const uint32_t*)(ws + o_order) + L.first,
                                   (const uint32_t*)(ws + o_prefix) + L.prefix_off, L.count,
-                                  (uint32_t*)(ws + o_cnt) + v, blocks, st));
+                                  (uint32_t*)(ws + o_cnt) + v, blocks_of[v], st));
         continue;
       }
-      const int sv = L.var.cplx ? 0 : c->batch_sv[L.variant];
-      int occ = qmck::occupancy_batch(L.var, sv);
-      uint32_t blocks = (uint32_t)std::max(1, occ) * (uint32_t)c->cus;
-      HIPCHK(qmck::launch_batch(L.var, sv, (const qmcd::EvalArgs*)(ws + o_items),
+      HIPCHK(qmck::launch_batch(L.var, sv_of[v], (const qmcd::EvalArgs*)(ws + o_items),
                                 (const uint32_t*)(ws + o_order) + L.first,
                                 (const uint32_t*)(ws + o_prefix) + L.prefix_off, L.count,
-                                (uint32_t*)(ws + o_cnt) + v, blocks, st));
+                                (uint32_t*)(ws + o_cnt) + v, blocks_of[v], st));
     }
     HIPCHK(qmck::launch_finalize_rows((const qmck::RowRef*)(ws + o_rows), (uint32_t)n_rows, d_out, st));
     return QMC_OK;
   };
 
   if (c->batch_graph) {
-    if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
-    hipGraph_t g = nullptr;
-    HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-    int erc = enqueue(c->cap_stream);
-    hipError_t ec = hipStreamEndCapture(c->cap_stream, &g);
-    if (erc) {
-      if (g) (void)hipGraphDestroy(g);
-      return erc;
-    }
-    if (ec != hipSuccess) return fail(QMC_EDEVICE, "hipStreamEndCapture failed: %s", hipGetErrorString(ec));
+    // a round of the same shape as an earlier one replays that round's graph
     hipGraphExec_t ge = nullptr;
-    hipError_t ei = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (ei != hipSuccess) return fail(QMC_EDEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(ei));
-    // the device interval starts here, after the host has built the graph
-    hipError_t er = hipEventRecord(c->ev0, c->stream);
-    hipError_t el = er != hipSuccess ? er : hipGraphLaunch(ge, c->stream);
-    if (el != hipSuccess) {
-      (void)hipGraphExecDestroy(ge);
-      return fail(QMC_EDEVICE, "hipGraphLaunch failed: %s", hipGetErrorString(el));
+    for (auto& e : c->graphs)
+      if (e.sig == sig) {
+        ge = e.exec;
+        e.last_use = ++c->graph_tick;
+        break;
+      }
+    if (!ge) {
+      if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+      hipGraph_t g = nullptr;
+      HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+      int erc = enqueue(c->cap_stream);
+      hipError_t ec = hipStreamEndCapture(c->cap_stream, &g);
+      if (erc) {
+        if (g) (void)hipGraphDestroy(g);
+        return erc;
+      }
+      if (ec != hipSuccess) return fail(QMC_EDEVICE, "hipStreamEndCapture failed: %s", hipGetErrorString(ec));
+      hipError_t ei = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ei != hipSuccess) return fail(QMC_EDEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(ei));
+      if (c->graphs.size() >= qmc_context::kGraphCache) {
+        auto lru = std::min_element(c->graphs.begin(), c->graphs.end(),
+                                    [](const qmc_context::CachedGraph& x, const qmc_context::CachedGraph& y) {
+                                      return x.last_use < y.last_use;
+                                    });
+        HIPCHK(hipStreamSynchronize(c->stream));  // no replay of it may still be queued
+        (void)hipGraphExecDestroy(lru->exec);
+        c->graphs.erase(lru);
+      }
+      c->graphs.push_back({sig, ge, ++c->graph_tick});
     }
+    // the device interval starts here, after the host has built the graph
+    HIPCHK(hipEventRecord(c->ev0, c->stream));
+    HIPCHK(hipGraphLaunch(ge, c->stream));
     HIPCHK(hipEventRecord(c->ev1, c->stream));
-    HIPCHK(hipMemcpyAsync(c->h_stage, d_out, n_rows * 8 + (size_t)J * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(c->h_stage, d_out, n_rows * 8 + (size_t)JT * 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
-    (void)hipGraphExecDestroy(ge);
   } else {
     HIPCHK(hipEventRecord(c->ev0, c->stream));
     rc = enqueue(c->stream);
     if (rc) return rc;
     HIPCHK(hipEventRecord(c->ev1, c->stream));
-    HIPCHK(hipMemcpyAsync(c->h_stage, d_out, n_rows * 8 + (size_t)J * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(c->h_stage, d_out, n_rows * 8 + (size_t)JT * 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
   }
   float ms = 0;
@@ -271,10 +490,59 @@ int run_batch(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_secon
   const unsigned long long* sg = (const unsigned long long*)(c->h_stage + n_rows);
   for (uint32_t i = 0; i < J; ++i) {
     const Plan& p = plan[i];
-    jobs[i]->sums.assign(c->h_stage + p.row0, c->h_stage + p.row0 + p.rows);
+    if (p.finish)
+      jobs[i]->sums.assign(c->h_stage + p.row0, c->h_stage + p.row0 + p.rows);
+    else
+      jobs[i]->sums.clear();
     jobs[i]->sign_points = sg[i];
+    jobs[i]->fp32_dev.clear();
+    jobs[i]->fp32_ref.clear();
+    jobs[i]->fp32_dev_points = 0;
+    if (p.twin >= 0) {
+      const Plan& t = plan[p.twin];
+      jobs[i]->fp32_dev.resize(p.rows);
+      jobs[i]->fp32_ref.assign(c->h_stage + t.row0, c->h_stage + t.row0 + p.rows);
+      for (uint32_t r = 0; r < p.rows; ++r)
+        jobs[i]->fp32_dev[r] = c->h_stage[p.pref_row0 + r] - c->h_stage[t.row0 + r];
+      uint64_t pts = 0;  // points of the sampled tiles (the last tile may be short)
+      for (uint32_t q = 0; q < t.ktiles; ++q) {
+        const uint64_t k0 = (uint64_t)q * kFp32SampleEvery * t.tile_points;
+        pts += std::min<uint64_t>(t.tile_points, jobs[i]->n - k0);
+      }
+      jobs[i]->fp32_dev_points = pts;
+    }
   }
   return QMC_OK;
+}
+
+}  // namespace
+
+// The fp32 error is taken as relative to the integral: the sample's summed
+// fp32 - fp64 difference over the sample's summed fp64 contribution (complex
+// modulus), times the modulus of the estimate.  A bias of the fp32 polynomials
+// that is a fraction of the integrand is then read off a sample that need not
+// represent the whole cube in value; when the sample is the whole lattice the
+// statement is |Q_fp32 - Q_fp64| up to a relative O(error).  A sample whose
+// fp64 sum vanishes falls back to the mean difference per point.
+void fp32_error(const double* dre, const double* dim, const double* rre, const double* rim, uint32_t m,
+                uint64_t points, qmc_result& r) {
+  double a = 0.0, b = 0.0, fr = 0.0, fi = 0.0;
+  for (uint32_t s = 0; s < m; ++s) {
+    a += dre[s];
+    b += dim[s];
+    fr += rre[s];
+    fi += rim[s];
+  }
+  const double ref = std::hypot(fr, fi);
+  if (ref > 0.0 && std::isfinite(ref)) {
+    const double q = std::hypot(r.re, r.im);
+    r.fp32_err_re = std::fabs(a) / ref * q;
+    r.fp32_err_im = std::fabs(b) / ref * q;
+  } else {
+    const double scale = points ? 1.0 / ((double)m * (double)points) : 0.0;
+    r.fp32_err_re = std::fabs(a) * scale;
+    r.fp32_err_im = std::fabs(b) * scale;
+  }
 }
 
 int run_requests(qmc_context* c, const qmc_request* reqs, uint32_t count, qmc_result* out, double* shift_sums) {
@@ -286,12 +554,18 @@ int run_requests(qmc_context* c, const qmc_request* reqs, uint32_t count, qmc_re
     uint64_t n;
     uint32_t mcur = 0, first_new = 0;  // shifts [first_new, mcur) run next
     std::vector<double> sre, sim;      // per-shift sums at the current lattice
+    std::vector<double> dre, dim_;     // fp32 evaluation: per-shift sampled fp32 - fp64 sums
+    std::vector<double> rre, rim;      // ... and sampled fp64 sums
     uint64_t signs = 0;
     bool done = false;
     qmc_result r{};
     BatchJob job;
   };
   std::vector<St> st(count);
+  // requests usually share generating vectors: each (z, n, dim) is checked once
+  const uint64_t* ok_z = nullptr;
+  uint64_t ok_n = 0;
+  uint32_t ok_dim = 0;
   for (uint32_t i = 0; i < count; ++i) {
     const qmc_request& q = reqs[i];
     if (!q.f) return fail(QMC_EINVAL, "request %u has no integrand", i);
@@ -302,8 +576,13 @@ int run_requests(qmc_context* c, const qmc_request* reqs, uint32_t count, qmc_re
     if (q.m < 1 || q.m > QMC_MAX_SHIFTS) return fail(QMC_EINVAL, "request %u: m=%u", i, q.m);
     const uint32_t dim = s.f->dim;
     if (q.z) {
-      int rc = check_lattice(q.n, dim, q.z);
-      if (rc) return rc;
+      if (!(q.z == ok_z && q.n == ok_n && dim <= ok_dim)) {
+        int rc = check_lattice(q.n, dim, q.z);
+        if (rc) return rc;
+        ok_z = q.z;
+        ok_n = q.n;
+        ok_dim = dim;
+      }
       s.n = q.n;
       s.z.assign(q.z, q.z + dim);
     } else {
@@ -352,6 +631,19 @@ int run_requests(qmc_context* c, const qmc_request* reqs, uint32_t count, qmc_re
       else
         s.sim.resize(m, 0.0);
       s.signs = (s.first_new ? s.signs : 0) + s.job.sign_points;
+      if (!s.job.fp32_dev.empty()) {
+        auto keep = [&](std::vector<double>& re, std::vector<double>& im, const std::vector<double>& rows) {
+          re.resize(s.first_new);
+          im.resize(s.first_new);
+          re.insert(re.end(), rows.begin(), rows.begin() + madd);
+          if (cplx)
+            im.insert(im.end(), rows.begin() + madd, rows.begin() + 2 * (size_t)madd);
+          else
+            im.resize(m, 0.0);
+        };
+        keep(s.dre, s.dim_, s.job.fp32_dev);
+        keep(s.rre, s.rim, s.job.fp32_ref);
+      }
       s.r.iterations += 1;
       s.r.evaluations += s.n * (uint64_t)madd;
       s.r.n = s.n;
@@ -364,6 +656,8 @@ int run_requests(qmc_context* c, const qmc_request* reqs, uint32_t count, qmc_re
         for (uint32_t k = 0; k < m; ++k) qs[k] = s.sim[k] / (double)s.n;
         estimate(qs.data(), m, s.r.im, s.r.err_im);
       }
+      if (!s.job.fp32_dev.empty())
+        fp32_error(s.dre.data(), s.dim_.data(), s.rre.data(), s.rim.data(), m, s.job.fp32_dev_points, s.r);
       s.r.flags &= ~(uint32_t)(QMC_NONFINITE | QMC_DEFORM_SIGN);
       if (s.signs) s.r.flags |= QMC_DEFORM_SIGN;
       if (s.f->has_vr && s.f->vr_fallback) s.r.flags |= QMC_VR_FALLBACK;
@@ -521,7 +815,7 @@ int autotune(qmc_context* c, const qmc_request* reqs, uint32_t count, uint32_t* 
 
 extern "C" int qmc_autotune_batch(qmc_context* c, const qmc_request* reqs, uint32_t count, uint32_t* configs_tried) {
   if (!c || (!reqs && count)) return qmch::fail(QMC_EINVAL, "NULL argument");
-  std::lock_guard<std::recursive_mutex> g(c->mu);
+  CtxLock g(c);
   if (c->broken) return qmch::fail(QMC_EDEVICE, "context is unusable after a device error");
   HIPCHK(hipSetDevice(c->device));
   return qmch::autotune(c, reqs, count, configs_tried);

@@ -214,7 +214,7 @@ extern "C" int qmc_cbc(qmc_context* c, uint64_t n, uint32_t dim, const double* g
   }
   z[0] = 1;
   if (dim == 1) return QMC_OK;
-  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  CtxLock lk(c);
   if (c->broken) return fail(QMC_EDEVICE, "context is unusable after a device error");
   HIPCHK(hipSetDevice(c->device));
   const uint64_t L = n - 1;

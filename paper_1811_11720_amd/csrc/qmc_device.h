@@ -75,6 +75,8 @@ struct EvalArgs {
   uint64_t tile_points;       // batch: points per tile (a multiple of the block size)
   uint32_t ktiles;            // batch: tiles along k (= columns of partial[][])
   uint32_t item;              // batch: index of this integral
+  uint32_t tile_skip;         // batch: column kt holds tile kt * (1 + tile_skip) (0: every tile)
+  uint32_t tile_first;        // batch: the item's tiles this launch covers start at this one
 };
 
 // Where one workgroup's threads sit in the lattice and where their sums go.
@@ -117,8 +119,23 @@ __device__ __forceinline__ uint64_t mulmod_u64(uint64_t a, uint64_t b, uint64_t 
   return r;
 }
 
-__device__ __forceinline__ uint64_t start_index(uint64_t k, uint64_t zj, uint64_t n) {
-  if (n <= 0xFFFFFFFFull && k <= 0xFFFFFFFFull && zj <= 0xFFFFFFFFull) return (k * zj) % n;
+// (a b) mod n for a, b < n <= 2^32, inv = RN(1/n): the quotient from fp64
+// (relative error a few 2^-53, so at most one unit off), the remainder in
+// 64-bit integers (the product is exact; the difference lies in [-n, 2n)).
+__device__ __forceinline__ uint64_t mulmod_32(uint64_t a, uint64_t b, uint64_t n, double inv) {
+  const uint64_t q = (uint64_t)__builtin_floor((double)a * (double)b * inv);
+  long long r = (long long)(a * b - q * n);
+  r = r < 0 ? r + (long long)n : r;
+  r = r >= (long long)n ? r - (long long)n : r;
+  return (uint64_t)r;
+}
+
+// (k z_j) mod n for k <= n, z_j < n; inv = RN(1/n)
+__device__ __forceinline__ uint64_t start_index(uint64_t k, uint64_t zj, uint64_t n, double inv) {
+  if (n <= 0xFFFFFFFFull) {
+    const uint64_t kk = k < n ? k : k - n;
+    return mulmod_32(kk, zj, n, inv);
+  }
   return mulmod_u64(k, zj, n);
 }
 
@@ -521,6 +538,76 @@ __device__ __forceinline__ cplx ldl_det(cplx (&B)[Tri<D>::N]) {
   return det;
 }
 
+// det(I - i lam A) for a real symmetric A (lower triangle, overwritten).
+// Householder reflections reduce A to a tridiagonal T with the same
+// eigenvalues, in real arithmetic (the reflections are orthogonal, so no
+// pivoting is needed and half the registers of a complex factorisation
+// suffice); det(I - i lam T) is then the continuant of its diagonal
+// 1 - i lam T_kk and squared off-diagonal -lam^2 T_{k+1,k}^2.  After step k,
+// A(k+1, k) holds T_{k+1,k}^2 = |column k below the diagonal|^2.
+template <int D>
+__device__ __forceinline__ cplx sym_shift_det(double (&A)[Tri<D>::N], double lam) {
+#pragma unroll
+  for (int k = 0; k + 2 < D; ++k) {
+    double s2 = 0.0;
+#pragma unroll
+    for (int i = k + 2; i < D; ++i) s2 = __builtin_fma(A[Tri<D>::at(i, k)], A[Tri<D>::at(i, k)], s2);
+    const double x0 = A[Tri<D>::at(k + 1, k)];
+    const double nrm2 = __builtin_fma(x0, x0, s2);
+    const double nrm = __builtin_sqrt(nrm2);
+    // v = x + sign(x0) |x| e_1 (no cancellation), H = I - beta v v^T with
+    // beta = 2 / v^T v = 1 / (|x|^2 + |x0| |x|); x = 0 gives H = I
+    const double den = __builtin_fma(__builtin_fabs(x0), nrm, nrm2);
+    const double beta = den > 0.0 ? fast_rcp(den) : 0.0;
+    double v[D], w[D];
+    v[k + 1] = x0 + __builtin_copysign(nrm, x0);
+#pragma unroll
+    for (int i = k + 2; i < D; ++i) v[i] = A[Tri<D>::at(i, k)];
+    A[Tri<D>::at(k + 1, k)] = nrm2;
+    // w = beta A22 v - (beta^2 v^T A22 v / 2) v, A22 = rows and columns k+1..D-1
+#pragma unroll
+    for (int i = k + 1; i < D; ++i) w[i] = A[Tri<D>::at(i, i)] * v[i];
+#pragma unroll
+    for (int i = k + 2; i < D; ++i)
+#pragma unroll
+      for (int j = k + 1; j < i; ++j) {
+        w[i] = __builtin_fma(A[Tri<D>::at(i, j)], v[j], w[i]);
+        w[j] = __builtin_fma(A[Tri<D>::at(i, j)], v[i], w[j]);
+      }
+    double kk = 0.0;
+#pragma unroll
+    for (int i = k + 1; i < D; ++i) {
+      w[i] *= beta;
+      kk = __builtin_fma(v[i], w[i], kk);
+    }
+    kk *= 0.5 * beta;
+#pragma unroll
+    for (int i = k + 1; i < D; ++i) w[i] = __builtin_fma(-kk, v[i], w[i]);
+    // A22 <- H A22 H = A22 - v w^T - w v^T
+#pragma unroll
+    for (int i = k + 1; i < D; ++i)
+#pragma unroll
+      for (int j = k + 1; j <= i; ++j)
+        A[Tri<D>::at(i, j)] = __builtin_fma(-v[i], w[j], __builtin_fma(-w[i], v[j], A[Tri<D>::at(i, j)]));
+  }
+  // D_k = (1 - i lam T_kk) D_{k-1} + lam^2 T_{k,k-1}^2 D_{k-2}, D_{-1} = 1
+  const double l2 = lam * lam;
+  cplx prev = cmk(1.0, 0.0);
+  cplx cur = cmk(1.0, -lam * A[Tri<D>::at(0, 0)]);
+#pragma unroll
+  for (int k = 1; k < D; ++k) {
+    const double t = A[Tri<D>::at(k, k - 1)];
+    const double e2 = (k + 1 < D) ? t : t * t;  // already squared by the reduction except the last one
+    const cplx next = cmul(cmk(1.0, -lam * A[Tri<D>::at(k, k)]), cur);
+    const double q = l2 * e2;
+    prev = cmk(__builtin_fma(q, prev.re, next.re), __builtin_fma(q, prev.im, next.im));
+    const cplx t2 = prev;
+    prev = cur;
+    cur = t2;
+  }
+  return cur;
+}
+
 // f at the deformed point z = x - i lambda x(1-x) grad F(x), times det(dz/dx).
 // Fn provides grad_hess (real, at x) and the polynomials U, F at complex z.
 template <int D, class Fn>
@@ -541,17 +628,17 @@ __device__ __forceinline__ cplx deformed_integrand(const double (&x)[D], const F
     sq[j] = __builtin_sqrt(d2[j]);
     z[j] = cmk(x[j], -lam * d2[j] * g[j]);
   }
-  // B = I - i lambda (S H S + diag((1-2x) g)), S = diag(sqrt(x(1-x))), similar to dz/dx
-  cplx B[Tri<D>::N];
+  // dz/dx is similar to I - i lambda A, A = S H S + diag((1-2x) g) with
+  // S = diag(sqrt(x(1-x))): a real symmetric A, formed in place of H
 #pragma unroll
   for (int i = 0; i < D; ++i)
 #pragma unroll
     for (int j = 0; j <= i; ++j) {
       double A = sq[i] * H[Tri<D>::at(i, j)] * sq[j];
       if (i == j) A = __builtin_fma(__builtin_fma(-2.0, x[i], 1.0), g[i], A);
-      B[Tri<D>::at(i, j)] = cmk(i == j ? 1.0 : 0.0, -lam * A);
+      H[Tri<D>::at(i, j)] = A;
     }
-  cplx det = ldl_det<D>(B);
+  cplx det = sym_shift_det<D>(H, lam);
   return cmul(cscale(a.prefactor, det), fn.uf(z, a, sign));
 }
 
@@ -895,7 +982,7 @@ __device__ __forceinline__ void eval_real_sched(const EvalArgs& a, const Fn& fn,
   uint64_t k = sc.k;
   uint64_t r[DMAX];
 #pragma unroll
-  for (int j = 0; j < DMAX; ++j) r[j] = (j < (int)dim && k < sc.k_end) ? start_index(k, a.z[j], a.n) : 0;
+  for (int j = 0; j < DMAX; ++j) r[j] = (j < (int)dim && k < sc.k_end) ? start_index(k, a.z[j], a.n, a.inv_n) : 0;
 
   for (; k < sc.k_end; k += sc.stride) {
     double q[DMAX];
@@ -1098,7 +1185,7 @@ __device__ __forceinline__ void eval_real_multi_sched(const EvalArgs& a, const S
   uint64_t k = sc.k;
   uint64_t r[DMAX];
 #pragma unroll
-  for (int j = 0; j < DMAX; ++j) r[j] = (j < (int)dim && k < sc.k_end) ? start_index(k, a.z[j], a.n) : 0;
+  for (int j = 0; j < DMAX; ++j) r[j] = (j < (int)dim && k < sc.k_end) ? start_index(k, a.z[j], a.n, a.inv_n) : 0;
 
   for (; k < sc.k_end; k += sc.stride) {
     double q[DMAX];
@@ -1173,7 +1260,7 @@ __device__ __forceinline__ void eval_complex_sched(const EvalArgs& a, const Fn& 
   uint64_t k = sc.k;
   uint64_t r[DMAX];
 #pragma unroll
-  for (int j = 0; j < DMAX; ++j) r[j] = (j < (int)dim && k < sc.k_end) ? start_index(k, a.z[j], a.n) : 0;
+  for (int j = 0; j < DMAX; ++j) r[j] = (j < (int)dim && k < sc.k_end) ? start_index(k, a.z[j], a.n, a.inv_n) : 0;
 
   for (; k < sc.k_end; k += sc.stride) {
     double q[DMAX];
@@ -1246,9 +1333,11 @@ __device__ __forceinline__ void eval_complex_body(const EvalArgs& a, const Fn& f
 // ------------------------------------------------------------------ persistent tile loop of the batch kernels
 // Workgroups pop tile numbers from an atomic counter until the list is
 // exhausted.  Tile t belongs to the item i with prefix[i] <= t < prefix[i+1]
-// (items in `order`, heaviest first); within the item, t - prefix[i] =
-// group * ktiles + kt.  A tile (points [kt*T, kt*T + T), shifts of the group)
-// is summed by one workgroup into column kt of the item's partial[][], so
+// (items in `order`, heaviest first); within the item, t - prefix[i] +
+// tile_first = group * ktiles + kt (a launch may cover a contiguous part of
+// an item's tiles, the rest in other launches).  A tile (points [kt*T, kt*T + T), shifts of the group)
+// is summed by one workgroup into column kt of the item's partial[][] (with
+// tile_skip > 0 column kt holds tile kt (1 + tile_skip): a strided sample), so
 // per-shift sums depend only on the integral's own tiling, never on the rest
 // of the batch.  body(a, sched) evaluates one tile.
 template <int S, class Body>
@@ -1273,9 +1362,9 @@ __device__ __forceinline__ void batch_tiles(const EvalArgs* __restrict__ items, 
         hi = mid;
     }
     const EvalArgs& a = items[order[lo]];
-    const uint32_t local = t - prefix[lo];
+    const uint32_t local = t - prefix[lo] + a.tile_first;
     const uint32_t kt = local % a.ktiles, g = local / a.ktiles;
-    const uint64_t k0 = (uint64_t)kt * a.tile_points;
+    const uint64_t k0 = (uint64_t)kt * (1u + a.tile_skip) * a.tile_points;
     Sched sc;
     sc.k = k0 + threadIdx.x;
     sc.k_end = (k0 + a.tile_points < a.n) ? k0 + a.tile_points : a.n;
@@ -1313,7 +1402,7 @@ __device__ __forceinline__ void hist_body(const EvalArgs& a, const HistArgs& h) 
 #pragma unroll
     for (int j = 0; j < DMAX; ++j) {
       if (j < (int)dim) {
-        double q = exact_quotient((double)start_index(k, a.z[j], a.n), a.n_d, a.inv_n);
+        double q = exact_quotient((double)start_index(k, a.z[j], a.n, a.inv_n), a.n_d, a.inv_n);
         x[j] = shifted(q, D[j]);
       } else {
         x[j] = 0.0;

@@ -34,7 +34,8 @@ struct qmc_context {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::map<uint64_t, std::vector<uint64_t>> lattices;  // guarded by lat_mu
   std::mutex lat_mu;                                  // innermost lock
-  std::recursive_mutex mu;
+  std::recursive_mutex mu;                            // taken through CtxLock
+  std::atomic<int> lock_waiters{0};                   // threads waiting in CtxLock
   int inflight = 0;
   int live_integrands = 0;  // the context is freed only after its last integrand
   std::atomic<bool> closing{false};  // destroy requested while integrands were alive
@@ -56,11 +57,36 @@ struct qmc_context {
   uint64_t batch_tile[qmck::BATCH_VARIANTS] = {};  // minimum points per tile (0 = the default)
   std::string tune_cache;             // file the autotuner reads and appends
   hipStream_t cap_stream = nullptr;   // private stream used only for graph capture
+  // instantiated graphs of recent batch rounds, keyed by every launch argument
+  struct CachedGraph {
+    std::vector<uint64_t> sig;
+    hipGraphExec_t exec;
+    uint64_t last_use;
+  };
+  static constexpr size_t kGraphCache = 16;
+  std::vector<CachedGraph> graphs;
+  uint64_t graph_tick = 0;
   // serving
   std::atomic<qmc_serve_state*> serve{nullptr};     // scheduler, created by the first qmc_submit
   size_t serve_mem_limit = (size_t)8 << 30;  // device bytes admitted requests may use
   uint64_t serve_max_n = (1ull << 31) - 1;   // growth stops above this lattice size
+  double serve_round_cost = 0x1p39;          // cost units (evaluations x per-evaluation weight) per serving round
   uint64_t build_max_n = 0;  // > 0: the growth loop builds missing lattices up to this size (qmc_cbc)
+};
+
+// The context lock for API calls.  The serving scheduler takes the lock for
+// every round and lets the threads counted here in before its next round, so
+// calls made while requests are being served wait for at most one round.
+struct CtxLock {
+  qmc_context* c;
+  explicit CtxLock(qmc_context* ctx) : c(ctx) {
+    c->lock_waiters.fetch_add(1, std::memory_order_acq_rel);
+    c->mu.lock();
+    c->lock_waiters.fetch_sub(1, std::memory_order_acq_rel);
+  }
+  ~CtxLock() { c->mu.unlock(); }
+  CtxLock(const CtxLock&) = delete;
+  CtxLock& operator=(const CtxLock&) = delete;
 };
 
 struct qmc_integrand {
@@ -154,9 +180,38 @@ struct BatchJob {
   uint32_t m = 0;
   const double* shifts = nullptr;  // [m][dim]
   qmc_transform t{};
-  std::vector<double> sums;  // out: rows (m or 2m)
-  uint64_t sign_points = 0;  // out
+  // in: evaluate only the tiles [tile_first, tile_first + tile_count) of the
+  // job's tiling (tile_count 0: all of them) into ext_partial (rows x ktiles
+  // doubles of device memory the caller keeps across calls; nullptr: batch
+  // scratch); the sums are produced only with `finish` set, by the call that
+  // evaluates the last of the tiles (calls run in order on one stream)
+  uint32_t tile_first = 0, tile_count = 0;
+  double* ext_partial = nullptr;
+  bool finish = true;
+  std::vector<double> sums;  // out: rows (m or 2m), when finished
+  uint64_t sign_points = 0;  // out: points of this call's tiles with Im F(z) > 0
+  // out, QMC_EVAL_FP32 jobs: per row, over a sample of the lattice's points
+  // (every kFp32SampleEvery-th tile), the sum of the fp32-evaluated
+  // contributions minus the fp64-evaluated ones, the sum of the fp64-evaluated
+  // ones, and the sample's size
+  std::vector<double> fp32_dev, fp32_ref;
+  uint64_t fp32_dev_points = 0;
 };
+// Tiles of an fp32 job that are also evaluated in fp64 to estimate the fp32
+// error: tiles 0, 16, 32, ... of its ktiles tiles, ceil(ktiles / 16) of them.
+constexpr uint32_t kFp32SampleEvery = 16;
+inline uint32_t batch_fp32_sample_tiles(uint32_t ktiles) { return (ktiles + kFp32SampleEvery - 1) / kFp32SampleEvery; }
+// Tiling of a batch job as run_batch lays it out: kernel variant (or the
+// integrand's specialised batch kernel), points per tile, tiles along k,
+// shift groups (tiles in all: ktiles x groups) and rows (m or 2m).
+struct BatchShape {
+  qmck::BatchVariant var;
+  bool use_jit = false;
+  qmcj::Kernel jk;
+  uint64_t tile_points = 0;
+  uint32_t ktiles = 0, groups = 0, rows = 0;
+};
+int batch_job_shape(qmc_context* c, const BatchJob& b, BatchShape& sh);
 // Points per tile of a batch job of n points: the variant's tuned minimum
 // (0 = the default for real or complex jobs), at least n / batch_max_ktiles,
 // rounded up to whole blocks.  A job's tiling depends only on this.
@@ -164,7 +219,12 @@ uint64_t batch_tile_points(const qmc_context* c, uint64_t tuned, bool cplx, uint
 // Most tiles any schedule can give a job of n points.
 uint64_t batch_ktiles_bound(const qmc_context* c, uint64_t n);
 // Upper bound of the batch scratch one job of `rows` rows and `ktiles` tiles takes.
-size_t batch_job_bytes(size_t rows, uint64_t ktiles, uint32_t m, uint32_t dim);
+size_t batch_job_bytes(size_t rows, uint64_t ktiles, uint32_t m, uint32_t dim, bool fp32);
+// fp32_err_re/im of a result (its estimate already set) from the per-shift
+// sampled sums of fp32 - fp64 contributions (dre, dim) and of fp64
+// contributions (rre, rim) over `points` points.
+void fp32_error(const double* dre, const double* dim, const double* rre, const double* rim, uint32_t m,
+                uint64_t points, qmc_result& r);
 // Evaluate all jobs with the persistent batch kernels (one round).
 int run_batch(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_seconds);
 // Requests through rounds of run_batch (growth loop per request).

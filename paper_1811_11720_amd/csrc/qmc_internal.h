@@ -86,10 +86,11 @@ int occupancy_batch(const BatchVariant& v, int sv);
 hipError_t launch_batch(const BatchVariant& v, int sv, const qmcd::EvalArgs* items, const uint32_t* order,
                         const uint32_t* prefix, uint32_t nitems, uint32_t* counter, uint32_t blocks, hipStream_t st);
 
-// Sums rows of per-item partial arrays in a fixed order: out[r] = sum_c rows[r].p[c].
+// Sums rows of per-item partial arrays in a fixed order:
+// out[r] = sum_{c < ncols} rows[r].p[c (1 + skip)].
 struct RowRef {
   const double* p;
-  uint32_t ncols, pad;
+  uint32_t ncols, skip;
 };
 hipError_t launch_finalize_rows(const RowRef* rows, uint32_t nrows, double* out, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t count, uint32_t v, hipStream_t st);

@@ -109,7 +109,7 @@ __global__ __launch_bounds__(QMCD_BLOCK) void k_finalize_rows(const RowRef* __re
                                                               double* __restrict__ out) {
   const RowRef r = rows[blockIdx.x];
   double t = 0.0;
-  for (uint32_t i = threadIdx.x; i < r.ncols; i += QMCD_BLOCK) t += r.p[i];
+  for (uint32_t i = threadIdx.x; i < r.ncols; i += QMCD_BLOCK) t += r.p[(size_t)i * (1u + r.skip)];
   t = qmcd::wave_sum(t);
   __shared__ double red[QMCD_BLOCK / 64];
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
@@ -156,6 +156,7 @@ hipError_t launch_batch(const BatchVariant& v, int sv, const qmcd::EvalArgs* ite
 
 struct IndexArgs {
   uint64_t n, k0, count, stride;
+  double inv_n;
   uint32_t dim, idx32;
   uint64_t z[QMCD_MAXD];
   uint64_t step[QMCD_MAXD];
@@ -167,7 +168,7 @@ __global__ __launch_bounds__(QMCD_BLOCK) void k_indices(IndexArgs a) {
   uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= a.count || t >= a.stride) return;
   uint64_t r[QMCD_MAXD];
-  for (uint32_t j = 0; j < a.dim; ++j) r[j] = qmcd::start_index(a.k0 + t, a.z[j], a.n);
+  for (uint32_t j = 0; j < a.dim; ++j) r[j] = qmcd::start_index(a.k0 + t, a.z[j], a.n, a.inv_n);
   for (uint64_t i = t; i < a.count; i += a.stride) {
     for (uint32_t j = 0; j < a.dim; ++j) {
       a.out[i * a.dim + j] = r[j];
@@ -188,6 +189,7 @@ hipError_t launch_indices(uint64_t n, uint32_t dim, const uint64_t* z_host, uint
   a.k0 = k0;
   a.count = count;
   a.stride = threads;
+  a.inv_n = 1.0 / (double)n;
   a.dim = dim;
   a.idx32 = n <= (1ull << 31) ? 1u : 0u;
   for (uint32_t j = 0; j < dim; ++j) {

@@ -138,7 +138,7 @@ extern "C" int qmc_integrate_noalloc(qmc_context* c, const qmc_integrand* f, uin
     return fail(QMC_EUNSUPPORTED, "fp32 evaluation runs only in the batch kernels (qmc_integrate_batch)");
   int rc = qmch::check_lattice(n, dim, z);
   if (rc) return rc;
-  std::lock_guard<std::recursive_mutex> g(c->mu);
+  CtxLock g(c);
   if (c->closing) return fail(QMC_EINVAL, "context has been destroyed");
   if (c->broken) return fail(QMC_EDEVICE, "context is unusable after a device error");
   rc = integrate_noalloc(c, f, dim, n, z, m, seed, t, out, shift_sums);

@@ -281,13 +281,15 @@ int plan_lattice(qmc_context* c, qmc_integrand* f, uint64_t n, const uint64_t* z
   p.tsel = tsel;
   p.use_jit = false;
   int S = cplx ? qmck::S_COMPLEX : qmck::S_REAL;
-  if (!f->genz && c->jit && npts * (uint64_t)m >= c->jit_min_evals) {
+  if (!f->genz && c->jit) {
+    // an integrand's specialised kernel, once compiled, runs all its jobs;
+    // compiling one (seconds) pays only for large jobs
     const int jkey = tsel * 2 + (f->has_vr ? 1 : 0);
     auto it = f->jit.find(jkey);
     if (it != f->jit.end()) {
       p.jk = it->second;
       p.use_jit = true;
-    } else if (may_compile && specialised_kernel(c, f, tsel, &p.jk) == 0) {
+    } else if (may_compile && npts * (uint64_t)m >= c->jit_min_evals && specialised_kernel(c, f, tsel, &p.jk) == 0) {
       p.use_jit = true;
     }
     if (p.use_jit) S = cplx ? qmck::S_COMPLEX_JIT : c->jit_S;
@@ -756,6 +758,8 @@ void free_context(qmc_context* c) {
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
+  for (auto& e : c->graphs) (void)hipGraphExecDestroy(e.exec);
+  c->graphs.clear();
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
 }
@@ -810,6 +814,7 @@ int qmc_context_create(int device, void* hip_stream, void* workspace, size_t wor
   }
   if (const char* v = std::getenv("QMC_BATCH_GRAPH")) c->batch_graph = atoi(v) != 0;
   if (const char* v = std::getenv("QMC_SERVE_MEM")) c->serve_mem_limit = (size_t)strtoull(v, nullptr, 10);
+  if (const char* v = std::getenv("QMC_SERVE_ROUND_COST")) c->serve_round_cost = std::max(1.0, atof(v));
   int force_sv = -1;
   if (const char* v = std::getenv("QMC_BATCH_SV")) force_sv = atoi(v);  // one points-per-decode variant for all
   for (int dc = 0; dc < 4; ++dc)
@@ -843,7 +848,7 @@ int qmc_context_create(int device, void* hip_stream, void* workspace, size_t wor
 int qmc_context_destroy(qmc_context* c) {
   if (!c) return QMC_OK;
   {
-    std::lock_guard<std::recursive_mutex> g(c->mu);
+    CtxLock g(c);
     int inflight = serve_inflight(c);
     if (inflight) return fail(QMC_EBUSY, "context has %d submitted tickets in flight", inflight);
     if (c->live_integrands > 0) {
@@ -859,7 +864,7 @@ int qmc_context_destroy(qmc_context* c) {
 int qmc_set_lattice_builder(qmc_context* c, uint64_t max_n) {
   if (!c) return fail(QMC_EINVAL, "context is NULL");
   if (max_n >= (1ull << 31)) return fail(QMC_EINVAL, "max_n must be below 2^31");
-  std::lock_guard<std::recursive_mutex> g(c->mu);
+  CtxLock g(c);
   c->build_max_n = max_n;
   return QMC_OK;
 }
@@ -909,7 +914,7 @@ int qmc_create_integrand(qmc_context* c, const qmc_integrand_desc* d, qmc_integr
   size_t b_expo = ((size_t)nm * 8 + 255) & ~(size_t)255;
   size_t b_vr = ((size_t)d->dim * 6 * 8 + 255) & ~(size_t)255;
   size_t b_c32 = ((size_t)nm * 4 + 255) & ~(size_t)255;
-  std::lock_guard<std::recursive_mutex> g(c->mu);
+  CtxLock g(c);
   (void)hipSetDevice(c->device);
   hipError_t e = hipMalloc((void**)&f->dmem, b_coef + b_expo + b_vr + b_c32);
   if (e != hipSuccess) {
@@ -956,7 +961,7 @@ int qmc_create_genz(qmc_context* c, int family, uint32_t dim, const double* cv, 
     tab.push_back(family == 2 ? 1.0 / (cv[j] * cv[j]) : family == 4 ? cv[j] * cv[j] : 0.0);
   const size_t b_coef = (tab.size() * 8 + 255) & ~(size_t)255;
   const size_t b_vr = ((size_t)dim * 6 * 8 + 255) & ~(size_t)255;
-  std::lock_guard<std::recursive_mutex> g(c->mu);
+  CtxLock g(c);
   (void)hipSetDevice(c->device);
   hipError_t e = hipMalloc((void**)&f->dmem, b_coef + b_vr);
   if (e != hipSuccess) {
@@ -982,7 +987,7 @@ int qmc_destroy_integrand(qmc_integrand* f) {
   qmc_context* c = f->ctx;
   bool last = false;
   {
-    std::lock_guard<std::recursive_mutex> g(c->mu);
+    CtxLock g(c);
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     if (f->dmem) (void)hipFree(f->dmem);
@@ -1008,7 +1013,7 @@ int qmc_set_vr(qmc_integrand* f, const double* params) {
     if (p[0] < 1.001 || p[1] > -0.001)
       return fail(QMC_EINVAL, "VR poles of dim %u inside (-0.001, 1.001): p0=%g p1=%g", j, p[0], p[1]);
   }
-  std::lock_guard<std::recursive_mutex> g(f->ctx->mu);
+  CtxLock g(f->ctx);
   f->vr.assign(params, params + 6 * f->dim);
   f->vr_fallback = 0;
   (void)hipSetDevice(f->ctx->device);
@@ -1034,7 +1039,7 @@ int qmc_integrate(qmc_context* c, const qmc_integrand* f, uint32_t dim, uint64_t
   q.abs_tol = 0;
   q.errormode = QMC_ERRMODE_LARGEST;
   q.max_evals = 0;
-  std::lock_guard<std::recursive_mutex> g(c->mu);
+  CtxLock g(c);
   if (c->closing) return fail(QMC_EINVAL, "context has been destroyed");
   if (c->broken) return fail(QMC_EDEVICE, "context is unusable after a device error");
   HIPCHK(hipSetDevice(c->device));
@@ -1046,7 +1051,7 @@ int qmc_integrate(qmc_context* c, const qmc_integrand* f, uint32_t dim, uint64_t
 
 int qmc_integrate_request(qmc_context* c, const qmc_request* q, qmc_result* out, double* shift_sums) {
   if (!c || !q || !q->f) return fail(QMC_EINVAL, "NULL context, request or integrand");
-  std::lock_guard<std::recursive_mutex> g(c->mu);
+  CtxLock g(c);
   if (c->closing) return fail(QMC_EINVAL, "context has been destroyed");
   if (c->broken) return fail(QMC_EDEVICE, "context is unusable after a device error");
   HIPCHK(hipSetDevice(c->device));
@@ -1058,7 +1063,7 @@ int qmc_integrate_request(qmc_context* c, const qmc_request* q, qmc_result* out,
 int qmc_integrate_batch(qmc_context* c, const qmc_request* reqs, uint32_t count, qmc_result* out,
                         double* shift_sums) {
   if (!c || (!reqs && count)) return fail(QMC_EINVAL, "NULL argument");
-  std::lock_guard<std::recursive_mutex> g(c->mu);
+  CtxLock g(c);
   if (c->broken) return fail(QMC_EDEVICE, "context is unusable after a device error");
   HIPCHK(hipSetDevice(c->device));
   int rc = run_requests(c, reqs, count, out, shift_sums);
@@ -1080,7 +1085,7 @@ int qmc_lattice_indices(qmc_context* c, uint64_t n, uint32_t dim, const uint64_t
   if (rc) return rc;
   if (k0 > n || count > n - k0) return fail(QMC_EINVAL, "range [k0, k0+count) exceeds n");
   if (count == 0) return QMC_OK;
-  std::lock_guard<std::recursive_mutex> g(c->mu);
+  CtxLock g(c);
   HIPCHK(hipSetDevice(c->device));
   char* ws = nullptr;
   size_t bytes = (size_t)count * dim * 8;
@@ -1103,7 +1108,7 @@ int qmc_shift_sums_range(qmc_context* c, const qmc_integrand* f, uint64_t n, con
   if (rc) return rc;
   if (k0 > k1 || k1 > n) return fail(QMC_EINVAL, "range [%llu, %llu) outside [0, n)", (unsigned long long)k0,
                                      (unsigned long long)k1);
-  std::lock_guard<std::recursive_mutex> g(c->mu);
+  CtxLock g(c);
   if (c->broken) return fail(QMC_EDEVICE, "context is unusable after a device error");
   HIPCHK(hipSetDevice(c->device));
   std::vector<double> sh((size_t)m * f->dim);
@@ -1153,7 +1158,7 @@ int qmc_histogram(qmc_context* c, const qmc_integrand* f, uint64_t n, const uint
   if (n >= (1ull << 53)) return fail(QMC_EINVAL, "n too large");
   int rc = check_lattice(n, f->dim, z);
   if (rc) return rc;
-  std::lock_guard<std::recursive_mutex> g(c->mu);
+  CtxLock g(c);
   if (c->broken) return fail(QMC_EDEVICE, "context is unusable after a device error");
   HIPCHK(hipSetDevice(c->device));
   std::vector<double> h;

@@ -35,6 +35,12 @@ struct Req {
   qmc_result r{};
   qmch::BatchJob job;
   size_t bytes = 0;
+  // progress on the current lattice when it is evaluated over several rounds
+  uint32_t tiles_total = 0, tiles_done = 0;  // tiles_total 0: the lattice has not started
+  double tile_cost = 0.0;                     // cost units of one tile
+  double* d_part = nullptr;                   // its tile partials, kept between rounds
+  size_t part_bytes = 0;
+  uint64_t lat_signs = 0;                     // points with Im F(z) > 0 so far on this lattice
 };
 
 struct Ticket {
@@ -60,6 +66,7 @@ struct qmc_serve_state {
   std::map<uint64_t, std::shared_ptr<Ticket>> all;
   size_t in_use = 0;
   uint64_t rounds = 0;
+  std::vector<double*> to_free;  // partial buffers of finished requests, freed before the next round
 };
 
 namespace qmch {
@@ -80,7 +87,7 @@ static size_t request_bytes(const qmc_integrand* f, uint64_t n, uint32_t m, cons
   const bool cplx = (f->flags & QMC_DEFORM) != 0;
   const uint64_t kt = batch_ktiles_bound(c, n);
   const size_t rows = cplx ? 2 * (size_t)m : m;
-  return batch_job_bytes(rows, kt, m, f->dim);
+  return batch_job_bytes(rows, kt, m, f->dim, (f->flags & QMC_EVAL_FP32) != 0);
 }
 
 static void release(qmc_serve_state* s, Ticket& t, size_t bytes) {
@@ -89,15 +96,76 @@ static void release(qmc_serve_state* s, Ticket& t, size_t bytes) {
   s->in_use -= bytes;
 }
 
+static void drop_partials(qmc_serve_state* s, Req& r) {
+  if (r.d_part) s->to_free.push_back(r.d_part);
+  r.d_part = nullptr;
+  r.part_bytes = 0;
+}
+
 static void finish_ticket(qmc_serve_state* s, Ticket& t, int status) {
   t.finished = true;
   t.status = status;
-  for (auto& r : t.reqs) r.f->refs -= 1;
+  for (auto& r : t.reqs) {
+    r.f->refs -= 1;
+    drop_partials(s, r);
+  }
   release(s, t, t.held);  // nothing is held by a ticket that was never admitted
   s->cv_done.notify_all();
 }
 
+// Cost units of one evaluation of f (the batch planner's ordering weight).
+static double eval_cost(const qmc_integrand* f) {
+  double cst = (double)(f->n_u + f->n_f) * f->dim + 10.0 * f->dim;
+  if (f->flags & QMC_DEFORM) cst = cst * 6.0 + 2.0 * f->dim * f->dim * f->dim;
+  return cst;
+}
+
+// The part of a request's current lattice that runs this round: all of it
+// when it fits its share of the round's cost budget (or the context has a
+// caller-owned workspace), else the next tiles that fit (at least one), with
+// the tile partials in a buffer kept until the lattice is done.
+static int plan_slice(qmc_context* c, qmc_serve_state* s, Req& r, double share) {
+  BatchJob& j = r.job;
+  j.tile_first = 0;
+  j.tile_count = 0;
+  j.ext_partial = nullptr;
+  j.finish = true;
+  if (r.tiles_total == 0) {
+    BatchShape sh;
+    int rc = batch_job_shape(c, j, sh);
+    if (rc) return rc;
+    const uint32_t S = (r.f->flags & QMC_DEFORM) ? qmck::S_COMPLEX : qmck::S_REAL;
+    r.tiles_total = sh.ktiles * sh.groups;
+    r.tiles_done = 0;
+    r.lat_signs = 0;
+    r.tile_cost = (double)sh.tile_points * std::min<uint32_t>(S, r.q.m) * eval_cost(r.f);
+    const double whole = (double)r.n * r.q.m * eval_cost(r.f);
+    if (whole <= share || !c->own_ws || r.tiles_total == 1) {
+      r.tiles_total = 0;  // one round: no state kept
+      return QMC_OK;
+    }
+    const size_t need = (size_t)sh.rows * sh.ktiles * sizeof(double);
+    if (need > r.part_bytes) {
+      if (r.d_part) HIPCHK(hipFree(r.d_part));
+      r.d_part = nullptr;
+      r.part_bytes = 0;
+      hipError_t e = hipMalloc((void**)&r.d_part, need);
+      if (e != hipSuccess) return fail(QMC_ENOMEM, "hipMalloc(%zu) for tile partials: %s", need, hipGetErrorString(e));
+      r.part_bytes = need;
+    }
+  }
+  const uint32_t left = r.tiles_total - r.tiles_done;
+  const double fit = std::floor(share / std::max(r.tile_cost, 1.0));
+  const uint32_t take = (uint32_t)std::max(1.0, std::min((double)left, fit));
+  j.tile_first = r.tiles_done;
+  j.tile_count = take;
+  j.ext_partial = r.d_part;
+  j.finish = take == left;
+  return QMC_OK;
+}
+
 static void scheduler(qmc_context* c, qmc_serve_state* s) {
+  (void)hipSetDevice(c->device);
   std::unique_lock<std::mutex> lk(s->mu);
   for (;;) {
     // admission: arrival order, while the memory budget allows
@@ -130,7 +198,10 @@ static void scheduler(qmc_context* c, qmc_serve_state* s) {
       s->cv_work.wait(lk);
       continue;
     }
-    // one round over every unfinished request of the admitted tickets
+    // one round over every unfinished request of the admitted tickets: each
+    // gets about an equal share of the round's cost budget (its whole current
+    // lattice when that fits, else the next slice of its tiles), so rounds,
+    // and with them the wait of a ticket that arrives meanwhile, stay bounded
     std::vector<BatchJob*> jobs;
     std::vector<std::pair<Ticket*, Req*>> refs;
     for (auto& t : s->active)
@@ -145,12 +216,25 @@ static void scheduler(qmc_context* c, qmc_serve_state* s) {
           jobs.push_back(&r.job);
           refs.push_back({t.get(), &r});
         }
+    std::vector<double*> frees;
+    frees.swap(s->to_free);
     lk.unlock();
     double ks = 0.0;
-    int rc;
+    int rc = QMC_OK;
     {
+      // API calls waiting for the context go first: they wait at most one round
+      for (int spin = 0; c->lock_waiters.load(std::memory_order_acquire) > 0; ++spin) {
+        if (spin < 64)
+          std::this_thread::yield();
+        else
+          std::this_thread::sleep_for(std::chrono::microseconds(50));
+      }
       std::lock_guard<std::recursive_mutex> g(c->mu);
-      rc = c->broken ? QMC_EDEVICE : run_batch(c, jobs, &ks);
+      for (double* q : frees) (void)hipFree(q);
+      const double share = c->serve_round_cost / (double)std::max<size_t>(1, refs.size());
+      for (auto& pr : refs)
+        if (rc == QMC_OK) rc = plan_slice(c, s, *pr.second, share);
+      if (rc == QMC_OK) rc = c->broken ? QMC_EDEVICE : run_batch(c, jobs, &ks);
       if (rc == QMC_EDEVICE) c->broken = true;
     }
     lk.lock();
@@ -165,10 +249,16 @@ static void scheduler(qmc_context* c, qmc_serve_state* s) {
       Ticket& tk = *pr.first;
       const bool cplx = (r.f->flags & QMC_DEFORM) != 0;
       const uint32_t m = r.q.m;
+      r.r.device_seconds += ks;
+      r.lat_signs += r.job.sign_points;
+      if (r.tiles_total) {  // a lattice evaluated over several rounds
+        r.tiles_done += r.job.tile_count;
+        if (!r.job.finish) continue;
+        r.tiles_total = 0;
+      }
       r.r.iterations += 1;
       r.r.evaluations += r.n * (uint64_t)m;
       r.r.n = r.n;
-      r.r.device_seconds += ks;
       std::vector<double> qs(m);
       for (uint32_t k = 0; k < m; ++k) qs[k] = r.job.sums[k] / (double)r.n;
       estimate(qs.data(), m, r.r.re, r.r.err_re);
@@ -177,20 +267,28 @@ static void scheduler(qmc_context* c, qmc_serve_state* s) {
         for (uint32_t k = 0; k < m; ++k) qs[k] = r.job.sums[m + k] / (double)r.n;
         estimate(qs.data(), m, r.r.im, r.r.err_im);
       }
+      if (!r.job.fp32_dev.empty()) {
+        const std::vector<double> zero(m, 0.0);
+        fp32_error(r.job.fp32_dev.data(), cplx ? r.job.fp32_dev.data() + m : zero.data(), r.job.fp32_ref.data(),
+                   cplx ? r.job.fp32_ref.data() + m : zero.data(), m, r.job.fp32_dev_points, r.r);
+      }
       r.r.flags &= ~(uint32_t)(QMC_NONFINITE | QMC_DEFORM_SIGN);
-      if (r.job.sign_points) r.r.flags |= QMC_DEFORM_SIGN;
+      if (r.lat_signs) r.r.flags |= QMC_DEFORM_SIGN;
+      r.lat_signs = 0;
       if (r.f->has_vr && r.f->vr_fallback) r.r.flags |= QMC_VR_FALLBACK;
       const bool finite = std::isfinite(r.r.re) && std::isfinite(r.r.im);
       if (!finite) r.r.flags |= QMC_NONFINITE;
       const bool grow = r.q.rel_tol > 0 || r.q.abs_tol > 0;
       if (!grow) {
         r.done = true;
+        drop_partials(s, r);
         release(s, tk, r.bytes);
         continue;
       }
       if (finite && goal_met(r.r, r.q.rel_tol, r.q.abs_tol, r.q.errormode, cplx)) {
         r.r.flags |= QMC_CONVERGED;
         r.done = true;
+        drop_partials(s, r);
         release(s, tk, r.bytes);
         continue;
       }
@@ -200,6 +298,7 @@ static void scheduler(qmc_context* c, qmc_serve_state* s) {
       if (g.kind != GrowthStep::LATTICE) {
         r.r.flags |= QMC_MAXEVAL_HIT;
         r.done = true;
+        drop_partials(s, r);
         release(s, tk, r.bytes);
         continue;
       }
@@ -236,6 +335,11 @@ void serve_shutdown(qmc_context* c) {
   }
   s->cv_work.notify_all();
   if (s->thr.joinable()) s->thr.join();
+  (void)hipSetDevice(c->device);
+  for (double* q : s->to_free) (void)hipFree(q);
+  for (auto& kv : s->all)
+    for (auto& r : kv.second->reqs)
+      if (r.d_part) (void)hipFree(r.d_part);
   delete s;
   c->serve = nullptr;
 }

@@ -45,8 +45,8 @@ def test_header_constants_match_binding():
 
 
 def test_result_struct_layout():
-    # 4 doubles, u64, 2 u32, u64, 2 u32, u64, 3 doubles
-    assert C.sizeof(Q.Result) == 4 * 8 + 8 + 8 + 8 + 8 + 8 + 3 * 8
+    # 4 doubles, u64, 2 u32, u64, 2 u32, u64, 3 doubles, 2 doubles
+    assert C.sizeof(Q.Result) == 4 * 8 + 8 + 8 + 8 + 8 + 8 + 3 * 8 + 2 * 8
 
 
 @pytest.mark.parametrize("seed,m,d", [(0, 1, 1), (7, 32, 6), (2 ** 63 + 5, 10, 3), (123, 64, 16)])

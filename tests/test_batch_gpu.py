@@ -108,6 +108,51 @@ def test_fp32_evaluation_error_is_small_and_reported(ctx):
             assert np.all(np.abs(r["sums_im"] - o.im) <= 2e-5 * o.abs_im + 1e-300)
 
 
+def test_fp32_error_statement_matches_the_oracle():
+    """Each fp32-evaluated result states its error, from an fp64 evaluation
+    of a sample of its points (the first tiles).  When the sample is the
+    whole lattice (one tile) the statement is exactly |Q_fp32 - Q_fp64| up to
+    rounding, so it matches the distance to the oracle's mean; with 16 or
+    more tiles it is an estimate from a sixteenth of the points, checked to
+    bound the real distance within a factor 4 (plus 1e-13 of the mean
+    |w f|); fp64 results state 0."""
+    c = _ctx(True)
+    cases = [(1009, 5), (4099, 9), (100003, 2), (1000003, 4)]
+    jobs, fs = [], []
+    for i, (n, m) in enumerate(cases):
+        for cx in (False, True):
+            dim = 3 + i
+            desc = W.sector(900 + 10 * i + cx, dim, 3, 6, -2.0, -1.5, complex_=cx, lam=0.5)
+            desc.fp32 = True
+            z = W.z_for(n, dim) if n in W.lattice_table() else cbc.fast_cbc(n, dim)
+            jobs.append(W.Job(desc, n, z, m, seed=40 + i, transform=KOR3))
+    res = _run(c, jobs, fs)
+    for j, r in zip(jobs, res):
+        sh = oracle.shifts(j.seed, j.m, j.desc.dim)
+        o = oracle.shift_sums(j.desc, j.n, j.z, j.m, sh, j.transform, threads=THREADS)
+        true_re = abs(np.mean(r["sums_re"] - o.re)) / j.n
+        scale = np.mean(o.abs_re) / j.n
+        if j.n <= 4096:  # one tile: the sample is the lattice
+            assert abs(r["fp32_err_re"] - true_re) <= 2e-12 * scale, (j.n, r["fp32_err_re"], true_re)
+        else:
+            assert true_re <= 4.0 * r["fp32_err_re"] + 1e-13 * scale, (j.n, r["fp32_err_re"], true_re)
+        assert r["fp32_err_re"] <= 1e-5 * scale
+        if j.desc.deform:
+            true_im = abs(np.mean(r["sums_im"] - o.im)) / j.n
+            sc_im = np.mean(o.abs_im) / j.n
+            if j.n <= 4096:
+                assert abs(r["fp32_err_im"] - true_im) <= 2e-12 * sc_im
+            else:
+                assert true_im <= 4.0 * r["fp32_err_im"] + 1e-13 * sc_im
+    fp64 = copy.copy(jobs[0].desc)
+    fp64.fp32 = False
+    r64 = _run(c, [W.Job(fp64, jobs[0].n, jobs[0].z, jobs[0].m, seed=jobs[0].seed, transform=KOR3)], fs)[0]
+    assert r64["fp32_err_re"] == 0.0 and r64["fp32_err_im"] == 0.0
+    for h in fs:
+        h.close()
+    c.close()
+
+
 def test_batched_growth_matches_oracle(ctx):
     table_ns = [cbc.next_prime(v) for v in (1000, 2000, 4000, 8000, 16000, 32000, 64000, 128000)]
     zs = {n: cbc.fast_cbc(n, 3) for n in table_ns}
@@ -259,4 +304,85 @@ def test_specialised_batch_matches_oracle_alone_and_in_a_mix():
         assert np.array_equal(a["sums_re"], b["sums_re"]) and np.array_equal(a["sums_im"], b["sums_im"])
     for f in keep:
         f.close()
+    c.close()
+
+
+def test_replicas_of_one_lattice_share_an_item_and_keep_their_sums():
+    """Real requests on one integrand, lattice and transform with different
+    seeds and shift counts run as one item with the shifts concatenated:
+    each request's sums are bitwise those it gets alone, and match the
+    oracle; a complex request on the same lattice is not merged."""
+    c = _ctx(True)
+    job = W.job_plain_product()
+    f = c.integrand(job.desc)
+    cx = W.sector(seed=31, dim=3, n_u=2, n_f=4, pow_u=-1.0, pow_f=-1.5, complex_=True, lam=0.5)
+    fc = c.integrand(cx)
+    other = W.sector(seed=32, dim=3, n_u=2, n_f=5, pow_u=-2.0, pow_f=-1.0)
+    fo = c.integrand(other)
+    ms = [10, 3, 8, 1, 17, 10, 9]
+    reqs = [dict(f=f, n=job.n, z=job.z, m=m, seed=500 + i, transform=job.transform) for i, m in enumerate(ms)]
+    reqs.insert(3, dict(f=fo, n=job.n, z=job.z, m=5, seed=77, transform=job.transform))
+    reqs.insert(5, dict(f=f, n=job.n, z=job.z, m=4, seed=78, transform=(W.T_BAKER, 0, 0)))  # another transform
+    reqs.append(dict(f=fc, n=job.n, z=job.z, m=6, seed=79, transform=job.transform))
+    mixed = c.integrate_batch(reqs, sums=True)
+    for r, g in zip(reqs, mixed):
+        alone = c.integrate_batch([r], sums=True)[0]
+        assert np.array_equal(alone["sums_re"], g["sums_re"]) and np.array_equal(alone["sums_im"], g["sums_im"])
+        assert alone["re"] == g["re"] and alone["err_re"] == g["err_re"]
+    for k in (0, 4, 7):
+        r = reqs[k]
+        desc = job.desc if r["f"] is f else other
+        o = oracle.shift_sums(desc, job.n, job.z, r["m"], oracle.shifts(r["seed"], r["m"], 3), r["transform"],
+                              threads=THREADS)
+        _check_sums(mixed[k]["sums_re"], o, label=f"replica {k}")
+    for h in (f, fc, fo):
+        h.close()
+    c.close()
+
+
+def test_cached_graph_replays_with_eager_work_between():
+    """Rounds of one shape replay one instantiated graph: three replays, with
+    single-integral launches and a differently shaped batch in between,
+    each bitwise equal to the batch run without graphs."""
+    jobs = _mix(10, 14)
+    eager_ctx = _ctx(False)
+    eager = _run(eager_ctx, jobs)
+    eager_ctx.close()
+    c = _ctx(True)
+    keep = []
+    fs = [c.integrand(j.desc) for j in jobs]
+    reqs = [dict(f=f, n=j.n, z=j.z, m=j.m, seed=j.seed, transform=j.transform) for f, j in zip(fs, jobs)]
+    pj = W.job_plain_product()
+    fp = c.integrand(pj.desc)
+    for rep in range(3):
+        g = c.integrate_batch(reqs, sums=True)
+        for a, b in zip(eager, g):
+            assert np.array_equal(a["sums_re"], b["sums_re"]) and np.array_equal(a["sums_im"], b["sums_im"]), rep
+        c.integrate(fp, pj.n, pj.z, pj.m, pj.seed + rep, pj.transform)
+        _run(c, _mix(3, 20 + rep), keep)
+    for h in fs + keep + [fp]:
+        h.close()
+    c.close()
+
+
+def test_single_jobs_use_an_integrands_compiled_kernel_at_any_size():
+    """Once a large job has compiled the integrand's specialised kernel,
+    smaller single jobs of that integrand run in it too (path 1) and still
+    match the oracle."""
+    import paper_1811_11720_amd as Q
+
+    c = Q.Context(0)
+    job = W.job_sector_real(W.SECTOR_REAL_NS[-2])
+    f = c.integrand(job.desc)
+    small = c.integrate(f, 100003, W.z_for(100003, 6), 8, 9, job.transform, sums=True)
+    assert small["path"] == 0
+    big = c.integrate(f, job.n, job.z, job.m, job.seed, job.transform)
+    assert big["path"] == 1
+    again = c.integrate(f, 100003, W.z_for(100003, 6), 8, 9, job.transform, sums=True)
+    assert again["path"] == 1
+    o = oracle.shift_sums(job.desc, 100003, W.z_for(100003, 6), 8, oracle.shifts(9, 8, 6), job.transform,
+                          threads=THREADS)
+    _check_sums(again["sums_re"], o, label="small after compile")
+    _check_sums(small["sums_re"], o, label="small before compile")
+    f.close()
     c.close()

@@ -25,5 +25,5 @@ def test_specialised_source_compiles(case):
     elif case == "large_polynomial":  # more terms than the exhaustive split search takes at once
         desc, tr = W.random_real_small(seed=5, dim=12, n_u=20, n_f=60), (W.T_SIDI, 3, 0)
     else:
-        desc, tr = W.sector_complex(seed=3), KOR3
+        desc, tr = W.sector_complex(), KOR3
     assert Q.specialize_check(desc, tr) > 1000

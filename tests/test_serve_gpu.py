@@ -100,23 +100,76 @@ def test_growth_requests_meet_their_goals_and_match_the_oracle(ctx):
     assert abs(q - res[j]["re"]) <= 1e-12 * np.mean(o.abs_re) / n * 16 + 1e-15
 
 
-def test_late_arrivals_join_while_others_run(ctx):
+def _round_ctx(cost):
+    old = os.environ.get("QMC_SERVE_ROUND_COST")
+    os.environ["QMC_SERVE_ROUND_COST"] = str(cost)
+    try:
+        return _serve_ctx()
+    finally:
+        if old is None:
+            os.environ.pop("QMC_SERVE_ROUND_COST", None)
+        else:
+            os.environ["QMC_SERVE_ROUND_COST"] = old
+
+
+def test_late_arrivals_join_while_others_run():
+    """Rounds are bounded: with a small per-round cost budget the large
+    lattices of a first ticket are evaluated a slice of tiles per round, so a
+    small ticket submitted while they run joins the next rounds, shares them
+    and finishes first.  The sliced evaluation gives bitwise the per-shift
+    results of the unsliced batch path."""
+    c = _round_ctx(2 ** 30)
     keep = []
     big = W.batch_mix(count=6, seed=34, n_lo=1e6, n_hi=2e6, m=32)
     big_reqs = []
     for j in big:
-        f = ctx.integrand(j.desc)
+        f = c.integrand(j.desc)
         keep.append(f)
         big_reqs.append(dict(f=f, n=j.n, z=j.z, m=j.m, seed=j.seed, transform=j.transform))
-    t_big = ctx.submit(big_reqs)
-    time.sleep(0.01)
-    small = _requests(ctx, 3, 35, keep=keep)
-    t_small = ctx.submit(small)
-    r_small = ctx.wait(t_small, len(small), timeout=300)
-    r_big = ctx.wait(t_big, len(big_reqs), timeout=300)
-    assert r_small is not None and r_big is not None
-    st = ctx.serve_stats()
-    assert st["queued"] == 0 and st["active"] == 0 and st["bytes_in_use"] == 0 and st["rounds"] >= 1
+    t_big = c.submit(big_reqs)
+    time.sleep(0.05)
+    r0 = c.serve_stats()["rounds"]
+    small = _requests(c, 3, 35, keep=keep)
+    t_small = c.submit(small)
+    r_small = c.wait(t_small, len(small), timeout=300)
+    assert r_small is not None
+    still = c.poll(t_big, len(big_reqs))
+    assert still is None, "the large ticket finished before the small one"
+    r_big = c.wait(t_big, len(big_reqs), timeout=300)
+    st = c.serve_stats()
+    assert st["queued"] == 0 and st["active"] == 0 and st["bytes_in_use"] == 0
+    assert st["rounds"] - r0 >= 10  # the large lattices ran over many rounds
+    direct = c.integrate_batch(big_reqs) + c.integrate_batch(small)
+    for a, b in zip(r_big + r_small, direct):
+        assert a["re"] == b["re"] and a["im"] == b["im"] and a["err_re"] == b["err_re"] and a["err_im"] == b["err_im"]
+        assert a["evaluations"] == b["evaluations"] and a["iterations"] == 1
+    # the small ticket waited for at most a few of the bounded rounds
+    assert max(x["queue_seconds"] for x in r_small) < 1.0
+    for f in keep:
+        f.close()
+    c.close()
+
+
+def test_sliced_growth_matches_the_unsliced_loop():
+    """Requests that grow through the table with a round budget far below
+    one lattice: same visited lattices, evaluations and estimates as with
+    unbounded rounds."""
+    keep = []
+    a = _round_ctx(2 ** 26)
+    b = _round_ctx(2 ** 60)
+    res = []
+    for c in (a, b):
+        reqs = _requests(c, 6, 37, rel=1e-7, keep=keep)
+        t = c.submit(reqs)
+        res.append(c.wait(t, len(reqs), timeout=300))
+    for x, y in zip(*res):
+        for k in ("re", "im", "err_re", "err_im", "n", "iterations", "evaluations", "flags"):
+            assert x[k] == y[k], k
+    assert a.serve_stats()["rounds"] > b.serve_stats()["rounds"]
+    for f in keep:
+        f.close()
+    a.close()
+    b.close()
 
 
 def test_memory_admission_queues_and_rejects():
