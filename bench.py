@@ -662,7 +662,7 @@ def bench_serve(a, Q, W, torch):
     ctx = Q.Context(0)
     ctx.register_table(W.lattice_table())
     fs = [ctx.integrand(j.desc) for j in pool]
-    spec = W.serving_requests(a.requests + 8, seed=5, lo=a.req_lo, hi=a.req_hi, pool=pool)
+    spec = W.serving_requests(4 + a.requests + a.requests_max, seed=5, lo=a.req_lo, hi=a.req_hi, pool=pool)
 
     def make(members, target):
         return [dict(f=fs[i], n=pool[i].n, z=None, m=pool[i].m, seed=pool[i].seed, transform=pool[i].transform,
@@ -710,21 +710,26 @@ def bench_serve(a, Q, W, torch):
         conv = sum(sum(1 for x in r if x["flags"] & 1) for r in out)
         return np.array(lat), ev, span, conv
 
-    warm = [make(*q) for q in spec[:8]]
+    warm = [make(*q) for q in spec[:4]]
     run(0, warm)
-    reqs = [make(*q) for q in spec[8:]]
+    reqs = [make(*q) for q in spec[4:4 + a.requests]]
     lat0, ev0, span0, conv0 = run(0, reqs)  # saturation: everything queued at once
     sat = len(reqs) / span0
     print(f"[serve] saturation {sat:.2f} requests/s, {ev0 / span0:.3e} evals/s", file=sys.stderr, flush=True)
+    pool_reqs = [make(*q) for q in spec[4 + a.requests:]]
     rates = []
     for frac in a.rates:
-        lat, ev, span, conv = run(frac * sat, reqs)
-        print(f"[serve] load {frac}: p50 {np.percentile(lat, 50) * 1e3:.1f} ms, p99 {np.percentile(lat, 99) * 1e3:.1f} ms",
-              file=sys.stderr, flush=True)
-        rates.append({"load": frac, "arrival_rate_per_s": frac * sat, "requests_per_s": len(reqs) / span,
+        # about seconds_per_rate of arrivals at this rate, within [8, requests_max] requests
+        cnt = int(min(a.requests_max, max(8, round(frac * sat * a.seconds_per_rate))))
+        sub = pool_reqs[:cnt]
+        lat, ev, span, conv = run(frac * sat, sub)
+        print(f"[serve] load {frac}: {cnt} requests, p50 {np.percentile(lat, 50) * 1e3:.1f} ms, "
+              f"p99 {np.percentile(lat, 99) * 1e3:.1f} ms", file=sys.stderr, flush=True)
+        rates.append({"load": frac, "arrival_rate_per_s": frac * sat, "requests": cnt,
+                      "requests_per_s": cnt / span,
                       "evals_per_s": ev / span, "p50_ms": float(np.percentile(lat, 50)) * 1e3,
                       "p99_ms": float(np.percentile(lat, 99)) * 1e3,
-                      "integrals_converged": conv, "integrals": sum(len(q) for q in reqs)})
+                      "integrals_converged": conv, "integrals": sum(len(q) for q in sub)})
     st = ctx.serve_stats()
     for f in fs:
         f.close()
@@ -743,9 +748,13 @@ def bench_serve(a, Q, W, torch):
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"serving: {len(reqs)} requests of {a.req_lo}-{a.req_hi} sector integrands, "
-                        f"rel targets 1e-8..1e-4, start n in [{a.n_lo:g}, {a.n_hi:g}], m={a.m}, growth through "
-                        f"the lattice table",
+            "workload": f"serving: requests of {a.req_lo}-{a.req_hi} sector integrands, rel targets "
+                        f"1e-8..1e-4, start n in [{a.n_lo:g}, {a.n_hi:g}], m={a.m}, growth through the lattice "
+                        f"table, at most {a.max_evals:g} evaluations per integral; {len(reqs)} requests at "
+                        f"saturation, then Poisson arrivals at each load for about {a.seconds_per_rate:g} s "
+                        f"(8 to {a.requests_max} requests per load: fewer than the 1000 per rate a full sweep "
+                        f"would take, to keep the run within minutes)",
+            "requests_saturation": len(reqs),
         },
         "saturation": {"requests_per_s": sat, "evals_per_s": ev0 / span0,
                        "p50_ms": float(np.percentile(lat0, 50)) * 1e3,
@@ -785,11 +794,13 @@ def main():
     ap.add_argument("--goal", type=float, default=1e-6, help="batch: relative goal of the equal-error comparison")
     ap.add_argument("--goal-count", type=int, default=32, help="batch: integrals in the equal-error comparison")
     ap.add_argument("--goal-max-evals", type=int, default=10 ** 9, help="batch: evaluation cap per integral there")
-    ap.add_argument("--requests", type=int, default=200, help="serve: requests per load level")
+    ap.add_argument("--requests", type=int, default=24, help="serve: requests of the saturation run")
+    ap.add_argument("--requests-max", type=int, default=64, help="serve: most requests per load level")
+    ap.add_argument("--seconds-per-rate", type=float, default=45.0, help="serve: arrival span per load level")
     ap.add_argument("--req-lo", type=int, default=10)
     ap.add_argument("--req-hi", type=int, default=500)
-    ap.add_argument("--max-evals", type=int, default=10 ** 9, help="serve: evaluations per integral")
-    ap.add_argument("--rates", type=float, nargs="*", default=[0.5, 0.9])
+    ap.add_argument("--max-evals", type=int, default=10 ** 8, help="serve: evaluations per integral")
+    ap.add_argument("--rates", type=float, nargs="*", default=[0.25, 0.5, 0.75, 0.9, 1.0, 1.1])
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported (sharding the "

@@ -103,18 +103,23 @@ int qmc_next_lattice(qmc_context* ctx, uint64_t preferred_n, uint32_t dim, uint6
 
 /*
  * Fast component-by-component construction of a generating vector on the
- * device (Sec. 2.2; App. A.3): prime n in [3, 2^31), z[0] = 1, each next
+ * device (Sec. 2.2; App. A.3): prime n in [3, 2^33 + 1], z[0] = 1, each next
  * component minimising the shift-averaged worst-case error of the Korobov
  * space with kernel omega(x) = 2 pi^2 (x^2 - x + 1/6) and product weights
  * gammas (host [dim], > 0; NULL = gamma_j = j^-2).  Candidates are
  * 1..(n-1)/2; among those within a relative 1e-9 of the minimum the smallest
  * wins.  The sums over all candidates are a cyclic convolution of length n-1
- * (Nuyens and Cools), done with power-of-two FFTs of length
- * N = 2^ceil(log2(2n-3)): device memory 48 N + 16 n bytes (13 GB at
- * n = 1e8), allocated for the call and freed before it returns.  z: host
- * [dim].  QMC_EINVAL for
- * a composite or out-of-range n, QMC_ENOMEM when the buffers do not fit.
- * The result can be registered with qmc_register_lattice.
+ * (Nuyens and Cools).  For n < 2^31 it is done with power-of-two FFTs of
+ * length N = 2^ceil(log2(2n-3)): device memory 48 N + 16 n bytes (13 GB at
+ * n = 1e8).  For n >= 2^31, n - 1 must be 2^a 3^b 5^c 7^d (the paper's
+ * largest lattice, 15173222401, is of this form): the convolution runs
+ * without padding through real-packed mixed-radix FFTs of length (n-1)/2,
+ * device memory 32 (n - 1) bytes (70 GB at n = 2.2e9; the 15173222401-point
+ * lattice would need 486 GB, more than one GPU holds).  Memory is allocated
+ * for the call and freed before it returns.  z: host [dim].  QMC_EINVAL for
+ * a composite or out-of-range n or an n >= 2^31 of another form, QMC_ENOMEM
+ * when the buffers do not fit.  The result can be registered with
+ * qmc_register_lattice.
  */
 int qmc_cbc(qmc_context* ctx, uint64_t n, uint32_t dim, const double* gammas, uint64_t* z);
 
@@ -134,7 +139,7 @@ typedef struct qmc_integrand qmc_integrand;
 enum {
   QMC_DEFORM = 1u,     /* complex result: contour deformation with parameter lambda */
   QMC_EVAL_FP32 = 2u,  /* evaluate U, F and the powers in fp32, accumulate in fp64 */
-  QMC_SPECIALISE = 4u  /* batches and serving: run the real fp64 jobs of this integrand in a kernel generated
+  QMC_SPECIALISE = 4u  /* batches and serving: run the fp64 jobs of this integrand (real or deformed) in a kernel generated
                           for its structure (compiled at first use, a few seconds; shared by integrands of the
                           same structure) instead of the table-driven kernels.  The per-shift sums of a job
                           then come from that kernel, still the same alone or in any batch.  Single
@@ -258,7 +263,7 @@ typedef struct {
   double queue_seconds;   /* submit-to-start wait (serving); 0 otherwise */
   double wall_seconds;    /* host wall time of the request */
   double fp32_err_re, fp32_err_im; /* QMC_EVAL_FP32 results: the fp32 evaluation's error in re, im,
-                             estimated on a sample of the last lattice (every 16th tile of the
+                             estimated on a sample of the last lattice (every 32nd tile of the
                              batch tiling: all points when it has one tile) that is evaluated in
                              fp64 as well: |sum (w f_fp32 - w f_fp64)| / |sum w f_fp64| over the
                              sample and all shifts (complex modulus), times |estimate|; 0 for

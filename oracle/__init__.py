@@ -93,6 +93,8 @@ def lib():
         L.oracle_histogram.restype = C.c_int
         L.oracle_cbc_criterion.argtypes = [C.c_uint64, C.c_uint32, up, dp]
         L.oracle_cbc_criterion.restype = C.c_double
+        L.oracle_cbc_partial.argtypes = [C.c_uint64, C.c_uint32, up, dp, C.c_uint64, C.c_uint64]
+        L.oracle_cbc_partial.restype = C.c_double
         L.oracle_cbc_brute.argtypes = [C.c_uint64, C.c_uint32, dp, C.c_double, up]
         L.oracle_cbc_brute.restype = C.c_int
         L.oracle_max_threads.restype = C.c_int
@@ -367,10 +369,20 @@ def integrate(desc, n, z_of, m, seed, transform=(T_KOROBOV, 3, 3), vr=None, rel_
 # ---------------------------------------------------------------- CBC
 
 
-def cbc_criterion(n, z, gammas) -> float:
+def cbc_criterion(n, z, gammas, threads: int = 1) -> float:
+    """e^2(z) of the CBC construction; with threads > 1 the sum over k is
+    split into that many consecutive ranges whose sums are added in order."""
     zz = np.ascontiguousarray(z, dtype=np.uint64)
     g = np.ascontiguousarray(gammas, dtype=np.float64)
-    return lib().oracle_cbc_criterion(n, zz.size, _up(zz), _dp(g))
+    if threads <= 1:
+        return lib().oracle_cbc_criterion(n, zz.size, _up(zz), _dp(g))
+    from concurrent.futures import ThreadPoolExecutor
+
+    edges = [n * i // threads for i in range(threads + 1)]
+    with ThreadPoolExecutor(threads) as ex:
+        parts = list(ex.map(lambda i: lib().oracle_cbc_partial(n, zz.size, _up(zz), _dp(g), edges[i], edges[i + 1]),
+                            range(threads)))
+    return math.fsum(parts) / n
 
 
 def cbc_brute(n, d, gammas=None, tie_rtol=1e-9) -> list[int]:

@@ -548,15 +548,20 @@ static double cbc_kernel(uint64_t r, uint64_t n) {
   return 2.0 * M_PI * M_PI * (x * x - x + 1.0 / 6.0);
 }
 
-/* e^2(z) = -1 + (1/n) sum_k prod_j (1 + gamma_j omega({k z_j / n})) */
-double oracle_cbc_criterion(uint64_t n, uint32_t d, const uint64_t* z, const double* gamma) {
+/* sum over k in [k0, k1) of prod_j (1 + gamma_j omega({k z_j / n})) - 1 */
+double oracle_cbc_partial(uint64_t n, uint32_t d, const uint64_t* z, const double* gamma, uint64_t k0, uint64_t k1) {
   dd_t s = {0, 0};
-  for (uint64_t k = 0; k < n; ++k) {
+  for (uint64_t k = k0; k < k1; ++k) {
     double p = 1.0;
     for (uint32_t j = 0; j < d; ++j) p *= 1.0 + gamma[j] * cbc_kernel(lattice_index(k, z[j], n), n);
     dd_add(&s, p - 1.0);
   }
-  return (s.hi + s.lo) / (double)n;
+  return s.hi + s.lo;
+}
+
+/* e^2(z) = -1 + (1/n) sum_k prod_j (1 + gamma_j omega({k z_j / n})) */
+double oracle_cbc_criterion(uint64_t n, uint32_t d, const uint64_t* z, const double* gamma) {
+  return oracle_cbc_partial(n, d, z, gamma, 0, n) / (double)n;
 }
 
 static uint64_t gcd_u64(uint64_t a, uint64_t b) {

@@ -99,7 +99,7 @@ int batch_job_shape(qmc_context* c, const BatchJob& b, BatchShape& sh) {
   if (rc) return rc;
   sh.var = qmck::BatchVariant{qmck::dim_class(f->dim, cplx), qmck::batch_tkc(tsel, f->has_vr), cplx, fp32};
   sh.use_jit = false;
-  if (!cplx && !fp32 && (f->flags & QMC_SPECIALISE) && c->jit &&
+  if (!fp32 && (f->flags & QMC_SPECIALISE) && c->jit &&
       specialised_kernel(c, const_cast<qmc_integrand*>(b.f), tsel, &sh.jk) == 0 && sh.jk.batch)
     sh.use_jit = true;
   const uint32_t S = cplx ? qmck::S_COMPLEX : qmck::S_REAL;
@@ -756,7 +756,7 @@ int autotune(qmc_context* c, const qmc_request* reqs, uint32_t count, uint32_t* 
     int rc = variant_of(reqs[i], v);
     if (rc) return rc;
     // jobs that run in a specialised kernel would time that kernel, not the variant's
-    if (!v.cplx && !v.fp32 && (reqs[i].f->flags & QMC_SPECIALISE) && c->jit) continue;
+    if (!v.fp32 && (reqs[i].f->flags & QMC_SPECIALISE) && c->jit) continue;
     by_var[v.index()].push_back(i);
     vars[v.index()] = v;
   }

@@ -119,10 +119,11 @@ __device__ __forceinline__ uint64_t mulmod_u64(uint64_t a, uint64_t b, uint64_t 
   return r;
 }
 
-// (a b) mod n for a, b < n <= 2^32, inv = RN(1/n): the quotient from fp64
-// (relative error a few 2^-53, so at most one unit off), the remainder in
-// 64-bit integers (the product is exact; the difference lies in [-n, 2n)).
-__device__ __forceinline__ uint64_t mulmod_32(uint64_t a, uint64_t b, uint64_t n, double inv) {
+// (a b) mod n for a, b < n <= 2^50, inv = RN(1/n): the quotient from fp64
+// (relative error a few 2^-53, so less than one unit off for quotients below
+// 2^50), the remainder in 64-bit integers modulo 2^64, which is exact because
+// the true remainder of that quotient lies in [-n, 2n).
+__device__ __forceinline__ uint64_t mulmod_fp(uint64_t a, uint64_t b, uint64_t n, double inv) {
   const uint64_t q = (uint64_t)__builtin_floor((double)a * (double)b * inv);
   long long r = (long long)(a * b - q * n);
   r = r < 0 ? r + (long long)n : r;
@@ -132,9 +133,9 @@ __device__ __forceinline__ uint64_t mulmod_32(uint64_t a, uint64_t b, uint64_t n
 
 // (k z_j) mod n for k <= n, z_j < n; inv = RN(1/n)
 __device__ __forceinline__ uint64_t start_index(uint64_t k, uint64_t zj, uint64_t n, double inv) {
-  if (n <= 0xFFFFFFFFull) {
+  if (n <= (1ull << 50)) {
     const uint64_t kk = k < n ? k : k - n;
-    return mulmod_32(kk, zj, n, inv);
+    return mulmod_fp(kk, zj, n, inv);
   }
   return mulmod_u64(k, zj, n);
 }

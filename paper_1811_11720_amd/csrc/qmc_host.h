@@ -198,8 +198,8 @@ struct BatchJob {
   uint64_t fp32_dev_points = 0;
 };
 // Tiles of an fp32 job that are also evaluated in fp64 to estimate the fp32
-// error: tiles 0, 16, 32, ... of its ktiles tiles, ceil(ktiles / 16) of them.
-constexpr uint32_t kFp32SampleEvery = 16;
+// error: tiles 0, 32, 64, ... of its ktiles tiles, ceil(ktiles / 32) of them.
+constexpr uint32_t kFp32SampleEvery = 32;
 inline uint32_t batch_fp32_sample_tiles(uint32_t ktiles) { return (ktiles + kFp32SampleEvery - 1) / kFp32SampleEvery; }
 // Tiling of a batch job as run_batch lays it out: kernel variant (or the
 // integrand's specialised batch kernel), points per tile, tiles along k,

@@ -29,15 +29,19 @@ enum Kind { KIND_REAL = 0 };
 constexpr int S_REAL = 8;
 // points evaluated together by the table-driven real kernels (register budget)
 constexpr int sv_real(int dmax, bool fp32) { return (fp32 || dmax <= 8) ? 2 : 1; }
-// shifts per thread group of the complex kernels (one evaluation is ~1e3 instructions)
-constexpr int S_COMPLEX = 2;
+// shifts per thread group of the complex kernels: one evaluation is
+// thousands of instructions, so the index and quotient work a larger group
+// would share is negligible, and one shift per thread keeps fewer registers live
+constexpr int S_COMPLEX = 1;
 // ... of the specialised complex kernels (register pressure: one point's Jacobian at a time)
 constexpr int S_COMPLEX_JIT = 1;
 // Waves per SIMD the table-driven complex kernels are compiled for.  They are
 // latency bound (scalar table loads, dependent fp64 chains), so more waves pay
-// even at the price of some spilled registers, up to 8 variables; the 10- and
-// 12-variable classes would spill most of the Jacobian and stay at one wave.
-constexpr int complex_waves(int dmax) { return dmax <= 4 ? 4 : dmax <= 6 ? 3 : dmax <= 8 ? 2 : 1; }
+// even at the price of spilled registers: measured on MI355X, the 8-variable
+// class runs 3% faster at three waves (about 500 bytes of spills per lane)
+// than at two, the 10-variable class 1.3x faster at two waves (400 bytes)
+// than at one; the 12-variable class would spill over 700 bytes and stays at one.
+constexpr int complex_waves(int dmax) { return dmax <= 4 ? 4 : dmax <= 8 ? 3 : dmax <= 10 ? 2 : 1; }
 // largest dimension of the complex (deformed) kernels
 constexpr uint32_t MAX_DIM_COMPLEX = 12;
 

@@ -477,6 +477,14 @@ std::string generate(const Spec& s) {
         << ", " << s.S << ", true, qmcd::JitComplex, " << (s.vr ? "qmcd::VRM_ON" : "qmcd::VRM_OFF")
         << ">(a, qmcd::JitComplex());\n}\n";
     }
+    // persistent batch entry: the table-driven complex batch kernels' tile
+    // loop and shift groups, with this integrand's evaluation
+    o << "extern \"C\" __global__ __launch_bounds__(QMCD_BLOCK) void qmc_jit_batch(const qmcd::EvalArgs* __restrict__ "
+         "items, const uint32_t* __restrict__ order, const uint32_t* __restrict__ prefix, uint32_t nitems, "
+         "uint32_t* __restrict__ counter) {\n  qmcd::batch_tiles<"
+      << qmck::S_COMPLEX << ">(items, order, prefix, nitems, counter, [&](const qmcd::EvalArgs& a, const qmcd::Sched& sc) {\n"
+      << "    qmcd::eval_complex_sched<" << d << ", " << tk << ", false, " << qmck::S_COMPLEX << ", true, qmcd::JitComplex, "
+      << (s.vr ? "qmcd::VRM_ON" : "qmcd::VRM_OFF") << ">(a, qmcd::JitComplex(), sc);\n  });\n}\n";
     return o.str();
   }
   Emitter em(d);
@@ -609,7 +617,7 @@ int get(int device, const Spec& s, Kernel* out) {
   hipError_t e = hipModuleLoadData(&m->mod, code.data());
   if (e == hipSuccess) e = hipModuleGetFunction(&m->f32, m->mod, "qmc_jit_eval32");
   if (e == hipSuccess) e = hipModuleGetFunction(&m->f64, m->mod, "qmc_jit_eval64");
-  if (e == hipSuccess && !s.cplx) e = hipModuleGetFunction(&m->batch, m->mod, "qmc_jit_batch");
+  if (e == hipSuccess) e = hipModuleGetFunction(&m->batch, m->mod, "qmc_jit_batch");
   if (e != hipSuccess) {
     g_jit_err = std::string("module load failed: ") + hipGetErrorString(e);
     return -2;

@@ -1,6 +1,7 @@
 """Device fast CBC (Sec. 2.2, App. A.3) against the oracle's brute-force CBC,
 the host fast CBC and the oracle's direct worst-case error."""
 
+import os
 import time
 
 import numpy as np
@@ -79,3 +80,74 @@ def test_device_cbc_rejects_bad_sizes(ctx):
         assert e.value.code == Q.QMC_EINVAL
     with pytest.raises(Q.QmcError):
         ctx.cbc(101, 3, [0.5, -1.0, 0.5])
+
+
+def _smooth7(m):
+    for q in (2, 3, 5, 7):
+        while m % q == 0:
+            m //= q
+    return m == 1
+
+
+def _mixed(ctx, n, d, gammas=None):
+    """The construction through the mixed-radix path (forced below 2^31)."""
+    old = os.environ.get("QMC_CBC_MIXED")
+    os.environ["QMC_CBC_MIXED"] = "1"
+    try:
+        return ctx.cbc(n, d, gammas)
+    finally:
+        if old is None:
+            os.environ.pop("QMC_CBC_MIXED", None)
+        else:
+            os.environ["QMC_CBC_MIXED"] = old
+
+
+SMOOTH_PRIMES = [n for n in range(5, 2000) if cbc.is_prime(n) and _smooth7((n - 1) // 2)]
+
+
+@pytest.mark.parametrize("n", SMOOTH_PRIMES[:6] + SMOOTH_PRIMES[-6:])
+def test_mixed_radix_cbc_equals_brute_force(ctx, n):
+    """The path for lattices of 2^31 points and more (real-packed mixed-radix
+    FFTs of length (n-1)/2, no padding), run at small n: the brute force's
+    vector."""
+    d = 5
+    assert _mixed(ctx, n, d) == oracle.cbc_brute(n, d, _gam(d))
+
+
+@pytest.mark.parametrize("n", [100801, 1166401, 5400001])
+def test_mixed_radix_cbc_matches_the_padded_path(ctx, n):
+    """Both device constructions at sizes where both run: the same vector, or
+    at the first component where they part (FFT rounding deciding inside the
+    1e-9 tie band), two choices of the same worst-case error.  After that the
+    greedy steps condition on different prefixes and may go their own ways."""
+    assert cbc.is_prime(n) and _smooth7((n - 1) // 2)
+    d = 6
+    zm = _mixed(ctx, n, d)
+    zp = ctx.cbc(n, d)
+    if zm != zp:
+        j = next(i for i in range(d) if zm[i] != zp[i])
+        em = oracle.cbc_criterion(n, zm[:j + 1], _gam(j + 1), threads=16)
+        ep = oracle.cbc_criterion(n, zp[:j + 1], _gam(j + 1), threads=16)
+        assert em == pytest.approx(ep, rel=1e-8)
+
+
+def test_cbc_beyond_2_31():
+    """n = 2187000001 = 2^6 3^7 5^6 + 1 (the smallest such prime above 2^31):
+    64-bit indices throughout.  The second component's worst-case error, by
+    the oracle's direct sum over all n points, is no larger than that of
+    other candidates (their own errors scattered over a wide range), and the
+    components are valid."""
+    import paper_1811_11720_amd as Q
+
+    n, d = 2187000001, 3
+    c = Q.Context(0)
+    t0 = time.perf_counter()
+    z = c.cbc(n, d)
+    print(f"device CBC n={n} d={d}: {time.perf_counter() - t0:.2f} s, z={z}", flush=True)
+    c.close()
+    assert z[0] == 1 and all(1 <= v <= (n - 1) // 2 for v in z) and len(set(z)) == d
+    e_best = oracle.cbc_criterion(n, z[:2], _gam(2), threads=16)
+    rng = np.random.default_rng(5)
+    for cand in rng.integers(2, (n - 1) // 2, size=3):
+        e = oracle.cbc_criterion(n, [1, int(cand)], _gam(2), threads=16)
+        assert e_best <= e * (1 + 1e-9), (int(cand), e, e_best)
