@@ -332,12 +332,15 @@ int qmc_integrate_batch(qmc_context* ctx, const qmc_request* reqs, uint32_t coun
  * Autotune the batch kernels on a sample of requests: for every kernel variant
  * (dimension class; Korobov r=3, baker or any other transform / VR map;
  * real/complex; fp64/fp32) present in the sample, time each
- * compiled points-per-decode variant and candidate tile size on one round and
- * keep the fastest for this context (and append it to the file named by the
- * environment variable QMC_TUNE_CACHE, read at context creation).  The
- * points-per-decode choice never changes results; the tile size fixes the
- * summation order, so tune before integrating, not between calls whose sums
- * must match bitwise.  Requests whose real fp64 jobs run in a specialised
+ * compiled points-per-decode variant, shifts-per-thread group (8, 4 or 2 for
+ * real kernels; complex kernels hold one shift per thread) and candidate tile
+ * size on one round and keep the fastest for this context (and append it to
+ * the file named by the environment variable QMC_TUNE_CACHE, read at context
+ * creation, one line "gfx950 <largest dimension of the class> <transform
+ * class> <complex> <fp32> <points-per-decode index> <tile points> <shifts per
+ * group, 0 = 8>").  The points-per-decode and group choices never change
+ * results; the tile size fixes the summation order, so tune before
+ * integrating, not between calls whose sums must match bitwise.  Requests whose real fp64 jobs run in a specialised
  * kernel (QMC_SPECIALISE) are left out.  *configs_tried (optional) counts
  * timed schedules.
  */

@@ -103,9 +103,11 @@ int batch_job_shape(qmc_context* c, const BatchJob& b, BatchShape& sh) {
       specialised_kernel(c, const_cast<qmc_integrand*>(b.f), tsel, &sh.jk) == 0 && sh.jk.batch)
     sh.use_jit = true;
   const uint32_t S = cplx ? qmck::S_COMPLEX : qmck::S_REAL;
+  const uint32_t tuned = sh.use_jit ? 0u : c->batch_group[sh.var.index()];
+  sh.group_size = (tuned && tuned < S) ? tuned : S;
   sh.tile_points = batch_tile_points(c, sh.use_jit ? 0 : c->batch_tile[sh.var.index()], cplx, b.n);
   sh.ktiles = (uint32_t)((b.n + sh.tile_points - 1) / sh.tile_points);
-  sh.groups = (b.m + S - 1) / S;
+  sh.groups = (b.m + sh.group_size - 1) / sh.group_size;
   sh.rows = cplx ? 2 * b.m : b.m;
   return QMC_OK;
 }
@@ -193,7 +195,7 @@ int run_batch_jobs(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_
   struct Plan {
     qmck::BatchVariant var;
     int variant;  // var.index()
-    uint32_t rows, ktiles, groups;
+    uint32_t rows, ktiles, groups, group_size;
     uint64_t tile_points;
     size_t part_off, sh_off, row0;
     double cost;
@@ -229,6 +231,7 @@ int run_batch_jobs(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_
     p.tile_points = sh.tile_points;
     p.ktiles = sh.ktiles;
     p.groups = sh.groups;
+    p.group_size = sh.group_size;
     p.rows = sh.rows;
     const uint64_t all = (uint64_t)p.ktiles * p.groups;
     if (b.tile_count && (b.tile_first >= all || b.tile_count > all - b.tile_first))
@@ -355,6 +358,7 @@ int run_batch_jobs(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_
     a.tile_points = p.tile_points;
     a.ktiles = p.ktiles;
     a.tile_first = b.tile_count ? b.tile_first : 0;
+    a.shift_group = p.group_size;
     a.item = i;
     std::memcpy(shifts + p.sh_off, b.shifts, (size_t)b.m * b.f->dim * 8);
     if (p.finish)
@@ -724,15 +728,17 @@ static int variant_of(const qmc_request& q, qmck::BatchVariant& v) {
   return QMC_OK;
 }
 
-// Cache lines: "gfx950 <class's largest dimension> <tkc> <complex> <fp32> <sv index> <tile points>".
+// Cache lines: "gfx950 <class's largest dimension> <tkc> <complex> <fp32> <sv index> <tile points>
+// <shifts per group>".
 void load_tune_cache(qmc_context* c) {
   if (c->tune_cache.empty()) return;
   FILE* fh = std::fopen(c->tune_cache.c_str(), "r");
   if (!fh) return;
   int dmax, tkc, cx, f32, sv;
   unsigned long long tile;
+  unsigned group;
   char arch[64];
-  while (std::fscanf(fh, "%63s %d %d %d %d %d %llu", arch, &dmax, &tkc, &cx, &f32, &sv, &tile) == 7) {
+  while (std::fscanf(fh, "%63s %d %d %d %d %d %llu %u", arch, &dmax, &tkc, &cx, &f32, &sv, &tile, &group) == 8) {
     if (std::strcmp(arch, "gfx950") != 0 || tkc < 0 || tkc >= qmck::TKC_COUNT || cx < 0 || cx > 1 || f32 < 0 ||
         f32 > 1 || dmax < 1 || dmax > (int)QMC_MAX_DIM)
       continue;
@@ -741,6 +747,7 @@ void load_tune_cache(qmc_context* c) {
     const int v = qmck::BatchVariant{dc, tkc, cx != 0, f32 != 0}.index();
     if (sv >= 0 && sv < qmck::BATCH_SV_VARIANTS) c->batch_sv[v] = sv;
     if (tile >= 256 && tile <= (1ull << 24)) c->batch_tile[v] = tile;
+    if (group <= (unsigned)qmck::S_REAL) c->batch_group[v] = group;
   }
   std::fclose(fh);
 }
@@ -773,36 +780,46 @@ int autotune(qmc_context* c, const qmc_request* reqs, uint32_t count, uint32_t* 
     const std::vector<uint64_t> tiles = var.cplx ? std::vector<uint64_t>{512, 1024, 4096}
                                                  : std::vector<uint64_t>{1024, 4096, 16384};
     const int nsv = var.cplx ? 1 : qmck::BATCH_SV_VARIANTS;
+    // shifts per thread: all the kernel holds (0), or groups of 4 or 2, which
+    // trade fewer registers and more waves for more lattice-point work per
+    // evaluation; complex kernels already hold one shift per thread
+    const std::vector<uint32_t> groups = var.cplx ? std::vector<uint32_t>{0} : std::vector<uint32_t>{0, 4, 2};
     double best = 1e300;
     int best_sv = 0;
     uint64_t best_tile = tiles[0];
+    uint32_t best_group = 0;
     for (int sv = 0; sv < nsv; ++sv) {
       if (!qmck::batch_kernel(var, sv)) continue;
-      for (uint64_t tile : tiles) {
-        c->batch_sv[vi] = sv;
-        c->batch_tile[vi] = tile;
-        double t_best = 1e300;
-        for (int rep = 0; rep < 2; ++rep) {
-          std::vector<qmc_result> out(sub.size());
-          int rc = run_requests(c, sub.data(), (uint32_t)sub.size(), out.data(), nullptr);
-          if (rc) return rc;
-          t_best = std::min(t_best, out[0].device_seconds);
-        }
-        ++tried;
-        if (t_best < best) {
-          best = t_best;
-          best_sv = sv;
-          best_tile = tile;
+      for (uint32_t group : groups) {
+        for (uint64_t tile : tiles) {
+          c->batch_sv[vi] = sv;
+          c->batch_tile[vi] = tile;
+          c->batch_group[vi] = group;
+          double t_best = 1e300;
+          for (int rep = 0; rep < 2; ++rep) {
+            std::vector<qmc_result> out(sub.size());
+            int rc = run_requests(c, sub.data(), (uint32_t)sub.size(), out.data(), nullptr);
+            if (rc) return rc;
+            t_best = std::min(t_best, out[0].device_seconds);
+          }
+          ++tried;
+          if (t_best < best) {
+            best = t_best;
+            best_sv = sv;
+            best_tile = tile;
+            best_group = group;
+          }
         }
       }
     }
     c->batch_sv[vi] = best_sv;
     c->batch_tile[vi] = best_tile;
+    c->batch_group[vi] = best_group;
     if (!c->tune_cache.empty()) {
       if (FILE* fh = std::fopen(c->tune_cache.c_str(), "a")) {
-        std::fprintf(fh, "gfx950 %d %d %d %d %d %llu\n", qmck::dim_class_max(var.dclass, var.cplx), var.tkc,
+        std::fprintf(fh, "gfx950 %d %d %d %d %d %llu %u\n", qmck::dim_class_max(var.dclass, var.cplx), var.tkc,
                      var.cplx ? 1 : 0, var.fp32 ? 1 : 0,
-                     best_sv, (unsigned long long)best_tile);
+                     best_sv, (unsigned long long)best_tile, best_group);
         std::fclose(fh);
       }
     }

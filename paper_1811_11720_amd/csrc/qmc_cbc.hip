@@ -10,8 +10,10 @@
 // cyclic convolution of length L = n-1:
 //   T[a] = sum_b P[b] W[(a-b) mod L],  P[b] = p(g^-b),  W[c] = omega(g^c / n),
 // where p(k) = prod over the chosen components of (1 + gamma_j omega(...)).
-// It is computed as a linear convolution through power-of-two FFTs (radix-2
-// Stockham passes, twiddles from sincospi), then folded.  Candidates are
+// Below 2^31 it is computed as a linear convolution through zero-padded
+// power-of-two FFTs (radix-4 Stockham passes, twiddles from sincospi), then
+// folded; from 2^31 on (n - 1 of the form 2^a 3^b 5^c 7^d) without padding,
+// as described further down.  Candidates are
 // 1..(n-1)/2 (omega is symmetric); among those whose criterion is within a
 // relative 1e-9 of the minimum the smallest z wins.  All reductions run in a
 // fixed order.
@@ -64,20 +66,6 @@ __global__ void k_fill_p(cd* __restrict__ buf, const double* __restrict__ p, con
                          uint64_t L, uint64_t N) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (uint64_t)gridDim.x * blockDim.x)
     buf[i] = i < L ? cd{p[gp[i == 0 ? 0 : L - i]], 0.0} : cd{0.0, 0.0};
-}
-
-// one radix-2 Stockham pass: sub-transforms of length m become length 2m
-__global__ void k_fft_pass(const cd* __restrict__ x, cd* __restrict__ y, uint64_t half, uint64_t m, double sign) {
-  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < half; t += (uint64_t)gridDim.x * blockDim.x) {
-    const uint64_t j = t / m, k = t - j * m;
-    double s, c;
-    sincospi(sign * (double)k / (double)m, &s, &c);  // exp(sign i pi k / m)
-    const cd a = x[t], b = x[t + half];
-    const cd wb = {c * b.re - s * b.im, c * b.im + s * b.re};
-    const uint64_t o = k + 2 * j * m;
-    y[o] = cd{a.re + wb.re, a.im + wb.im};
-    y[o + m] = cd{a.re - wb.re, a.im - wb.im};
-  }
 }
 
 __global__ void k_cmul(cd* __restrict__ a, const cd* __restrict__ b, uint64_t N, double scale) {
@@ -455,6 +443,28 @@ static std::vector<int> mixed_radices(uint64_t m) {
   return r;
 }
 
+// Stockham passes of the given radices over N complex values from `in`
+// (`other` the second buffer); the transform ends in the returned buffer.
+static qmcc::cd* fft_passes(hipStream_t st, int cus, const std::vector<int>& rad, qmcc::cd* in, qmcc::cd* other,
+                            uint64_t N, double sign) {
+  qmcc::cd *a = in, *b = other;
+  uint64_t ns = 1;
+  for (int r : rad) {
+    const uint32_t gr = (uint32_t)std::min<uint64_t>((N / r + qmcc::BLOCK - 1) / qmcc::BLOCK,
+                                                     (uint64_t)std::max(1, cus) * 64);
+    switch (r) {
+      case 2: hipLaunchKernelGGL(qmcc::k_fft_pass_r<2>, dim3(gr), dim3(qmcc::BLOCK), 0, st, a, b, N, ns, sign); break;
+      case 3: hipLaunchKernelGGL(qmcc::k_fft_pass_r<3>, dim3(gr), dim3(qmcc::BLOCK), 0, st, a, b, N, ns, sign); break;
+      case 4: hipLaunchKernelGGL(qmcc::k_fft_pass_r<4>, dim3(gr), dim3(qmcc::BLOCK), 0, st, a, b, N, ns, sign); break;
+      case 5: hipLaunchKernelGGL(qmcc::k_fft_pass_r<5>, dim3(gr), dim3(qmcc::BLOCK), 0, st, a, b, N, ns, sign); break;
+      default: hipLaunchKernelGGL(qmcc::k_fft_pass_r<7>, dim3(gr), dim3(qmcc::BLOCK), 0, st, a, b, N, ns, sign); break;
+    }
+    ns *= (uint64_t)r;
+    std::swap(a, b);
+  }
+  return a;
+}
+
 // The construction for n - 1 = 2M with M 7-smooth: cyclic convolutions of
 // length n - 1 through real-packed mixed-radix FFTs of length M (no zero
 // padding: 32 (n - 1) bytes of device memory in all).
@@ -489,24 +499,7 @@ static int cbc_big(qmc_context* c, uint64_t n, uint32_t dim, const std::vector<d
   if (e != hipSuccess) return fail(QMC_ENOMEM, "device buffers for n=%llu: %s", (unsigned long long)n,
                                    hipGetErrorString(e));
   // transform of `in` in the given direction; the result ends in the returned buffer
-  auto fft = [&](qmcc::cd* in, qmcc::cd* other, double sign) -> qmcc::cd* {
-    qmcc::cd *a = in, *b = other;
-    uint64_t ns = 1;
-    for (int r : rad) {
-      const uint32_t gr = (uint32_t)std::min<uint64_t>((M / r + qmcc::BLOCK - 1) / qmcc::BLOCK,
-                                                       (uint64_t)std::max(1, c->cus) * 64);
-      switch (r) {
-        case 2: hipLaunchKernelGGL(qmcc::k_fft_pass_r<2>, dim3(gr), dim3(qmcc::BLOCK), 0, st, a, b, M, ns, sign); break;
-        case 3: hipLaunchKernelGGL(qmcc::k_fft_pass_r<3>, dim3(gr), dim3(qmcc::BLOCK), 0, st, a, b, M, ns, sign); break;
-        case 4: hipLaunchKernelGGL(qmcc::k_fft_pass_r<4>, dim3(gr), dim3(qmcc::BLOCK), 0, st, a, b, M, ns, sign); break;
-        case 5: hipLaunchKernelGGL(qmcc::k_fft_pass_r<5>, dim3(gr), dim3(qmcc::BLOCK), 0, st, a, b, M, ns, sign); break;
-        default: hipLaunchKernelGGL(qmcc::k_fft_pass_r<7>, dim3(gr), dim3(qmcc::BLOCK), 0, st, a, b, M, ns, sign); break;
-      }
-      ns *= (uint64_t)r;
-      std::swap(a, b);
-    }
-    return a;
-  };
+  auto fft = [&](qmcc::cd* in, qmcc::cd* other, double sign) { return fft_passes(st, c->cus, rad, in, other, M, sign); };
   // half spectrum of W, kept for every component
   hipLaunchKernelGGL(qmcc::k_fill_w_big, dim3(grid), dim3(qmcc::BLOCK), 0, st, x, L, g, gG, n, inv);
   qmcc::cd* wy = fft(x, y, -1.0);
@@ -582,11 +575,7 @@ extern "C" int qmc_cbc(qmc_context* c, uint64_t n, uint32_t dim, const double* g
   HIPCHK(hipSetDevice(c->device));
   const uint64_t L = n - 1;
   uint64_t N = 1;
-  int passes = 0;
-  while (N < 2 * L - 1) {
-    N <<= 1;
-    ++passes;
-  }
+  while (N < 2 * L - 1) N <<= 1;
   const uint64_t g = primitive_root_host(n);
   const uint32_t half_n = (uint32_t)((n - 1) / 2);
   hipStream_t st = c->stream;
@@ -610,15 +599,10 @@ extern "C" int qmc_cbc(qmc_context* c, uint64_t n, uint32_t dim, const double* g
                                    hipGetErrorString(e));
   // forward (sign -1) or inverse (+1) transform of `in`; the result ends in
   // the returned buffer (in or the other one)
-  auto fft = [&](qmcc::cd* in, qmcc::cd* other, double sign) -> qmcc::cd* {
-    qmcc::cd *a = in, *b = other;
-    for (int s = 0; s < passes; ++s) {
-      hipLaunchKernelGGL(qmcc::k_fft_pass, dim3(grid), dim3(qmcc::BLOCK), 0, st, a, b, N / 2, (uint64_t)1 << s,
-                         sign);
-      std::swap(a, b);
-    }
-    return a;
-  };
+  // radix-4 Stockham passes (one radix-2 pass when log2 N is odd): half the
+  // passes through memory of a radix-2 transform
+  const std::vector<int> rad2 = mixed_radices(N);
+  auto fft = [&](qmcc::cd* in, qmcc::cd* other, double sign) { return fft_passes(st, c->cus, rad2, in, other, N, sign); };
   const uint64_t chunk = 256;
   hipLaunchKernelGGL(qmcc::k_powers, dim3((uint32_t)((L / chunk + qmcc::BLOCK) / qmcc::BLOCK)), dim3(qmcc::BLOCK), 0,
                      st, gp, L, g, n, chunk);

@@ -77,6 +77,7 @@ struct EvalArgs {
   uint32_t item;              // batch: index of this integral
   uint32_t tile_skip;         // batch: column kt holds tile kt * (1 + tile_skip) (0: every tile)
   uint32_t tile_first;        // batch: the item's tiles this launch covers start at this one
+  uint32_t shift_group;       // batch: shifts per thread group, at most the kernel's S (0: S)
 };
 
 // Where one workgroup's threads sit in the lattice and where their sums go.
@@ -88,6 +89,7 @@ struct Sched {
   const uint64_t* step;   // (stride * z_j) mod n
   uint32_t col;           // column of partial[][] written by this workgroup
   uint32_t s0;            // first shift of the group
+  uint32_t ns_max;        // shifts in a group (at most the kernel's S)
 };
 
 __device__ __forceinline__ Sched grid_sched(const EvalArgs& a, int S) {
@@ -98,6 +100,7 @@ __device__ __forceinline__ Sched grid_sched(const EvalArgs& a, int S) {
   sc.step = a.step;
   sc.col = blockIdx.x;
   sc.s0 = blockIdx.y * S;
+  sc.ns_max = S;
   return sc;
 }
 
@@ -974,7 +977,7 @@ struct bounded_fn<Fn, decltype(void(Fn::kBounded))> {
 template <int DMAX, int TK, bool IDX32, int S, bool EXACT, class Fn, int VRM = VRM_RUNTIME, bool COMP = false>
 __device__ __forceinline__ void eval_real_sched(const EvalArgs& a, const Fn& fn, const Sched& sc) {
   const uint32_t s0 = sc.s0;
-  const uint32_t ns = (a.m - s0) < (uint32_t)S ? (a.m - s0) : (uint32_t)S;
+  const uint32_t ns = (a.m - s0) < sc.ns_max ? (a.m - s0) : sc.ns_max;
   const uint32_t dim = EXACT ? (uint32_t)DMAX : a.dim;
   double acc[S], cmp[S];
 #pragma unroll
@@ -1177,7 +1180,7 @@ template <int DMAX, int TK, bool IDX32, int S, int SV, bool F32, bool COMP, int 
 __device__ __forceinline__ void eval_real_multi_sched(const EvalArgs& a, const Sched& sc) {
   static_assert(S % SV == 0, "shift group must be a multiple of the point group");
   const uint32_t s0 = sc.s0;
-  const uint32_t ns = (a.m - s0) < (uint32_t)S ? (a.m - s0) : (uint32_t)S;
+  const uint32_t ns = (a.m - s0) < sc.ns_max ? (a.m - s0) : sc.ns_max;
   const uint32_t dim = a.dim;
   double acc[S], cmp[S];
 #pragma unroll
@@ -1251,7 +1254,7 @@ __device__ __forceinline__ void eval_real_multi_sched(const EvalArgs& a, const S
 template <int DMAX, int TK, bool IDX32, int S, bool EXACT, class Fn, int VRM = VRM_RUNTIME, bool COMP = false>
 __device__ __forceinline__ void eval_complex_sched(const EvalArgs& a, const Fn& fn, const Sched& sc) {
   const uint32_t s0 = sc.s0;
-  const uint32_t ns = (a.m - s0) < (uint32_t)S ? (a.m - s0) : (uint32_t)S;
+  const uint32_t ns = (a.m - s0) < sc.ns_max ? (a.m - s0) : sc.ns_max;
   const uint32_t dim = EXACT ? (uint32_t)DMAX : a.dim;
   double acc_re[S], acc_im[S], c_re[S], c_im[S];
 #pragma unroll
@@ -1372,7 +1375,9 @@ __device__ __forceinline__ void batch_tiles(const EvalArgs* __restrict__ items, 
     sc.stride = QMCD_BLOCK;
     sc.step = a.step;
     sc.col = kt;
-    sc.s0 = g * S;
+    const uint32_t gs = (a.shift_group && a.shift_group < (uint32_t)S) ? a.shift_group : (uint32_t)S;
+    sc.s0 = g * gs;
+    sc.ns_max = gs;
     body(a, sc);
     __syncthreads();  // the reduction's LDS is reused by the next tile
   }

@@ -55,6 +55,7 @@ struct qmc_context {
   // per kernel variant [dimension class][complex][fp32]: tuned schedule (0 = default)
   int batch_sv[qmck::BATCH_VARIANTS] = {};         // index into the compiled points-per-decode variants
   uint64_t batch_tile[qmck::BATCH_VARIANTS] = {};  // minimum points per tile (0 = the default)
+  uint32_t batch_group[qmck::BATCH_VARIANTS] = {};  // shifts per thread group (0 = the kernel's S)
   std::string tune_cache;             // file the autotuner reads and appends
   hipStream_t cap_stream = nullptr;   // private stream used only for graph capture
   // instantiated graphs of recent batch rounds, keyed by every launch argument
@@ -210,6 +211,7 @@ struct BatchShape {
   qmcj::Kernel jk;
   uint64_t tile_points = 0;
   uint32_t ktiles = 0, groups = 0, rows = 0;
+  uint32_t group_size = 0;  // shifts per thread group
 };
 int batch_job_shape(qmc_context* c, const BatchJob& b, BatchShape& sh);
 // Points per tile of a batch job of n points: the variant's tuned minimum

@@ -826,6 +826,11 @@ int qmc_context_create(int device, void* hip_stream, void* workspace, size_t wor
         c->batch_sv[v] = f32 ? 1 : 2;
         if (force_sv >= 0 && force_sv < qmck::BATCH_SV_VARIANTS) c->batch_sv[v] = force_sv;
       }
+  if (const char* v = std::getenv("QMC_BATCH_GROUP")) {  // shifts per thread of the real batch kernels (0: all 8)
+    const int g = atoi(v);
+    if (g >= 0 && g <= qmck::S_REAL)
+      for (int v = 0; v < qmck::BATCH_VARIANTS; ++v) c->batch_group[v] = (uint32_t)g;
+  }
   if (const char* v = std::getenv("QMC_TUNE_CACHE")) {
     c->tune_cache = v;
     load_tune_cache(c);

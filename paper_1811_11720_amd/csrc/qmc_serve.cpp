@@ -134,11 +134,10 @@ static int plan_slice(qmc_context* c, qmc_serve_state* s, Req& r, double share) 
     BatchShape sh;
     int rc = batch_job_shape(c, j, sh);
     if (rc) return rc;
-    const uint32_t S = (r.f->flags & QMC_DEFORM) ? qmck::S_COMPLEX : qmck::S_REAL;
     r.tiles_total = sh.ktiles * sh.groups;
     r.tiles_done = 0;
     r.lat_signs = 0;
-    r.tile_cost = (double)sh.tile_points * std::min<uint32_t>(S, r.q.m) * eval_cost(r.f);
+    r.tile_cost = (double)sh.tile_points * std::min<uint32_t>(sh.group_size, r.q.m) * eval_cost(r.f);
     const double whole = (double)r.n * r.q.m * eval_cost(r.f);
     if (whole <= share || !c->own_ws || r.tiles_total == 1) {
       r.tiles_total = 0;  // one round: no state kept

@@ -247,6 +247,22 @@ def test_points_per_decode_variants_give_identical_sums():
             assert np.array_equal(a["sums_re"], b["sums_re"]) and np.array_equal(a["sums_im"], b["sums_im"])
 
 
+def test_shift_group_sizes_give_identical_sums():
+    """Shifts per thread (the autotuner's third choice): a shift's sum is
+    accumulated over the same points in the same order whichever shifts share
+    its thread, so groups of 8, 4, 2 and 1 (with their ragged last groups at
+    m not a multiple) give the same sums bitwise."""
+    jobs = _mix(12, 16) + _mix(6, 17, fp32=True)
+    outs = []
+    for g in (0, 4, 2, 1):
+        c = _ctx_env(QMC_BATCH_GROUP=g)
+        outs.append(_run(c, jobs))
+        c.close()
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a["sums_re"], b["sums_re"]) and np.array_equal(a["sums_im"], b["sums_im"])
+
+
 def test_autotune_keeps_parity_and_writes_its_cache(tmp_path):
     cache = tmp_path / "tune.txt"
     jobs = _mix(10, 8)
@@ -261,8 +277,9 @@ def test_autotune_keeps_parity_and_writes_its_cache(tmp_path):
         sh = oracle.shifts(j.seed, j.m, j.desc.dim)
         o = oracle.shift_sums(j.desc, j.n, j.z, j.m, sh, j.transform, threads=THREADS)
         _check_sums(r["sums_re"], o, r["sums_im"] if j.desc.deform else None, label=f"d{j.desc.dim}")
-    lines = cache.read_text().split()
-    assert len(lines) >= 6 and lines[0] == "gfx950"
+    lines = cache.read_text().splitlines()
+    assert lines and all(len(l.split()) == 8 and l.split()[0] == "gfx950" for l in lines)
+    assert all(int(l.split()[7]) in (0, 4, 2) for l in lines)
     # a new context reads the cache and reproduces the tuned schedule bitwise
     c2 = _ctx_env(QMC_TUNE_CACHE=cache)
     again = _run(c2, jobs, keep=keep)

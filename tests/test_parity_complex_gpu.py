@@ -152,3 +152,25 @@ def test_sector_complex_range_at_1e7(ctx):
     o = oracle.shift_sums(job.desc, job.n, job.z, job.m, sh, job.transform, k0=k0, k1=k1, ids=ids,
                           threads=THREADS)
     _check_sums(g_re[ids], o, g_im[ids])
+
+
+def test_sector_complex_at_its_final_lattice():
+    """The complex sector workload's last lattice on its way to relative
+    1e-8: n = 1135362251, built on the device as the growth loop builds it,
+    with the VR map fitted as the bench fits it (1024-bin histograms on one
+    shifted 100003-point lattice).  Two shifts over a k-range of 200000
+    points against the oracle."""
+    c = make_ctx("specialised")
+    job = W.job_sector_complex(100003)
+    f = c.integrand(job.desc)
+    params, mask = c.fit_vr(f, 100003, W.z_for(100003, 8), job.seed)
+    n = 1135362251
+    assert cbc.is_prime(n)
+    z = c.cbc(n, 8)
+    k0, k1 = 987_654_321, 987_854_321
+    g_re, g_im = c.shift_sums_range(f, n, z, 2, job.seed, job.transform, k0, k1)
+    sh = oracle.shifts(job.seed, 2, 8)
+    o = oracle.shift_sums(job.desc, n, z, 2, sh, job.transform, params, k0=k0, k1=k1, threads=THREADS)
+    _check_sums(g_re, o, g_im, label="c3 final lattice")
+    f.close()
+    c.close()
