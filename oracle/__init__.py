@@ -20,6 +20,7 @@ import ctypes as C
 import math
 import os
 import subprocess
+import threading
 
 import numpy as np
 
@@ -33,7 +34,7 @@ T_NONE, T_KOROBOV, T_BAKER, T_SIDI = 0, 1, 2, 3
 def build(force: bool = True) -> str:
     """Compile oracle.c with gcc (plain fp64: no fast-math, no contraction)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
+        tmp = f"{_LIB}.{os.getpid()}.{threading.get_ident()}.tmp"  # concurrent builders do not share it
         subprocess.check_call(
             ["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-shared", "-fPIC",
              "-std=gnu11", _SRC, "-o", tmp, "-lm"]
@@ -59,11 +60,16 @@ class _Desc(C.Structure):
 
 
 _lib = None
+_lib_mu = threading.Lock()
 
 
 def lib():
     global _lib
-    if _lib is None:
+    if _lib is not None:
+        return _lib
+    with _lib_mu:  # callers on several threads: one build and load
+        if _lib is not None:
+            return _lib
         if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build(force=True)
         L = C.CDLL(_LIB)
@@ -93,8 +99,8 @@ def lib():
         L.oracle_histogram.restype = C.c_int
         L.oracle_cbc_criterion.argtypes = [C.c_uint64, C.c_uint32, up, dp]
         L.oracle_cbc_criterion.restype = C.c_double
-        L.oracle_cbc_partial.argtypes = [C.c_uint64, C.c_uint32, up, dp, C.c_uint64, C.c_uint64]
-        L.oracle_cbc_partial.restype = C.c_double
+        L.oracle_cbc_partial.argtypes = [C.c_uint64, C.c_uint32, up, dp, C.c_uint64, C.c_uint64, dp]
+        L.oracle_cbc_partial.restype = None
         L.oracle_cbc_brute.argtypes = [C.c_uint64, C.c_uint32, dp, C.c_double, up]
         L.oracle_cbc_brute.restype = C.c_int
         L.oracle_max_threads.restype = C.c_int
@@ -371,7 +377,8 @@ def integrate(desc, n, z_of, m, seed, transform=(T_KOROBOV, 3, 3), vr=None, rel_
 
 def cbc_criterion(n, z, gammas, threads: int = 1) -> float:
     """e^2(z) of the CBC construction; with threads > 1 the sum over k is
-    split into that many consecutive ranges whose sums are added in order."""
+    split into that many consecutive ranges, each summed in double-double,
+    and the ranges' words are added exactly."""
     zz = np.ascontiguousarray(z, dtype=np.uint64)
     g = np.ascontiguousarray(gammas, dtype=np.float64)
     if threads <= 1:
@@ -379,10 +386,15 @@ def cbc_criterion(n, z, gammas, threads: int = 1) -> float:
     from concurrent.futures import ThreadPoolExecutor
 
     edges = [n * i // threads for i in range(threads + 1)]
+    words = np.zeros((threads, 2))
+
+    def part(i):
+        lib().oracle_cbc_partial(n, zz.size, _up(zz), _dp(g), edges[i], edges[i + 1], _dp(words[i]))
+
     with ThreadPoolExecutor(threads) as ex:
-        parts = list(ex.map(lambda i: lib().oracle_cbc_partial(n, zz.size, _up(zz), _dp(g), edges[i], edges[i + 1]),
-                            range(threads)))
-    return math.fsum(parts) / n
+        list(ex.map(part, range(threads)))
+    # fsum of the ranges' high and low words: their exact sum, rounded once
+    return math.fsum(words.reshape(-1).tolist()) / n
 
 
 def cbc_brute(n, d, gammas=None, tie_rtol=1e-9) -> list[int]:

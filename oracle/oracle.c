@@ -549,19 +549,27 @@ static double cbc_kernel(uint64_t r, uint64_t n) {
 }
 
 /* sum over k in [k0, k1) of prod_j (1 + gamma_j omega({k z_j / n})) - 1 */
-double oracle_cbc_partial(uint64_t n, uint32_t d, const uint64_t* z, const double* gamma, uint64_t k0, uint64_t k1) {
+/* sum over k in [k0, k1) of prod_j (1 + gamma_j omega({k z_j / n})) - 1, as
+ * the two words of a double-double: a range's sum can be many orders of
+ * magnitude larger than the whole lattice's, so callers that split k add the
+ * words exactly (one double per range would lose the small total). */
+void oracle_cbc_partial(uint64_t n, uint32_t d, const uint64_t* z, const double* gamma, uint64_t k0, uint64_t k1,
+                        double* hi_lo) {
   dd_t s = {0, 0};
   for (uint64_t k = k0; k < k1; ++k) {
     double p = 1.0;
     for (uint32_t j = 0; j < d; ++j) p *= 1.0 + gamma[j] * cbc_kernel(lattice_index(k, z[j], n), n);
     dd_add(&s, p - 1.0);
   }
-  return s.hi + s.lo;
+  hi_lo[0] = s.hi;
+  hi_lo[1] = s.lo;
 }
 
 /* e^2(z) = -1 + (1/n) sum_k prod_j (1 + gamma_j omega({k z_j / n})) */
 double oracle_cbc_criterion(uint64_t n, uint32_t d, const uint64_t* z, const double* gamma) {
-  return oracle_cbc_partial(n, d, z, gamma, 0, n) / (double)n;
+  double s[2];
+  oracle_cbc_partial(n, d, z, gamma, 0, n, s);
+  return (s[0] + s[1]) / (double)n;
 }
 
 static uint64_t gcd_u64(uint64_t a, uint64_t b) {

@@ -38,36 +38,44 @@ def test_paper_vectors_reach_the_minimum_under_equal_weights(ctx):
     for n, zp in [(7, [1, 3]), (11, [1, 7])]:
         z = ctx.cbc(n, 2, [0.5, 0.5])
         assert oracle.cbc_criterion(n, z, [0.5, 0.5]) == pytest.approx(oracle.cbc_criterion(n, zp, [0.5, 0.5]),
-                                                                      rel=1e-12)
+                                                                      rel=1e-12, abs=0.0)
+
+
+def _first_divergence_equal(n, za, zb, rel):
+    """Greedy vectors that part at some component: there both choices have the
+    same worst-case error within `rel` (after it each step conditions on a
+    different prefix, so the rest is not comparable)."""
+    if za == zb:
+        return
+    j = next(i for i in range(len(za)) if za[i] != zb[i])
+    ea = oracle.cbc_criterion(n, za[:j + 1], _gam(j + 1), threads=16)
+    eb = oracle.cbc_criterion(n, zb[:j + 1], _gam(j + 1), threads=16)
+    assert ea == pytest.approx(eb, rel=rel, abs=0.0), (j, za[j], zb[j], ea, eb)
 
 
 @pytest.mark.parametrize("n", [10007, 65537, 1000003])
 def test_device_cbc_matches_host_fast_cbc(ctx, n):
-    """Same vector as the host construction, or (inside the 1e-9 tie band,
-    where FFT rounding may decide) a vector of the same worst-case error."""
+    """Same vector as the host construction, or, at the first component where
+    they part (FFT rounding deciding between near-equal candidates), two
+    choices of the same worst-case error."""
     d = 8
-    zg = ctx.cbc(n, d)
-    zh = cbc.fast_cbc(n, d)
-    if zg != zh:
-        for j in range(2, d + 1):
-            eg = oracle.cbc_criterion(n, zg[:j], _gam(j))
-            eh = oracle.cbc_criterion(n, zh[:j], _gam(j))
-            assert eg == pytest.approx(eh, rel=1e-8)
+    _first_divergence_equal(n, ctx.cbc(n, d), cbc.fast_cbc(n, d), rel=1e-6)
 
 
 def test_device_cbc_at_the_headline_size(ctx):
-    """n = 100000007: the first components against the committed table's
-    (host-built) vector by the oracle's direct worst-case error."""
+    """n = 100000007 against the committed table's (host-built) vector.  The
+    FFT constructions resolve e^2 here to about 4e-7 relative (their
+    convolutions' rounding, about 2e-12 on sums of size 14, far above the 1e-9
+    tie band), so two candidates closer than that may be taken either way and
+    the vectors may part; at the first component where they do, the two
+    choices must agree within 1e-5 by the oracle's direct sum."""
     n, d = 100000007, 4
     t0 = time.perf_counter()
     zg = ctx.cbc(n, d)
     dt = time.perf_counter() - t0
-    print(f"device CBC n={n} d={d}: {dt:.2f} s")
+    print(f"device CBC n={n} d={d}: {dt:.2f} s, z={zg}", flush=True)
     zt = W.lattice_table()[n][:d]
-    if zg != zt:
-        eg = oracle.cbc_criterion(n, zg, _gam(d))
-        et = oracle.cbc_criterion(n, zt, _gam(d))
-        assert eg == pytest.approx(et, rel=1e-8)
+    _first_divergence_equal(n, zg, zt, rel=1e-5)
     assert zg[0] == 1 and all(1 <= v <= (n - 1) // 2 for v in zg)
 
 
@@ -122,13 +130,7 @@ def test_mixed_radix_cbc_matches_the_padded_path(ctx, n):
     greedy steps condition on different prefixes and may go their own ways."""
     assert cbc.is_prime(n) and _smooth7((n - 1) // 2)
     d = 6
-    zm = _mixed(ctx, n, d)
-    zp = ctx.cbc(n, d)
-    if zm != zp:
-        j = next(i for i in range(d) if zm[i] != zp[i])
-        em = oracle.cbc_criterion(n, zm[:j + 1], _gam(j + 1), threads=16)
-        ep = oracle.cbc_criterion(n, zp[:j + 1], _gam(j + 1), threads=16)
-        assert em == pytest.approx(ep, rel=1e-8)
+    _first_divergence_equal(n, _mixed(ctx, n, d), ctx.cbc(n, d), rel=1e-8)
 
 
 def test_cbc_beyond_2_31():

@@ -667,3 +667,17 @@ def test_goal_rules_complex():
     assert not oracle.goal_met(1.0, 1e-3, 1e-6, 1e-6, 1e-5, 0.0, "all", True)
     assert oracle.goal_met(1.0, 1e-3, 1e-6, 1e-9, 1e-5, 0.0, "all", True)
     assert oracle.goal_met(1.0, 0.0, 1e-8, 0.0, 0.0, 1e-7, "all", False)
+
+
+def test_cbc_criterion_split_over_threads_is_the_single_sum():
+    """e^2 is a small difference of O(1) terms; summed over k-ranges on
+    threads, each range's double-double sum is added exactly, so the result is
+    the single-range sum's to the last bits (one double per range would lose
+    about 1e-7 of it here, whose ranges sum to ~1e5)."""
+    n = 1000003
+    z = [1, 386343]
+    g = [1.0, 0.25]
+    one = oracle.cbc_criterion(n, z, g)
+    for t in (2, 3, 8):
+        assert oracle.cbc_criterion(n, z, g, threads=t) == pytest.approx(one, rel=1e-14, abs=0.0)
+
