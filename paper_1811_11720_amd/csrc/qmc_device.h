@@ -344,8 +344,12 @@ __device__ __forceinline__ uint32_t mono_exp(uint32_t w0, uint32_t w1, int j) {
   return ((j < 8 ? w0 : w1) >> (4 * (j & 7))) & 15u;
 }
 
-__device__ __forceinline__ double vr_map(double y, cptr<double> p, double& w) {
-  double p0 = p[0], p1 = p[1], p2 = __builtin_fabs(p[2]), p3 = __builtin_fabs(p[3]), p4 = p[4], p5 = p[5];
+// PolySingular map y -> x(y), w *= x'(y) (Sec. 2.4, eq. ISfit, App. A.5 form with |p2|, |p3|), its
+// parameters passed as values (read from a table, or constants compiled into a kernel)
+__device__ __forceinline__ double vr_map_v(double y, double p0, double p1, double p2, double p3, double p4, double p5,
+                                           double& w) {
+  p2 = __builtin_fabs(p2);
+  p3 = __builtin_fabs(p3);
   double c3 = 1.0 - p2 - p3 - p4 - p5;
   double i0 = fast_rcp(p0 - y), i1 = fast_rcp(p1 - y);  // poles stay outside [0, 1]
   double x = p2 * y * (p0 - 1.0) * i0 + p3 * y * (p1 - 1.0) * i1 + y * (p4 + y * (p5 + y * c3));
@@ -353,6 +357,9 @@ __device__ __forceinline__ double vr_map(double y, cptr<double> p, double& w) {
               y * (2.0 * p5 + 3.0 * c3 * y);
   w *= dx;
   return x;
+}
+__device__ __forceinline__ double vr_map(double y, cptr<double> p, double& w) {
+  return vr_map_v(y, p[0], p[1], p[2], p[3], p[4], p[5], w);
 }
 
 // ------------------------------------------------------------------ integrand
@@ -953,7 +960,8 @@ __device__ __forceinline__ void block_store(const double (&acc)[S], uint32_t ns,
 // EXACT: the integrand has exactly DMAX variables (specialised kernels).
 // VRM: variance-reduction map 0 = decided at run time (a.vr), 1 = off, 2 = on.
 // COMP: compensated (Neumaier) accumulation of the contributions.
-enum { VRM_RUNTIME = 0, VRM_OFF = 1, VRM_ON = 2 };
+// VRM_FN: the functor supplies the map (fn.vr_map(y, j, w)), parameters compiled in
+enum { VRM_RUNTIME = 0, VRM_OFF = 1, VRM_ON = 2, VRM_FN = 3 };
 
 __device__ __forceinline__ void neumaier(double& s, double& c, double v) {
   double t = s + v;
@@ -1282,7 +1290,10 @@ __device__ __forceinline__ void eval_complex_sched(const EvalArgs& a, const Fn& 
           if (j < (int)dim) {
             double u = shifted(q[j], D[j]);
             double y = transform<TK>(u, wt, a);
-            if (VRM == VRM_ON || (VRM == VRM_RUNTIME && a.vr)) y = vr_map(y, as_const(a.vr) + 6 * j, wv);
+            if constexpr (VRM == VRM_FN)
+              y = fn.vr_map(y, j, wv);
+            else if (VRM == VRM_ON || (VRM == VRM_RUNTIME && a.vr))
+              y = vr_map(y, as_const(a.vr) + 6 * j, wv);
             x[j] = y;
           } else {
             x[j] = 0.0;

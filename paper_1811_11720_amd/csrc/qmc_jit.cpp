@@ -239,9 +239,20 @@ struct Val {
   bool real;  // a real scalar (coefficient); otherwise a cplx value in the complex domain
 };
 
+// A coefficient as the kernel reads it: from its arguments, or, with the values
+// given, as an exact hexadecimal constant.  Constants take no registers across
+// the point loop, where the table-read values of a large integrand overflow
+// the scalar registers and are spilled and reloaded at every point.
+std::string coef_value(const double* values, uint32_t i) {
+  if (!values) return "a.coef[" + std::to_string(i) + "]";
+  char buf[64];
+  std::snprintf(buf, sizeof buf, "%a", values[i]);
+  return buf;
+}
+
 class CEmitter {
  public:
-  CEmitter(int dim, bool cplx_domain) : dim_(dim), cx_(cplx_domain) {}
+  CEmitter(int dim, bool cplx_domain, const double* values) : dim_(dim), cx_(cplx_domain), values_(values) {}
   std::string tmp() { return std::string(cx_ ? "w" : "r") + std::to_string(ntmp_++); }
   void line(const std::string& s) { body_ << "    " << s << "\n"; }
   std::string coef(uint32_t i, int mult) {
@@ -273,7 +284,7 @@ class CEmitter {
   }
   std::string decls() const {
     std::ostringstream o;
-    for (uint32_t i : coefs_) o << "    const double c" << i << " = a.coef[" << i << "];\n";
+    for (uint32_t i : coefs_) o << "    const double c" << i << " = " << coef_value(values_, i) << ";\n";
     for (auto& kv : scaled_) o << "    const double " << kv.first << " = " << kv.second << ";\n";
     return o.str();
   }
@@ -285,6 +296,7 @@ class CEmitter {
  private:
   int dim_;
   bool cx_;
+  const double* values_;
   int ntmp_ = 0;
   std::set<uint32_t> coefs_;
   std::map<std::string, std::string> scaled_;
@@ -408,7 +420,7 @@ std::string generate_complex_fn(const qmcj::Spec& s) {
       for (int j = 0; j < d; ++j) any = any || t.e[j];
       if (any) used.insert(t.ci);
     }
-    for (uint32_t i : used) o << "    const double c" << i << " = a.coef[" << i << "];\n";
+    for (uint32_t i : used) o << "    const double c" << i << " = " << coef_value(s.coef, i) << ";\n";
     std::set<int> rjs;
     for (auto& p : erx) rjs.insert(p.first);
     for (int j : rjs) o << "    const double rx" << j << " = fast_rcp(x[" << j << "]);\n";
@@ -431,7 +443,7 @@ std::string generate_complex_fn(const qmcj::Spec& s) {
     o << "  }\n";
   }
   for (int which = 0; which < 2; ++which) {
-    CEmitter em(d, true);
+    CEmitter em(d, true, s.coef);
     HornerPlan plan(d, 0);  // greedy: complex products make the operation count a poor cost model
     Val v = chorner(which == 0 ? tu : tf, em, plan);
     o << "  __device__ __forceinline__ cplx " << (which == 0 ? "U" : "F") << "(const cplx (&z)[" << d
@@ -441,6 +453,13 @@ std::string generate_complex_fn(const qmcj::Spec& s) {
   }
   o << "  __device__ __forceinline__ cplx uf(const cplx (&z)[" << d
     << "], const EvalArgs& a, uint32_t& sign) const {\n    return uf_fp64<" << d << ">(*this, z, a, sign);\n  }\n";
+  if (s.vr && s.vr_params) {
+    // the fitted map with its parameters as constants (j is unrolled at every call)
+    o << "  __device__ __forceinline__ double vr_map(double y, int j, double& w) const {\n"
+      << "    constexpr double P[" << 6 * d << "] = {";
+    for (int i = 0; i < 6 * d; ++i) o << (i ? ", " : "") << coef_value(s.vr_params, (uint32_t)i);
+    o << "};\n    return vr_map_v(y, P[6 * j], P[6 * j + 1], P[6 * j + 2], P[6 * j + 3], P[6 * j + 4], P[6 * j + 5], w);\n  }\n";
+  }
   o << "};\n}  // namespace qmcd\n";
   return o.str();
 }
@@ -469,13 +488,13 @@ std::string generate(const Spec& s) {
                    : s.tk == qmcd::TK_SIDI    ? "qmcd::TK_SIDI"
                                                : "qmcd::TK_NONE";
   if (s.cplx) {
+    const char* vrm = !s.vr ? "qmcd::VRM_OFF" : s.vr_params ? "qmcd::VRM_FN" : "qmcd::VRM_ON";
     std::ostringstream o;
     o << "#define QMC_RTC 1\n" << kDeviceSrc << "\n" << generate_complex_fn(s);
     for (int w = 0; w < 2; ++w) {
       o << "extern \"C\" __global__ __launch_bounds__(QMCD_BLOCK) void qmc_jit_eval" << (w ? "64" : "32")
         << "(qmcd::EvalArgs a) {\n  qmcd::eval_complex_body<" << d << ", " << tk << ", " << (w ? "false" : "true")
-        << ", " << s.S << ", true, qmcd::JitComplex, " << (s.vr ? "qmcd::VRM_ON" : "qmcd::VRM_OFF")
-        << ">(a, qmcd::JitComplex());\n}\n";
+        << ", " << s.S << ", true, qmcd::JitComplex, " << vrm << ">(a, qmcd::JitComplex());\n}\n";
     }
     // persistent batch entry: the table-driven complex batch kernels' tile
     // loop and shift groups, with this integrand's evaluation
@@ -484,7 +503,7 @@ std::string generate(const Spec& s) {
          "uint32_t* __restrict__ counter) {\n  qmcd::batch_tiles<"
       << qmck::S_COMPLEX << ">(items, order, prefix, nitems, counter, [&](const qmcd::EvalArgs& a, const qmcd::Sched& sc) {\n"
       << "    qmcd::eval_complex_sched<" << d << ", " << tk << ", false, " << qmck::S_COMPLEX << ", true, qmcd::JitComplex, "
-      << (s.vr ? "qmcd::VRM_ON" : "qmcd::VRM_OFF") << ">(a, qmcd::JitComplex(), sc);\n  });\n}\n";
+      << vrm << ">(a, qmcd::JitComplex(), sc);\n  });\n}\n";
     return o.str();
   }
   Emitter em(d);

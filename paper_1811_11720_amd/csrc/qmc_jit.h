@@ -22,6 +22,11 @@ struct Spec {
   // > 0: real f = prefactor (U^ru F^rf)^(-1/2), one reciprocal square root for
   // both powers (pow_u = -ru/2, pow_f = -rf/2); 0: the separate powers
   int ru = 0, rf = 0;
+  // complex integrands: coefficient values [n_u + n_f] and, with vr, the map
+  // parameters [dim][6] compiled into the kernel as constants (nullptr: read
+  // from the kernel's arguments)
+  const double* coef = nullptr;
+  const double* vr_params = nullptr;
 };
 
 struct Kernel {

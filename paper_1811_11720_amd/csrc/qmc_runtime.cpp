@@ -251,6 +251,12 @@ int specialised_kernel(qmc_context* c, qmc_integrand* f, int tsel, qmcj::Kernel*
   qmcj::Spec sp{f->dim, f->n_u, f->n_f, f->expo.data(), f->pu_mode, f->pu_k, f->pf_mode, f->pf_k, tsel,
                 cplx ? qmck::S_COMPLEX_JIT : c->jit_S, f->has_vr ? 1 : 0, cplx ? 1 : 0};
   if (!cplx) combined_root(f->dim, f->n_u, f->n_f, f->coef.data(), f->expo.data(), f->pow_u, f->pow_f, sp.ru, sp.rf);
+  if (cplx) {
+    // a deformed integrand's kernel holds its coefficients and fitted map as
+    // constants (it is compiled for this integrand only)
+    sp.coef = f->coef.data();
+    if (f->has_vr) sp.vr_params = f->vr.data();
+  }
   if (qmcj::get(c->device, sp, out) != 0) {
     f->jit_failed[jkey] = 1;
     if (std::getenv("QMC_JIT_VERBOSE")) std::fprintf(stderr, "qmc: specialisation failed: %s\n", qmcj::last_error());
@@ -829,7 +835,7 @@ int qmc_context_create(int device, void* hip_stream, void* workspace, size_t wor
   if (const char* v = std::getenv("QMC_BATCH_GROUP")) {  // shifts per thread of the real batch kernels (0: all 8)
     const int g = atoi(v);
     if (g >= 0 && g <= qmck::S_REAL)
-      for (int v = 0; v < qmck::BATCH_VARIANTS; ++v) c->batch_group[v] = (uint32_t)g;
+      for (int vi = 0; vi < qmck::BATCH_VARIANTS; ++vi) c->batch_group[vi] = (uint32_t)g;
   }
   if (const char* v = std::getenv("QMC_TUNE_CACHE")) {
     c->tune_cache = v;
@@ -1006,9 +1012,19 @@ int qmc_destroy_integrand(qmc_integrand* f) {
 
 int qmc_set_vr(qmc_integrand* f, const double* params) {
   if (!f) return fail(QMC_EINVAL, "integrand is NULL");
+  // specialised kernels of a deformed integrand hold the map's parameters as
+  // constants: those compiled for the previous map are dropped
+  auto drop_vr_kernels = [f]() {
+    if (!(f->flags & QMC_DEFORM)) return;
+    for (auto it = f->jit.begin(); it != f->jit.end();) it = (it->first & 1) ? f->jit.erase(it) : std::next(it);
+    for (auto it = f->jit_failed.begin(); it != f->jit_failed.end();)
+      it = (it->first & 1) ? f->jit_failed.erase(it) : std::next(it);
+  };
   if (!params) {
+    CtxLock g(f->ctx);
     f->has_vr = false;
     f->vr_fallback = 0;
+    drop_vr_kernels();
     return QMC_OK;
   }
   for (uint32_t j = 0; j < f->dim; ++j) {
@@ -1021,6 +1037,7 @@ int qmc_set_vr(qmc_integrand* f, const double* params) {
   CtxLock g(f->ctx);
   f->vr.assign(params, params + 6 * f->dim);
   f->vr_fallback = 0;
+  drop_vr_kernels();
   (void)hipSetDevice(f->ctx->device);
   (void)hipStreamSynchronize(f->ctx->stream);
   HIPCHK(hipMemcpy(f->d_vr, f->vr.data(), f->vr.size() * 8, hipMemcpyHostToDevice));
@@ -1151,6 +1168,7 @@ int qmc_specialize_check(const qmc_integrand_desc* d, qmc_transform t, size_t* c
   const int cx = (d->flags & QMC_DEFORM) ? 1 : 0;
   qmcj::Spec sp{d->dim, d->n_u, d->n_f, d->expo, pu_mode, pu_k, pf_mode, pf_k, tsel, cx ? qmck::S_COMPLEX_JIT : S, 0, cx};
   if (!cx) combined_root(d->dim, d->n_u, d->n_f, d->coef, d->expo, d->pow_u, d->pow_f, sp.ru, sp.rf);
+  if (cx) sp.coef = d->coef;
   if (qmcj::compile_only(sp, code_bytes) != 0) return fail(QMC_EINVAL, "%s", qmcj::last_error());
   return QMC_OK;
 }

@@ -120,6 +120,29 @@ def test_complex_with_vr_map(ctx):
     _both(ctx, desc, n, cbc.fast_cbc(n, 3), 6, 9, KOR3, vr=vr)
 
 
+def test_complex_vr_map_replaced(ctx):
+    """The specialised kernel of a deformed integrand holds its coefficients
+    and its map's parameters as constants: after set_vr with other parameters
+    (and after removing the map) each result follows the map in force."""
+    desc = W.sector(seed=29, dim=3, n_u=2, n_f=5, pow_u=-2.0, pow_f=-1.5, complex_=True, lam=0.5, neg_frac=0.3)
+    vr1 = np.array([[1.3, -0.4, 0.05, 0.1, 0.9, 0.05],
+                    [2.0, -1.5, 0.2, 0.0, 0.7, -0.1],
+                    [1.01, -0.01, 0.01, 0.02, 1.0, 0.0]])
+    vr2 = np.array([[1.8, -0.7, 0.1, 0.05, 0.8, 0.0],
+                    [1.2, -0.3, 0.0, 0.3, 0.6, 0.1],
+                    [3.0, -2.0, 0.3, 0.1, 0.5, 0.05]])
+    n = 4099
+    z = cbc.fast_cbc(n, 3)
+    f = ctx.integrand(desc)
+    for vr in (vr1, vr2, None, vr1):
+        f.set_vr(vr)
+        g = ctx.integrate(f, n, z, 6, 10, KOR3, sums=True)
+        assert g["path"] == ctx.path
+        o = oracle.shift_sums(desc, n, z, 6, oracle.shifts(10, 6, 3), KOR3, vr, threads=THREADS)
+        _check_sums(np.asarray(g["sums_re"])[o.ids], o, np.asarray(g["sums_im"])[o.ids])
+    f.close()
+
+
 def test_wrong_side_of_the_cut_is_flagged(ctx):
     """lambda < 0 deforms into Im F > 0: the result is still computed and the
     DEFORM_SIGN flag is raised, as the oracle counts such points too."""
