@@ -295,17 +295,23 @@ int run_batch_jobs(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_
   off = align256(off + n_rows * sizeof(qmck::RowRef));
   const size_t o_sh = off;
   off = align256(off + n_sh * 8);
+  // the variants' tile counters and the jobs' sign counts start at zero: they
+  // are part of the upload (zeros from the host), so a round needs no fill
+  // kernel; the sign counts are followed directly by the row results, and one
+  // copy returns both
+  const size_t o_cnt = off;
+  off = (off + (size_t)NV * 4 + 7) / 8 * 8;
+  const size_t o_sign = off;
+  off += (size_t)JT * 8;
   const size_t upload = off;  // everything above comes from the host
+  const size_t o_out = off;
+  off = align256(off + n_rows * 8);
   const size_t o_part = off;
   off = align256(off + n_part * 8);
-  const size_t o_out = off;
-  off = align256(off + n_rows * 8 + (size_t)JT * 8);
-  const size_t o_cnt = off;
-  off = align256(off + (size_t)NV * 4);
   char* ws = nullptr;
   int rc = scratch(c, off, &ws);
   if (rc) return rc;
-  rc = stage(c, std::max(upload, n_rows * 8 + (size_t)JT * 8));
+  rc = stage(c, std::max(upload, (size_t)JT * 8 + n_rows * 8));
   if (rc) return rc;
   char* h = (char*)c->h_stage;
   std::memset(h, 0, upload);
@@ -315,7 +321,7 @@ int run_batch_jobs(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_
   double* shifts = (double*)(h + o_sh);
   double* d_part = (double*)(ws + o_part);
   double* d_out = (double*)(ws + o_out);
-  unsigned long long* d_sign = (unsigned long long*)(ws + o_out + n_rows * 8);
+  unsigned long long* d_sign = (unsigned long long*)(ws + o_sign);
   for (uint32_t i = 0; i < JT; ++i) {
     const Plan& p = plan[i];
     BatchJob& b = *jobs[p.job];
@@ -421,8 +427,6 @@ int run_batch_jobs(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_
                            L.first, L.count, L.prefix_off, blocks_of[v]});
   }
   auto enqueue = [&](hipStream_t st) -> int {
-    HIPCHK(qmck::launch_fill_u32((uint32_t*)(ws + o_cnt), NV, 0u, st));
-    HIPCHK(qmck::launch_fill_u64(d_sign, JT, 0ull, st));
     for (uint32_t v = 0; v < (uint32_t)launches.size(); ++v) {
       const Launch& L = launches[v];
       if (L.jit) {
@@ -478,24 +482,25 @@ int run_batch_jobs(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_
     HIPCHK(hipEventRecord(c->ev0, c->stream));
     HIPCHK(hipGraphLaunch(ge, c->stream));
     HIPCHK(hipEventRecord(c->ev1, c->stream));
-    HIPCHK(hipMemcpyAsync(c->h_stage, d_out, n_rows * 8 + (size_t)JT * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(c->h_stage, d_sign, (size_t)JT * 8 + n_rows * 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
   } else {
     HIPCHK(hipEventRecord(c->ev0, c->stream));
     rc = enqueue(c->stream);
     if (rc) return rc;
     HIPCHK(hipEventRecord(c->ev1, c->stream));
-    HIPCHK(hipMemcpyAsync(c->h_stage, d_out, n_rows * 8 + (size_t)JT * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(c->h_stage, d_sign, (size_t)JT * 8 + n_rows * 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
   }
   float ms = 0;
   HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
   if (kernel_seconds) *kernel_seconds = ms * 1e-3;
-  const unsigned long long* sg = (const unsigned long long*)(c->h_stage + n_rows);
+  const unsigned long long* sg = (const unsigned long long*)c->h_stage;
+  const double* hout = c->h_stage + JT;  // the rows follow the sign counts
   for (uint32_t i = 0; i < J; ++i) {
     const Plan& p = plan[i];
     if (p.finish)
-      jobs[i]->sums.assign(c->h_stage + p.row0, c->h_stage + p.row0 + p.rows);
+      jobs[i]->sums.assign(hout + p.row0, hout + p.row0 + p.rows);
     else
       jobs[i]->sums.clear();
     jobs[i]->sign_points = sg[i];
@@ -505,9 +510,9 @@ int run_batch_jobs(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_
     if (p.twin >= 0) {
       const Plan& t = plan[p.twin];
       jobs[i]->fp32_dev.resize(p.rows);
-      jobs[i]->fp32_ref.assign(c->h_stage + t.row0, c->h_stage + t.row0 + p.rows);
+      jobs[i]->fp32_ref.assign(hout + t.row0, hout + t.row0 + p.rows);
       for (uint32_t r = 0; r < p.rows; ++r)
-        jobs[i]->fp32_dev[r] = c->h_stage[p.pref_row0 + r] - c->h_stage[t.row0 + r];
+        jobs[i]->fp32_dev[r] = hout[p.pref_row0 + r] - hout[t.row0 + r];
       uint64_t pts = 0;  // points of the sampled tiles (the last tile may be short)
       for (uint32_t q = 0; q < t.ktiles; ++q) {
         const uint64_t k0 = (uint64_t)q * kFp32SampleEvery * t.tile_points;

@@ -676,69 +676,76 @@ __device__ __forceinline__ void keep_branch() { asm volatile(""); }
 // Generic (table-driven) polynomial pieces for the deformed integrand.
 template <int DMAX>
 struct GenericComplex {
-  // gradient and Hessian of F at real x by exponent arithmetic (no division by x)
+  // Gradient and Hessian of F at real x.  For a monomial v = c prod_j x_j^e_j,
+  // dv/dx_j = v e_j / x_j and d2v/dx_j dx_l = v e_j (e_l - [j = l]) / (x_j x_l),
+  // so the monomial loop only accumulates G_j = sum v e_j and
+  // M_jl = sum v e_j (e_l - [j = l]) (an add or multiply-add per nonzero
+  // exponent, and per variable below each nonzero one), and the 1 / x factors
+  // are applied once per point.
+  // x_j = 0 (a point on a face; padding variables of a class kernel) is
+  // replaced by 2^-500 in v and 1/x: a power of two, so v / x_j stays exact for
+  // e_j = 1, and the terms with e_j >= 2 that it sends to about 0 are those
+  // that vanish at x_j = 0, apart from d2F/dx_j^2, which enters the
+  // determinant only times x_j (1 - x_j) = 0.
   __device__ __forceinline__ void grad_hess(const double (&x)[DMAX], double (&g)[DMAX], double (&H)[Tri<DMAX>::N],
                                             const EvalArgs& a) const {
+    double xs[DMAX], xs2[DMAX];
 #pragma unroll
-    for (int j = 0; j < DMAX; ++j) g[j] = 0.0;
+    for (int j = 0; j < DMAX; ++j) {
+      xs[j] = x[j] > 0.0 ? x[j] : 0x1p-500;
+      xs2[j] = xs[j] * xs[j];
+      g[j] = 0.0;
+    }
 #pragma unroll
     for (int j = 0; j < Tri<DMAX>::N; ++j) H[j] = 0.0;
     const cptr<double> C = as_const(a.coef);
     const cptr<uint32_t> E = as_const(a.expo);
     for (uint32_t i = a.n_u; i < a.n_u + a.n_f; ++i) {
-      const double c = C[i];
       const uint32_t w0 = E[2 * i], w1 = E[2 * i + 1];
       uint32_t e[DMAX];
 #pragma unroll
       for (int j = 0; j < DMAX; ++j) e[j] = mono_exp(w0, w1, j);
-      double P[DMAX], D1[DMAX], D2[DMAX];
+      double v = C[i];
 #pragma unroll
       for (int j = 0; j < DMAX; ++j) {
-        // x^e, e x^(e-1), e (e-1) x^(e-2)
-        double pe = 1.0, pe1 = 0.0, pe2 = 0.0;
+        if (e[j] != 0u) {
+          keep_branch();
+          v *= xpow<double>(xs[j], xs2[j], e[j]);
+        }
+      }
+      double t[DMAX];  // v e_j (0 where e_j = 0)
+#pragma unroll
+      for (int j = 0; j < DMAX; ++j) {
+        t[j] = 0.0;
         if (e[j] == 1u) {
           keep_branch();
-          pe = x[j];
-          pe1 = 1.0;
+          t[j] = v;
+          g[j] += v;
         } else if (e[j] >= 2u) {
           keep_branch();
-          double q2 = 1.0;  // x^(e-2)
-          for (uint32_t t = 2; t < e[j]; ++t) q2 *= x[j];
-          const double q1 = q2 * x[j];  // x^(e-1)
-          pe = q1 * x[j];
-          pe1 = (double)e[j] * q1;
-          pe2 = (double)(e[j] * (e[j] - 1u)) * q2;
+          t[j] = v * (double)e[j];
+          g[j] += t[j];
+          H[Tri<DMAX>::at(j, j)] = __builtin_fma(t[j], (double)(e[j] - 1u), H[Tri<DMAX>::at(j, j)]);
         }
-        P[j] = pe;
-        D1[j] = pe1;
-        D2[j] = pe2;
       }
-      double pre[DMAX + 1], suf[DMAX + 1];
-      pre[0] = c;
 #pragma unroll
-      for (int j = 0; j < DMAX; ++j) pre[j + 1] = pre[j] * P[j];
-      suf[DMAX] = 1.0;
-#pragma unroll
-      for (int j = DMAX - 1; j >= 0; --j) suf[j] = suf[j + 1] * P[j];
-#pragma unroll
-      for (int j = 0; j < DMAX; ++j) {
-        if (e[j] == 0u) continue;
+      for (int l = 1; l < DMAX; ++l) {
+        if (e[l] == 0u) continue;
         keep_branch();
-        g[j] = __builtin_fma(pre[j] * D1[j], suf[j + 1], g[j]);
-        if (e[j] >= 2u) {
-          keep_branch();
-          H[Tri<DMAX>::at(j, j)] = __builtin_fma(pre[j] * D2[j], suf[j + 1], H[Tri<DMAX>::at(j, j)]);
-        }
-        double mid = pre[j] * D1[j];  // c prod_{q<j} P_q * D1_j * prod_{j<q<l} P_q
+        const double el = (double)e[l];
+        // all earlier variables, t_j = 0 where e_j = 0: a multiply-add is
+        // cheaper than the scalar test and branch that would skip it
 #pragma unroll
-        for (int l = j + 1; l < DMAX; ++l) {
-          if (e[l] != 0u) {  // P_l = 1 otherwise
-            keep_branch();
-            H[Tri<DMAX>::at(l, j)] = __builtin_fma(mid * D1[l], suf[l + 1], H[Tri<DMAX>::at(l, j)]);
-            mid *= P[l];
-          }
-        }
+        for (int j = 0; j < l; ++j) H[Tri<DMAX>::at(l, j)] = __builtin_fma(t[j], el, H[Tri<DMAX>::at(l, j)]);
       }
+    }
+    double r[DMAX];
+#pragma unroll
+    for (int j = 0; j < DMAX; ++j) {
+      r[j] = fast_rcp(xs[j]);
+      g[j] *= r[j];
+#pragma unroll
+      for (int l = 0; l <= j; ++l) H[Tri<DMAX>::at(j, l)] *= r[j] * r[l];
     }
   }
   __device__ __forceinline__ cplx poly(const cplx (&z)[DMAX], uint32_t first, uint32_t count,
@@ -982,8 +989,21 @@ struct bounded_fn<Fn, decltype(void(Fn::kBounded))> {
   static constexpr bool value = Fn::kBounded;
 };
 
+// A functor with bind(a) reads what it needs of the arguments (the generated
+// kernels' coefficients) once, before the point loop.
+template <class Fn, class = void>
+struct fn_binder {
+  __device__ static void bind(Fn&, const EvalArgs&) {}
+};
+template <class Fn>
+struct fn_binder<Fn, decltype(void(&Fn::bind))> {
+  __device__ static void bind(Fn& f, const EvalArgs& a) { f.bind(a); }
+};
+
 template <int DMAX, int TK, bool IDX32, int S, bool EXACT, class Fn, int VRM = VRM_RUNTIME, bool COMP = false>
-__device__ __forceinline__ void eval_real_sched(const EvalArgs& a, const Fn& fn, const Sched& sc) {
+__device__ __forceinline__ void eval_real_sched(const EvalArgs& a, const Fn& fn0, const Sched& sc) {
+  Fn fn = fn0;
+  fn_binder<Fn>::bind(fn, a);
   const uint32_t s0 = sc.s0;
   const uint32_t ns = (a.m - s0) < sc.ns_max ? (a.m - s0) : sc.ns_max;
   const uint32_t dim = EXACT ? (uint32_t)DMAX : a.dim;

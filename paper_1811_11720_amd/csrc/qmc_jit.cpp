@@ -70,9 +70,16 @@ class Emitter {
     pows_[key] = n;
     return n;
   }
-  std::string header() const {
+  // The coefficients are members of the functor, read once per tile by
+  // bind() (through the constant address space: scalar loads) before the point
+  // loop.  Read inside the evaluation they sit in the shift loop's conditional
+  // block, where they are reloaded for every shift of every point.
+  std::string members() const {
     std::ostringstream o;
-    for (auto& kv : coefs_) o << "    const double " << kv.second << " = a.coef[" << kv.first << "];\n";
+    for (auto& kv : coefs_) o << "  double " << kv.second << ";\n";
+    o << "  __device__ __forceinline__ void bind(const EvalArgs& a) {\n";
+    for (auto& kv : coefs_) o << "    " << kv.second << " = as_const(a.coef)[" << kv.first << "];\n";
+    o << "  }\n";
     return o.str();
   }
   std::string pre() const { return pre_.str(); }
@@ -244,7 +251,7 @@ struct Val {
 // the point loop, where the table-read values of a large integrand overflow
 // the scalar registers and are spilled and reloaded at every point.
 std::string coef_value(const double* values, uint32_t i) {
-  if (!values) return "a.coef[" + std::to_string(i) + "]";
+  if (!values) return "as_const(a.coef)[" + std::to_string(i) + "]";
   char buf[64];
   std::snprintf(buf, sizeof buf, "%a", values[i]);
   return buf;
@@ -524,9 +531,10 @@ std::string generate(const Spec& s) {
   // the single-root form is only chosen when U and F are bounded away from 0
   // and infinity on [0, 1]^d, so f is finite there
   if (s.ru > 0 && s.rf > 0 && s.n_f) o << "  static constexpr bool kBounded = true;\n";
+  o << em.members();
   o << "  __device__ __forceinline__ double operator()(const double (&x)[" << d
     << "], const EvalArgs& a) const {\n";
-  o << em.header() << em.pre() << em.body();
+  o << em.pre() << em.body();
   if (s.ru > 0 && s.rf > 0 && s.n_f) {
     // U^ru F^rf by binary powering, then one reciprocal square root
     int nt = 0;

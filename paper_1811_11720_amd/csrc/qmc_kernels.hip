@@ -105,26 +105,34 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t count, uint32_t v, hipStream_t 
   return hipLaunchKernel((const void*)k_fill_u32, dim3((count + 255) / 256), dim3(256), args, 0, st);
 }
 
-__global__ __launch_bounds__(QMCD_BLOCK) void k_finalize_rows(const RowRef* __restrict__ rows,
+// Row sums in a fixed order that depends only on the row's own column count:
+// QMCD_BLOCK virtual threads v take columns v, v + QMCD_BLOCK, ... in turn,
+// each group of 64 consecutive virtual threads is summed by the xor butterfly,
+// and the group sums are added in order to 0.  One wave per row (four rows per
+// block): lane l plays virtual threads l, l + 64, l + 128 and l + 192; a row
+// with at most 64 columns leaves the last three groups at +0.
+__global__ __launch_bounds__(QMCD_BLOCK) void k_finalize_rows(const RowRef* __restrict__ rows, uint32_t nrows,
                                                               double* __restrict__ out) {
-  const RowRef r = rows[blockIdx.x];
-  double t = 0.0;
-  for (uint32_t i = threadIdx.x; i < r.ncols; i += QMCD_BLOCK) t += r.p[(size_t)i * (1u + r.skip)];
-  t = qmcd::wave_sum(t);
-  __shared__ double red[QMCD_BLOCK / 64];
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int w = 0; w < QMCD_BLOCK / 64; ++w) s += red[w];
-    out[blockIdx.x] = s;
+  const uint32_t row = blockIdx.x * (QMCD_BLOCK / 64) + (threadIdx.x >> 6);
+  if (row >= nrows) return;  // whole waves leave together
+  const RowRef r = rows[row];
+  const uint32_t lane = threadIdx.x & 63;
+  const size_t stride = 1u + (size_t)r.skip;
+  double s = 0.0;
+  const uint32_t groups = r.ncols > 64 ? QMCD_BLOCK / 64 : 1;
+  for (uint32_t w = 0; w < groups; ++w) {
+    double t = 0.0;
+    for (uint32_t i = w * 64 + lane; i < r.ncols; i += QMCD_BLOCK) t += r.p[(size_t)i * stride];
+    s += qmcd::wave_sum(t);
   }
+  if (lane == 0) out[row] = s;
 }
 
 hipError_t launch_finalize_rows(const RowRef* rows, uint32_t nrows, double* out, hipStream_t st) {
   if (nrows == 0) return hipSuccess;
-  void* args[] = {(void*)&rows, (void*)&out};
-  return hipLaunchKernel((const void*)k_finalize_rows, dim3(nrows), dim3(QMCD_BLOCK), args, 0, st);
+  void* args[] = {(void*)&rows, (void*)&nrows, (void*)&out};
+  const uint32_t per = QMCD_BLOCK / 64;
+  return hipLaunchKernel((const void*)k_finalize_rows, dim3((nrows + per - 1) / per), dim3(QMCD_BLOCK), args, 0, st);
 }
 
 extern BatchFn g_batch4[TKC_COUNT][2][2][3], g_batch6[TKC_COUNT][2][2][3], g_batch8[TKC_COUNT][2][2][3],

@@ -44,7 +44,13 @@ def test_paper_vectors_reach_the_minimum_under_equal_weights(ctx):
 def _first_divergence_equal(n, za, zb, rel):
     """Greedy vectors that part at some component: there both choices have the
     same worst-case error within `rel` (after it each step conditions on a
-    different prefix, so the rest is not comparable)."""
+    different prefix, so the rest is not comparable).  Which of two candidates
+    closer than an FFT construction's resolution of e^2 is taken depends on its
+    rounding, which grows with n: at n = 1e8 the convolution sums (size 14)
+    are off their direct sums by about 2e-12, 4e-7 of e^2 for two components;
+    at n = 5400001 the padded and mixed-radix constructions take second
+    components 1.5e-8 apart.  The tolerances are 1e-6 up to 5.4e6 and 1e-5
+    at 1e8."""
     if za == zb:
         return
     j = next(i for i in range(len(za)) if za[i] != zb[i])
@@ -130,7 +136,7 @@ def test_mixed_radix_cbc_matches_the_padded_path(ctx, n):
     greedy steps condition on different prefixes and may go their own ways."""
     assert cbc.is_prime(n) and _smooth7((n - 1) // 2)
     d = 6
-    _first_divergence_equal(n, _mixed(ctx, n, d), ctx.cbc(n, d), rel=1e-8)
+    _first_divergence_equal(n, _mixed(ctx, n, d), ctx.cbc(n, d), rel=1e-6)
 
 
 def test_cbc_beyond_2_31():
