@@ -138,10 +138,11 @@ def host_threads() -> int:
 
 def _oracle_rate(jobs, k, threads):
     """Oracle evals/s over all shifts of the points [0, min(k, n)) of each job.
-    With several threads the sample is cut into (job, point range) pieces of at
-    most 16384 points run on a pool of that many threads, each piece one
-    single-threaded oracle call (the oracle itself threads only over 16384-point
-    chunks of one lattice, so small jobs would otherwise run on one core)."""
+    With several threads the sample is cut into (job, point range) pieces, at
+    least four per thread and at most 16384 points each, run on a pool of that
+    many threads, each piece one single-threaded oracle call (the oracle itself
+    threads only over 16384-point chunks of one lattice, so small jobs would
+    otherwise run on one core)."""
     import oracle
     from concurrent.futures import ThreadPoolExecutor
 
@@ -149,7 +150,7 @@ def _oracle_rate(jobs, k, threads):
     for j in jobs:
         kk = min(k, j.n)
         sh = oracle.shifts(j.seed, j.m, j.desc.dim)
-        step = 16384 if threads > 1 else kk
+        step = kk if threads <= 1 else max(256, min(16384, -(-kk * len(jobs) // (4 * threads))))
         for a in range(0, kk, step):
             pieces.append((j, sh, a, min(kk, a + step)))
         ev += kk * j.m
@@ -917,6 +918,10 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
             "traffic": measured_traffic(job.n, job.m) if res["path"] == 1 else None,
+            # the counters cannot be read by the timed process itself: HBM bytes come from
+            # rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of this command, scaled by a copy
+            "traffic_source": "FETCH_SIZE and WRITE_SIZE runs of this command on the same kernel sources "
+                              "(hash-checked), scaled by a 1 GiB copy: " + os.path.relpath(TRAFFIC_FILE, ROOT),
             "kernel_ms": kern * 1e3,
             "evals_per_s_kernel": evals / kern,
         },

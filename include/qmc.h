@@ -322,8 +322,9 @@ int qmc_integrate_request(qmc_context* ctx, const qmc_request* req, qmc_result* 
  * integrands run here (U, F and powers in fp32, compensated fp64 sums).
  * shift_sums (optional) gets each request's per-shift sums of its last
  * lattice for its requested m shifts, back to back ([m] or [2m] each).
- * device_seconds is the batch's
- * total kernel time.
+ * device_seconds is the batch's total evaluation-kernel time, summed over its
+ * rounds (HIP events around each round's evaluation kernels; the row
+ * reduction after them is not included, as for a single lattice).
  */
 int qmc_integrate_batch(qmc_context* ctx, const qmc_request* reqs, uint32_t count,
                         qmc_result* out, double* shift_sums);

@@ -440,7 +440,15 @@ int run_batch_jobs(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_
                                 (const uint32_t*)(ws + o_prefix) + L.prefix_off, L.count,
                                 (uint32_t*)(ws + o_cnt) + v, blocks_of[v], st));
     }
-    HIPCHK(qmck::launch_finalize_rows((const qmck::RowRef*)(ws + o_rows), (uint32_t)n_rows, d_out, st));
+    return QMC_OK;
+  };
+  // the evaluation kernels lie between the context's two events (the
+  // reported device time, as for a single lattice); the row reduction follows
+  auto finish = [&]() -> int {
+    HIPCHK(hipEventRecord(c->ev1, c->stream));
+    HIPCHK(qmck::launch_finalize_rows((const qmck::RowRef*)(ws + o_rows), (uint32_t)n_rows, d_out, c->stream));
+    HIPCHK(hipMemcpyAsync(c->h_stage, d_sign, (size_t)JT * 8 + n_rows * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
     return QMC_OK;
   };
 
@@ -481,16 +489,14 @@ int run_batch_jobs(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_
     // the device interval starts here, after the host has built the graph
     HIPCHK(hipEventRecord(c->ev0, c->stream));
     HIPCHK(hipGraphLaunch(ge, c->stream));
-    HIPCHK(hipEventRecord(c->ev1, c->stream));
-    HIPCHK(hipMemcpyAsync(c->h_stage, d_sign, (size_t)JT * 8 + n_rows * 8, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
+    rc = finish();
+    if (rc) return rc;
   } else {
     HIPCHK(hipEventRecord(c->ev0, c->stream));
     rc = enqueue(c->stream);
     if (rc) return rc;
-    HIPCHK(hipEventRecord(c->ev1, c->stream));
-    HIPCHK(hipMemcpyAsync(c->h_stage, d_sign, (size_t)JT * 8 + n_rows * 8, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
+    rc = finish();
+    if (rc) return rc;
   }
   float ms = 0;
   HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
@@ -785,9 +791,9 @@ int autotune(qmc_context* c, const qmc_request* reqs, uint32_t count, uint32_t* 
     const std::vector<uint64_t> tiles = var.cplx ? std::vector<uint64_t>{512, 1024, 4096}
                                                  : std::vector<uint64_t>{1024, 4096, 16384};
     const int nsv = var.cplx ? 1 : qmck::BATCH_SV_VARIANTS;
-    // shifts per thread: all the kernel holds (0), or groups of 4 or 2, which
-    // trade fewer registers and more waves for more lattice-point work per
-    // evaluation; complex kernels already hold one shift per thread
+    // shifts per thread: all the kernel holds (0), or groups of 4 or 2: more,
+    // smaller tiles (a small batch spreads over more workgroups) for more
+    // index work per evaluation; complex kernels hold one shift per thread
     const std::vector<uint32_t> groups = var.cplx ? std::vector<uint32_t>{0} : std::vector<uint32_t>{0, 4, 2};
     double best = 1e300;
     int best_sv = 0;
