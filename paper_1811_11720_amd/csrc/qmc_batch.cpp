@@ -452,7 +452,9 @@ int run_batch_jobs(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_
     return QMC_OK;
   };
 
-  if (c->batch_graph) {
+  // a round of one evaluation kernel launches it directly: a graph of one node
+  // only adds launch latency (4% of the round for 1024 replicas of a small job)
+  if (c->batch_graph && launches.size() > 1) {
     // a round of the same shape as an earlier one replays that round's graph
     hipGraphExec_t ge = nullptr;
     for (auto& e : c->graphs)
@@ -737,6 +739,35 @@ static int variant_of(const qmc_request& q, qmck::BatchVariant& v) {
   v = qmck::BatchVariant{qmck::dim_class(f->dim, cplx), qmck::batch_tkc(tsel, f->has_vr), cplx,
                          (f->flags & QMC_EVAL_FP32) != 0};
   return QMC_OK;
+}
+
+// Default batch schedules of a new context, then the environment's overrides
+// (QMC_BATCH_SV, QMC_BATCH_GROUP, QMC_BATCH_TILE, QMC_BATCH_TILE_COMPLEX) and
+// the tune cache named by QMC_TUNE_CACHE.
+void batch_schedule_defaults(qmc_context* c) {
+  int force_sv = -1;
+  if (const char* v = std::getenv("QMC_BATCH_SV")) force_sv = atoi(v);  // one points-per-decode variant for all
+  for (int dc = 0; dc < 4; ++dc)
+    for (int tkc = 0; tkc < qmck::TKC_COUNT; ++tkc)
+      for (int f32 = 0; f32 < 2; ++f32) {
+        const int v = qmck::BatchVariant{dc, tkc, false, f32 != 0}.index();
+        // the autotuner's choices on MI355X: 4 points per decode (despite some
+        // spilling), except 2 for fp32 evaluation of at most 4 variables
+        c->batch_sv[v] = (f32 && dc == 0) ? 1 : 2;
+        if (force_sv >= 0 && force_sv < qmck::BATCH_SV_VARIANTS) c->batch_sv[v] = force_sv;
+      }
+  if (const char* v = std::getenv("QMC_BATCH_GROUP")) {  // shifts per thread of the real batch kernels (0: all 8)
+    const int g = atoi(v);
+    if (g >= 0 && g <= qmck::S_REAL)
+      for (int vi = 0; vi < qmck::BATCH_VARIANTS; ++vi) c->batch_group[vi] = (uint32_t)g;
+  }
+  if (const char* v = std::getenv("QMC_TUNE_CACHE")) {
+    c->tune_cache = v;
+    load_tune_cache(c);
+  }
+  if (const char* v = std::getenv("QMC_BATCH_TILE")) c->batch_tile_real = std::max(256ull, strtoull(v, nullptr, 10));
+  if (const char* v = std::getenv("QMC_BATCH_TILE_COMPLEX"))
+    c->batch_tile_complex = std::max(256ull, strtoull(v, nullptr, 10));
 }
 
 // Cache lines: "gfx950 <class's largest dimension> <tkc> <complex> <fp32> <sv index> <tile points>

@@ -236,6 +236,7 @@ void serve_shutdown(qmc_context* c);
 int serve_inflight(qmc_context* c);
 void free_context(qmc_context* c);
 void load_tune_cache(qmc_context* c);
+void batch_schedule_defaults(qmc_context* c);
 
 }  // namespace qmch
 

@@ -821,29 +821,7 @@ int qmc_context_create(int device, void* hip_stream, void* workspace, size_t wor
   if (const char* v = std::getenv("QMC_BATCH_GRAPH")) c->batch_graph = atoi(v) != 0;
   if (const char* v = std::getenv("QMC_SERVE_MEM")) c->serve_mem_limit = (size_t)strtoull(v, nullptr, 10);
   if (const char* v = std::getenv("QMC_SERVE_ROUND_COST")) c->serve_round_cost = std::max(1.0, atof(v));
-  int force_sv = -1;
-  if (const char* v = std::getenv("QMC_BATCH_SV")) force_sv = atoi(v);  // one points-per-decode variant for all
-  for (int dc = 0; dc < 4; ++dc)
-    for (int tkc = 0; tkc < qmck::TKC_COUNT; ++tkc)
-      for (int f32 = 0; f32 < 2; ++f32) {
-        const int v = qmck::BatchVariant{dc, tkc, false, f32 != 0}.index();
-        // measured on MI355X: fp64 variants are fastest at 4 points per decode
-        // (despite some spilling), fp32 ones at 2
-        c->batch_sv[v] = f32 ? 1 : 2;
-        if (force_sv >= 0 && force_sv < qmck::BATCH_SV_VARIANTS) c->batch_sv[v] = force_sv;
-      }
-  if (const char* v = std::getenv("QMC_BATCH_GROUP")) {  // shifts per thread of the real batch kernels (0: all 8)
-    const int g = atoi(v);
-    if (g >= 0 && g <= qmck::S_REAL)
-      for (int vi = 0; vi < qmck::BATCH_VARIANTS; ++vi) c->batch_group[vi] = (uint32_t)g;
-  }
-  if (const char* v = std::getenv("QMC_TUNE_CACHE")) {
-    c->tune_cache = v;
-    load_tune_cache(c);
-  }
-  if (const char* v = std::getenv("QMC_BATCH_TILE")) c->batch_tile_real = std::max(256ull, strtoull(v, nullptr, 10));
-  if (const char* v = std::getenv("QMC_BATCH_TILE_COMPLEX"))
-    c->batch_tile_complex = std::max(256ull, strtoull(v, nullptr, 10));
+  batch_schedule_defaults(c);  // default batch schedules, environment overrides, tune cache
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
     c->cus = cus;
