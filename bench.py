@@ -726,16 +726,18 @@ def bench_serve(a, Q, W, torch):
                     print(f"[serve] {k}/{len(reqs)} requests done", file=sys.stderr, flush=True)
             done.set()
 
+        # a Poisson process with exactly len(reqs) arrivals in [0, len(reqs) / rate]:
+        # its arrival times are that many sorted uniform draws over the span, so
+        # the realised rate is the nominal one (independent gaps would drift by
+        # sqrt(len(reqs)) gaps)
+        offsets = np.sort(rng.uniform(0.0, len(reqs) / rate, len(reqs))) if rate > 0 else np.zeros(len(reqs))
         th = threading.Thread(target=waiter)
         th.start()
         t0 = time.perf_counter()
-        t_next = t0
-        for q in reqs:
-            if rate > 0:
-                t_next += rng.exponential(1.0 / rate)
-                dt = t_next - time.perf_counter()
-                if dt > 0:
-                    time.sleep(dt)
+        for q, off in zip(reqs, offsets):
+            dt = t0 + off - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
             tickets.append((ctx.submit(q), len(q)))
         done.wait()
         th.join()
@@ -751,17 +753,24 @@ def bench_serve(a, Q, W, torch):
     reqs = [make(*q) for q in spec[4:4 + a.requests]]
     lat0, ev0, span0, conv0 = run(0, reqs)  # saturation: everything queued at once
     sat = len(reqs) / span0
-    print(f"[serve] saturation {sat:.2f} requests/s, {ev0 / span0:.3e} evals/s", file=sys.stderr, flush=True)
+    # requests differ in size (10-500 integrals): a load level is a fraction of the
+    # integrals per second served at saturation, turned into a request rate with
+    # the mean size of the requests that arrive at that level
+    sat_ips = sum(len(q) for q in reqs) / span0
+    print(f"[serve] saturation {sat:.2f} requests/s ({sat_ips:.0f} integrals/s), {ev0 / span0:.3e} evals/s",
+          file=sys.stderr, flush=True)
     pool_reqs = [make(*q) for q in spec[4 + a.requests:]]
+    mean_pool = float(np.mean([len(q) for q in pool_reqs]))
     rates = []
     for frac in a.rates:
         # about seconds_per_rate of arrivals at this rate, within [8, requests_max] requests
-        cnt = int(min(a.requests_max, max(8, round(frac * sat * a.seconds_per_rate))))
+        cnt = int(min(a.requests_max, max(8, round(frac * sat_ips / mean_pool * a.seconds_per_rate))))
         sub = pool_reqs[:cnt]
-        lat, ev, span, conv = run(frac * sat, sub)
+        rate = frac * sat_ips / float(np.mean([len(q) for q in sub]))
+        lat, ev, span, conv = run(rate, sub)
         print(f"[serve] load {frac}: {cnt} requests, p50 {np.percentile(lat, 50) * 1e3:.1f} ms, "
               f"p99 {np.percentile(lat, 99) * 1e3:.1f} ms", file=sys.stderr, flush=True)
-        rates.append({"load": frac, "arrival_rate_per_s": frac * sat, "requests": cnt,
+        rates.append({"load": frac, "arrival_rate_per_s": rate, "requests": cnt,
                       "requests_per_s": cnt / span,
                       "evals_per_s": ev / span, "p50_ms": float(np.percentile(lat, 50)) * 1e3,
                       "p99_ms": float(np.percentile(lat, 99)) * 1e3,
@@ -787,12 +796,13 @@ def bench_serve(a, Q, W, torch):
             "workload": f"serving: requests of {a.req_lo}-{a.req_hi} sector integrands, rel targets "
                         f"1e-8..1e-4, start n in [{a.n_lo:g}, {a.n_hi:g}], m={a.m}, growth through the lattice "
                         f"table, at most {a.max_evals:g} evaluations per integral; {len(reqs)} requests at "
-                        f"saturation, then Poisson arrivals at each load for about {a.seconds_per_rate:g} s "
+                        f"saturation, then Poisson arrivals at each load (a fraction of the integrals per "
+                        f"second served at saturation) for about {a.seconds_per_rate:g} s "
                         f"(8 to {a.requests_max} requests per load: fewer than the 1000 per rate a full sweep "
                         f"would take, to keep the run within minutes)",
             "requests_saturation": len(reqs),
         },
-        "saturation": {"requests_per_s": sat, "evals_per_s": ev0 / span0,
+        "saturation": {"requests_per_s": sat, "integrals_per_s": sat_ips, "evals_per_s": ev0 / span0,
                        "p50_ms": float(np.percentile(lat0, 50)) * 1e3,
                        "p99_ms": float(np.percentile(lat0, 99)) * 1e3},
         "latency_by_load": rates,

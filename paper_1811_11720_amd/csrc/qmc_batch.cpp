@@ -68,25 +68,31 @@ namespace {
 int run_batch_jobs(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_seconds);
 
 // Key of the jobs that can share one item: the integrand, the lattice and the
-// transform (the shifts are what differs).
-std::string merge_key(const BatchJob& b) {
-  std::string k;
-  const uint32_t dim = b.f->dim;
-  k.resize(sizeof(void*) + 8 + 3 * 4 + (size_t)dim * 8);
-  char* w = &k[0];
-  std::memcpy(w, &b.f, sizeof(void*));
-  w += sizeof(void*);
-  std::memcpy(w, &b.n, 8);
-  w += 8;
-  const int32_t t[3] = {b.t.kind, b.t.r0, b.t.r1};
-  std::memcpy(w, t, 12);
-  w += 12;
-  for (uint32_t j = 0; j < dim; ++j) {
-    const uint64_t zj = b.z[j] % b.n;
-    std::memcpy(w + 8 * j, &zj, 8);
+// transform (the shifts are what differs); generating vectors compare by their
+// components mod n.
+struct MergeKey {
+  const BatchJob* b;
+};
+struct MergeHash {
+  size_t operator()(const MergeKey& k) const {
+    const BatchJob& b = *k.b;
+    uint64_t h = (uint64_t)(uintptr_t)b.f * 0x9e3779b97f4a7c15ULL ^ b.n;
+    h = h * 0x100000001b3ULL ^ (uint64_t)(uint32_t)b.t.kind ^ ((uint64_t)(uint32_t)b.t.r0 << 20) ^
+        ((uint64_t)(uint32_t)b.t.r1 << 40);
+    for (uint32_t j = 0; j < b.f->dim; ++j) h = (h ^ (b.z[j] % b.n)) * 0x100000001b3ULL;
+    return (size_t)h;
   }
-  return k;
-}
+};
+struct MergeEq {
+  bool operator()(const MergeKey& x, const MergeKey& y) const {
+    const BatchJob &a = *x.b, &b = *y.b;
+    if (a.f != b.f || a.n != b.n || a.t.kind != b.t.kind || a.t.r0 != b.t.r0 || a.t.r1 != b.t.r1) return false;
+    if (a.z == b.z) return true;
+    for (uint32_t j = 0; j < a.f->dim; ++j)
+      if (a.z[j] % a.n != b.z[j] % b.n) return false;
+    return true;
+  }
+};
 
 }  // namespace
 
@@ -125,14 +131,14 @@ int run_batch(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_secon
   const uint32_t J = (uint32_t)jobs.size();
   if (kernel_seconds) *kernel_seconds = 0.0;
   if (J < 2) return run_batch_jobs(c, jobs, kernel_seconds);
-  std::unordered_map<std::string, uint32_t> slot;  // key -> index into work
+  std::unordered_map<MergeKey, uint32_t, MergeHash, MergeEq> slot;  // key -> index into members
   std::vector<std::vector<uint32_t>> members;
   std::vector<BatchJob*> work;
   std::vector<uint32_t> owner(J, UINT32_MAX);
   for (uint32_t i = 0; i < J; ++i) {
     const BatchJob& b = *jobs[i];
     if ((b.f->flags & QMC_DEFORM) || b.ext_partial || b.tile_count) continue;
-    auto ins = slot.emplace(merge_key(b), (uint32_t)members.size());
+    auto ins = slot.emplace(MergeKey{&b}, (uint32_t)members.size());
     if (ins.second) members.emplace_back();
     members[ins.first->second].push_back(i);
   }
@@ -566,11 +572,16 @@ int run_requests(qmc_context* c, const qmc_request* reqs, uint32_t count, qmc_re
   auto t0 = std::chrono::steady_clock::now();
   struct St {
     qmc_integrand* f;
-    std::vector<double> shifts;
-    std::vector<uint64_t> z;
+    const double* sh = nullptr;   // shift table: in the call's pool, or in shifts
+    std::vector<double> shifts;   // a table grown by the Monte Carlo fallback
+    const uint64_t* z = nullptr;  // the request's generating vector, or zown
+    std::vector<uint64_t> zown;   // a registered or grown lattice's
     uint64_t n;
     uint32_t mcur = 0, first_new = 0;  // shifts [first_new, mcur) run next
-    std::vector<double> sre, sim;      // per-shift sums at the current lattice
+    // per-shift sums at the current lattice: in job.sums when the round evaluated
+    // all of its shifts, else in sre, sim (the earlier shifts' sums kept there)
+    const double *re = nullptr, *im = nullptr;
+    std::vector<double> sre, sim;
     std::vector<double> dre, dim_;     // fp32 evaluation: per-shift sampled fp32 - fp64 sums
     std::vector<double> rre, rim;      // ... and sampled fp64 sums
     uint64_t signs = 0;
@@ -579,6 +590,11 @@ int run_requests(qmc_context* c, const qmc_request* reqs, uint32_t count, qmc_re
     BatchJob job;
   };
   std::vector<St> st(count);
+  size_t pool_size = 0;
+  for (uint32_t i = 0; i < count; ++i)
+    if (reqs[i].f && reqs[i].m <= QMC_MAX_SHIFTS) pool_size += (size_t)reqs[i].m * reqs[i].f->dim;
+  std::vector<double> pool(pool_size);  // every request's first shift table
+  size_t pool_off = 0;
   // requests usually share generating vectors: each (z, n, dim) is checked once
   const uint64_t* ok_z = nullptr;
   uint64_t ok_n = 0;
@@ -601,20 +617,23 @@ int run_requests(qmc_context* c, const qmc_request* reqs, uint32_t count, qmc_re
         ok_dim = dim;
       }
       s.n = q.n;
-      s.z.assign(q.z, q.z + dim);
+      s.z = q.z;  // the caller's array outlives the call
     } else {
       uint64_t nn = 0;
-      if (next_registered(c, q.n, dim, &nn, true, &s.z) != QMC_OK)
+      if (next_registered(c, q.n, dim, &nn, true, &s.zown) != QMC_OK)
         return fail(QMC_ENOTFOUND, "request %u: no registered lattice with %u components", i, dim);
       s.n = nn;
+      s.z = s.zown.data();
     }
-    s.shifts.resize((size_t)q.m * dim);
-    make_shifts(q.seed, q.m, dim, s.shifts.data());
+    make_shifts(q.seed, q.m, dim, pool.data() + pool_off);
+    s.sh = pool.data() + pool_off;
+    pool_off += (size_t)q.m * dim;
     s.mcur = q.m;
     s.r.m = q.m;
     s.r.path = 2;
   }
   double dev = 0.0;
+  std::vector<double> qs;  // one shift-mean buffer for every estimate
   for (;;) {
     std::vector<BatchJob*> jobs;
     std::vector<uint32_t> idx;
@@ -623,9 +642,9 @@ int run_requests(qmc_context* c, const qmc_request* reqs, uint32_t count, qmc_re
       if (s.done) continue;
       s.job.f = s.f;
       s.job.n = s.n;
-      s.job.z = s.z.data();
+      s.job.z = s.z;
       s.job.m = s.mcur - s.first_new;
-      s.job.shifts = s.shifts.data() + (size_t)s.first_new * s.f->dim;
+      s.job.shifts = s.sh + (size_t)s.first_new * s.f->dim;
       s.job.t = reqs[i].t;
       jobs.push_back(&s.job);
       idx.push_back(i);
@@ -640,13 +659,19 @@ int run_requests(qmc_context* c, const qmc_request* reqs, uint32_t count, qmc_re
       const qmc_request& q = reqs[i];
       const bool cplx = (s.f->flags & QMC_DEFORM) != 0;
       const uint32_t madd = s.mcur - s.first_new, m = s.mcur;
-      s.sre.resize(s.first_new);
-      s.sim.resize(s.first_new);
-      s.sre.insert(s.sre.end(), s.job.sums.begin(), s.job.sums.begin() + madd);
-      if (cplx)
-        s.sim.insert(s.sim.end(), s.job.sums.begin() + madd, s.job.sums.begin() + 2 * (size_t)madd);
-      else
-        s.sim.resize(m, 0.0);
+      if (s.first_new == 0) {  // this round evaluated every shift of the lattice
+        s.re = s.job.sums.data();
+        s.im = cplx ? s.job.sums.data() + madd : nullptr;
+      } else {  // shifts added by the Monte Carlo fallback: append to the kept sums
+        s.sre.resize(s.first_new);
+        s.sre.insert(s.sre.end(), s.job.sums.begin(), s.job.sums.begin() + madd);
+        s.re = s.sre.data();
+        if (cplx) {
+          s.sim.resize(s.first_new);
+          s.sim.insert(s.sim.end(), s.job.sums.begin() + madd, s.job.sums.begin() + 2 * (size_t)madd);
+          s.im = s.sim.data();
+        }
+      }
       s.signs = (s.first_new ? s.signs : 0) + s.job.sign_points;
       if (!s.job.fp32_dev.empty()) {
         auto keep = [&](std::vector<double>& re, std::vector<double>& im, const std::vector<double>& rows) {
@@ -665,12 +690,12 @@ int run_requests(qmc_context* c, const qmc_request* reqs, uint32_t count, qmc_re
       s.r.evaluations += s.n * (uint64_t)madd;
       s.r.n = s.n;
       s.r.m = m;
-      std::vector<double> qs(m);
-      for (uint32_t k = 0; k < m; ++k) qs[k] = s.sre[k] / (double)s.n;
+      qs.resize(m);
+      for (uint32_t k = 0; k < m; ++k) qs[k] = s.re[k] / (double)s.n;
       estimate(qs.data(), m, s.r.re, s.r.err_re);
       s.r.im = s.r.err_im = 0.0;
       if (cplx) {
-        for (uint32_t k = 0; k < m; ++k) qs[k] = s.sim[k] / (double)s.n;
+        for (uint32_t k = 0; k < m; ++k) qs[k] = s.im[k] / (double)s.n;
         estimate(qs.data(), m, s.r.im, s.r.err_im);
       }
       if (!s.job.fp32_dev.empty())
@@ -696,13 +721,18 @@ int run_requests(qmc_context* c, const qmc_request* reqs, uint32_t count, qmc_re
         s.done = true;
       } else if (g.kind == GrowthStep::LATTICE) {
         s.n = g.n;
-        s.z.swap(g.z);
+        s.zown.swap(g.z);
+        s.z = s.zown.data();
         s.first_new = 0;
       } else {
+        // the next round overwrites job.sums: keep this lattice's sums
+        if (s.re != s.sre.data()) s.sre.assign(s.re, s.re + m);
+        if (cplx && s.im != s.sim.data()) s.sim.assign(s.im, s.im + m);
         s.first_new = m;
         s.mcur = g.m;
         s.shifts.resize((size_t)g.m * s.f->dim);
         make_shifts(q.seed, g.m, s.f->dim, s.shifts.data());
+        s.sh = s.shifts.data();
       }
     }
   }
@@ -715,10 +745,10 @@ int run_requests(qmc_context* c, const qmc_request* reqs, uint32_t count, qmc_re
     if (out) out[i] = s.r;
     if (shift_sums) {  // the requested m shifts of each request
       const uint32_t m = reqs[i].m;
-      std::memcpy(shift_sums + off, s.sre.data(), (size_t)m * 8);
+      std::memcpy(shift_sums + off, s.re, (size_t)m * 8);
       off += m;
       if (s.f->flags & QMC_DEFORM) {
-        std::memcpy(shift_sums + off, s.sim.data(), (size_t)m * 8);
+        std::memcpy(shift_sums + off, s.im, (size_t)m * 8);
         off += m;
       }
     }
