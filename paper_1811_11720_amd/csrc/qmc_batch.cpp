@@ -174,11 +174,17 @@ int run_batch(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_secon
   int rc = run_batch_jobs(c, work, kernel_seconds);
   if (rc) return rc;
   std::vector<uint32_t> at(merged.size(), 0);  // next shift of each merged job
+  // the members read their rows in place from the merged job's (shared) rows
+  std::vector<std::shared_ptr<const std::vector<double>>> rows_of(merged.size());
+  for (size_t g = 0; g < merged.size(); ++g)
+    rows_of[g] = std::make_shared<const std::vector<double>>(std::move(merged[g].sums));
   for (uint32_t i = 0; i < J; ++i) {
     if (owner[i] == UINT32_MAX) continue;
     const BatchJob& mj = merged[owner[i]];
     const uint32_t s0 = at[owner[i]];
-    jobs[i]->sums.assign(mj.sums.begin() + s0, mj.sums.begin() + s0 + jobs[i]->m);
+    jobs[i]->sums.clear();
+    jobs[i]->sums_keep = rows_of[owner[i]];
+    jobs[i]->sums_at = rows_of[owner[i]]->data() + s0;
     jobs[i]->sign_points = 0;
     jobs[i]->fp32_dev.clear();
     jobs[i]->fp32_ref.clear();
@@ -320,7 +326,11 @@ int run_batch_jobs(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_
   rc = stage(c, std::max(upload, (size_t)JT * 8 + n_rows * 8));
   if (rc) return rc;
   char* h = (char*)c->h_stage;
-  std::memset(h, 0, upload);
+  // zeros where the loop below writes only some fields (the argument table) and
+  // for the counters and sign counts; every row reference and every shift is
+  // written in full, so those (large) regions are not cleared first
+  std::memset(h, 0, o_rows);
+  std::memset(h + o_cnt, 0, upload - o_cnt);
 
   qmcd::EvalArgs* items = (qmcd::EvalArgs*)(h + o_items);
   qmck::RowRef* rows = (qmck::RowRef*)(h + o_rows);
@@ -345,6 +355,7 @@ int run_batch_jobs(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_
       for (uint32_t r = 0; r < p.rows; ++r) {
         rows[p.row0 + r].p = d_part + p.part_off + (size_t)r * p.ktiles;
         rows[p.row0 + r].ncols = p.ktiles;
+        rows[p.row0 + r].skip = 0;
         rows[plan[p.job].pref_row0 + r].p = jp + (size_t)r * plan[p.job].ktiles;
         rows[plan[p.job].pref_row0 + r].ncols = p.ktiles;
         rows[plan[p.job].pref_row0 + r].skip = kFp32SampleEvery - 1;
@@ -373,10 +384,11 @@ int run_batch_jobs(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_
     a.shift_group = p.group_size;
     a.item = i;
     std::memcpy(shifts + p.sh_off, b.shifts, (size_t)b.m * b.f->dim * 8);
-    if (p.finish)
+    if (p.finish)  // a slice that does not finish its lattice owns no rows
       for (uint32_t r = 0; r < p.rows; ++r) {
         rows[p.row0 + r].p = part + (size_t)r * p.ktiles;
         rows[p.row0 + r].ncols = p.ktiles;
+        rows[p.row0 + r].skip = 0;
       }
   }
   uint32_t* order = (uint32_t*)(h + o_order);
@@ -517,6 +529,8 @@ int run_batch_jobs(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_
       jobs[i]->sums.assign(hout + p.row0, hout + p.row0 + p.rows);
     else
       jobs[i]->sums.clear();
+    jobs[i]->sums_at = jobs[i]->sums.data();
+    jobs[i]->sums_keep.reset();
     jobs[i]->sign_points = sg[i];
     jobs[i]->fp32_dev.clear();
     jobs[i]->fp32_ref.clear();
@@ -660,15 +674,15 @@ int run_requests(qmc_context* c, const qmc_request* reqs, uint32_t count, qmc_re
       const bool cplx = (s.f->flags & QMC_DEFORM) != 0;
       const uint32_t madd = s.mcur - s.first_new, m = s.mcur;
       if (s.first_new == 0) {  // this round evaluated every shift of the lattice
-        s.re = s.job.sums.data();
-        s.im = cplx ? s.job.sums.data() + madd : nullptr;
+        s.re = s.job.sums_at;
+        s.im = cplx ? s.job.sums_at + madd : nullptr;
       } else {  // shifts added by the Monte Carlo fallback: append to the kept sums
         s.sre.resize(s.first_new);
-        s.sre.insert(s.sre.end(), s.job.sums.begin(), s.job.sums.begin() + madd);
+        s.sre.insert(s.sre.end(), s.job.sums_at, s.job.sums_at + madd);
         s.re = s.sre.data();
         if (cplx) {
           s.sim.resize(s.first_new);
-          s.sim.insert(s.sim.end(), s.job.sums.begin() + madd, s.job.sums.begin() + 2 * (size_t)madd);
+          s.sim.insert(s.sim.end(), s.job.sums_at + madd, s.job.sums_at + 2 * (size_t)madd);
           s.im = s.sim.data();
         }
       }

@@ -190,6 +190,10 @@ struct BatchJob {
   double* ext_partial = nullptr;
   bool finish = true;
   std::vector<double> sums;  // out: rows (m or 2m), when finished
+  // where the rows are: sums.data(), or a range of the rows of the job it was
+  // merged into (replicas of one lattice), kept alive by sums_keep
+  const double* sums_at = nullptr;
+  std::shared_ptr<const std::vector<double>> sums_keep;
   uint64_t sign_points = 0;  // out: points of this call's tiles with Im F(z) > 0
   // out, QMC_EVAL_FP32 jobs: per row, over a sample of the lattice's points
   // (every kFp32SampleEvery-th tile), the sum of the fp32-evaluated

@@ -259,11 +259,11 @@ static void scheduler(qmc_context* c, qmc_serve_state* s) {
       r.r.evaluations += r.n * (uint64_t)m;
       r.r.n = r.n;
       std::vector<double> qs(m);
-      for (uint32_t k = 0; k < m; ++k) qs[k] = r.job.sums[k] / (double)r.n;
+      for (uint32_t k = 0; k < m; ++k) qs[k] = r.job.sums_at[k] / (double)r.n;
       estimate(qs.data(), m, r.r.re, r.r.err_re);
       r.r.im = r.r.err_im = 0.0;
       if (cplx) {
-        for (uint32_t k = 0; k < m; ++k) qs[k] = r.job.sums[m + k] / (double)r.n;
+        for (uint32_t k = 0; k < m; ++k) qs[k] = r.job.sums_at[m + k] / (double)r.n;
         estimate(qs.data(), m, r.r.im, r.r.err_im);
       }
       if (!r.job.fp32_dev.empty()) {
