@@ -8,6 +8,9 @@ of the method that are plain arithmetic on m numbers:
   * estimate and error from the m per-shift estimates (Sec. 2.1, eqs. lattice
     and lattice-error);
   * the error goal, real and complex ("all" / "largest", App. A.1 errormode);
+  * the variance-reduction fit (Sec. 2.4, eq. ISfit, App. A.5): bounded
+    nonlinear least squares of the PolySingular map against the sampled
+    inverse CDF, scipy's solver serving as the library routine;
   * the "Case 1" growth loop (Sec. 3.3.1): evaluate minm shifts of the
     smallest lattice >= minn, discard and move to a larger lattice until the
     goal or maxeval is reached; only the last result counts.  The next size
@@ -88,6 +91,8 @@ def lib():
             getattr(L, f).argtypes = [C.c_double, C.c_int]
             getattr(L, f).restype = C.c_double
         L.oracle_vr_map.argtypes = [dp, C.c_double, dp, dp]
+        L.oracle_vr_residuals.argtypes = [dp, dp, dp, C.c_uint32, dp]
+        L.oracle_vr_residuals.restype = None
         L.oracle_eval_point.argtypes = [C.POINTER(_Desc), dp, dp, dp]
         L.oracle_eval_point.restype = C.c_int
         L.oracle_shift_sums.argtypes = [
@@ -177,6 +182,70 @@ def vr_map(a, y):
     dx = C.c_double()
     lib().oracle_vr_map(_dp(a), float(y), C.byref(x), C.byref(dx))
     return x.value, dx.value
+
+
+# ---------------------------------------------------------------- variance-reduction fit
+
+
+VR_IDENTITY = (2.0, -1.0, 0.0, 0.0, 1.0, 0.0)
+
+
+def vr_cdf_points(hist) -> tuple[np.ndarray, np.ndarray]:
+    """Points (C_b, e_b), b = 0..bins, of one dimension's inverse CDF (Sec. 2.4,
+    eq. CDF): e_b = b / bins are the bin edges and C_b the fraction of the
+    histogram's weight below e_b."""
+    h = np.asarray(hist, dtype=np.float64)
+    bins = h.size
+    tot = math.fsum(h)
+    run = np.concatenate([[0.0], np.cumsum(h)])
+    cdf = np.minimum(1.0, run / tot)
+    cdf[-1] = 1.0
+    return cdf, np.arange(bins + 1) / bins
+
+
+def vr_fit_cost(a, hist) -> float:
+    """Half the sum of squared residuals p(C_b; a) - e_b over the inverse-CDF
+    points of one dimension."""
+    cdf, edge = vr_cdf_points(hist)
+    r = np.empty(cdf.size)
+    lib().oracle_vr_residuals(_dp(np.ascontiguousarray(a, dtype=np.float64)), _dp(cdf), _dp(edge), cdf.size, _dp(r))
+    return 0.5 * math.fsum(r * r)
+
+
+def fit_vr(hist) -> np.ndarray:
+    """PolySingular parameters (App. A.5) fitted to each row's inverse CDF by
+    bounded nonlinear least squares (Sec. 2.4): the paper fits eq. ISfit to the
+    sampled inverse CDF with a library least-squares routine under the bounds
+    a0 >= 1.001, a1 <= -0.001 and positive a2, a3.  Here the library routine is
+    scipy's trust-region reflective solver, run to tight tolerances; rows with
+    no weight get the identity map.  Returns [rows, 6]."""
+    from scipy.optimize import least_squares
+
+    h = np.atleast_2d(np.asarray(hist, dtype=np.float64))
+    out = np.empty((h.shape[0], 6))
+    lo = [1.001, -np.inf, 0.0, 0.0, -np.inf, -np.inf]
+    hi = [np.inf, -0.001, np.inf, np.inf, np.inf, np.inf]
+    for j, row in enumerate(h):
+        tot = math.fsum(row)
+        if not (tot > 0.0 and math.isfinite(tot)):
+            out[j] = VR_IDENTITY
+            continue
+        cdf, edge = vr_cdf_points(row)
+        r = np.empty(cdf.size)
+
+        def res(a):
+            lib().oracle_vr_residuals(_dp(np.ascontiguousarray(a)), _dp(cdf), _dp(edge), cdf.size, _dp(r))
+            return r.copy()
+
+        best = None
+        for p0 in (1.002, 1.02, 1.2, 2.0):
+            for p1 in (-0.002, -0.02, -0.2, -1.0):
+                sol = least_squares(res, x0=[p0, p1, 0.05, 0.05, 1.0, 0.0], bounds=(lo, hi), method="trf",
+                                    xtol=1e-12, ftol=1e-12, gtol=1e-12, max_nfev=300)
+                if best is None or sol.cost < best.cost:
+                    best = sol
+        out[j] = best.x
+    return out
 
 
 def eval_point(desc, x) -> complex:

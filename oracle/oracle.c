@@ -202,6 +202,17 @@ void oracle_vr_map(const double* a, double y, double* x, double* dxdy) {
           p4 + 2.0 * p5 * y + 3.0 * c3 * y * y;
 }
 
+/* Residuals of the variance-reduction fit (Sec. 2.4): the map p of eq. ISfit
+   is fitted to the inverse of the per-dimension CDF, sampled at the points
+   (cdf[b], edge[b]); r[b] = p(cdf[b]; a) - edge[b]. */
+void oracle_vr_residuals(const double* a, const double* cdf, const double* edge, uint32_t count, double* r) {
+  for (uint32_t b = 0; b < count; ++b) {
+    double x, dx;
+    oracle_vr_map(a, cdf[b], &x, &dx);
+    r[b] = x - edge[b];
+  }
+}
+
 /* ------------------------------------------------------------------ */
 /* integrand f = prefactor * U^pow_u * F^pow_f                          */
 

@@ -6,8 +6,11 @@
 // of App. A.5, with |p2| and |p3|) should be the inverse CDF, so it is fitted
 // to the points (C_b, e_b) by unweighted nonlinear least squares:
 //   r_b(a) = p(C_b; a) - e_b,  b = 0..bins.
-// Levenberg-Marquardt with the analytic Jacobian; after every step the poles
-// are projected back to p0 >= 1.001 and p1 <= -0.001 (the paper's bounds).
+// Levenberg-Marquardt with the analytic Jacobian under the paper's bounds
+// p0 >= 1.001, p1 <= -0.001, p2 >= 0, p3 >= 0: a parameter that sits on its
+// bound while the gradient points out of the box is held fixed for that step
+// (without this, |p3| of a term that wants to vanish flips sign at every step
+// and the fit crawls), and every step is projected back into the box.
 // Stopping rules follow the paper's defaults (App. A.1): at most 40 iterations,
 // step tolerance 3e-3, gradient tolerance 1e-8, cost tolerance 1e-8.  A fit is
 // accepted only if p' > 0 on a 4097-point grid; otherwise the identity map is
@@ -49,9 +52,14 @@ struct Model {
   }
 };
 
+constexpr double kLo[6] = {1.001, -HUGE_VAL, 0.0, 0.0, -HUGE_VAL, -HUGE_VAL};
+constexpr double kHi[6] = {HUGE_VAL, -0.001, HUGE_VAL, HUGE_VAL, HUGE_VAL, HUGE_VAL};
+
 void project(double* a) {
-  if (!(a[0] >= 1.001)) a[0] = 1.001;
-  if (!(a[1] <= -0.001)) a[1] = -0.001;
+  for (int i = 0; i < 6; ++i) {
+    if (!(a[i] >= kLo[i])) a[i] = kLo[i];
+    if (!(a[i] <= kHi[i])) a[i] = kHi[i];
+  }
 }
 
 double cost(const double* a, const std::vector<double>& C, const std::vector<double>& e) {
@@ -138,16 +146,21 @@ bool fit_dimension(const double* hist, uint32_t bins, double* a) {
         for (int k = 0; k < 6; ++k) A[i][k] += grad[i] * grad[k];
       }
     }
+    // held: on a bound with the descent direction -g leaving the box
+    bool held[6];
     double gmax = 0.0;
-    for (int i = 0; i < 6; ++i) gmax = std::max(gmax, std::fabs(g[i]));
+    for (int i = 0; i < 6; ++i) {
+      held[i] = (x[i] <= kLo[i] && g[i] > 0.0) || (x[i] >= kHi[i] && g[i] < 0.0);
+      if (!held[i]) gmax = std::max(gmax, std::fabs(g[i]));
+    }
     if (gmax <= gtol) break;
     bool accepted = false;
     for (int tries = 0; tries < 12 && !accepted; ++tries) {
       double M[6][6], d[6];
       for (int i = 0; i < 6; ++i) {
-        for (int k = 0; k < 6; ++k) M[i][k] = A[i][k];
-        M[i][i] += mu * std::max(A[i][i], 1e-12);
-        d[i] = -g[i];
+        for (int k = 0; k < 6; ++k) M[i][k] = (held[i] || held[k]) ? 0.0 : A[i][k];
+        M[i][i] = held[i] ? 1.0 : M[i][i] + mu * std::max(A[i][i], 1e-12);
+        d[i] = held[i] ? 0.0 : -g[i];
       }
       if (!solve6(M, d)) {
         mu *= 4.0;

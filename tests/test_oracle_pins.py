@@ -555,6 +555,54 @@ def test_histogram_marginals_of_a_separable_integrand():
         assert np.max(np.abs(cdf - want)) < 2e-4
 
 
+# ------------------------------------------------------------------ VR fit
+
+
+def _bins_of_cdf(cdf, bins=1024):
+    e = np.arange(bins + 1) / bins
+    return np.diff(cdf(e))
+
+
+@pytest.mark.parametrize("c", [0.02, 0.3])
+def test_vr_fit_inverts_a_pole_density_below_zero(c):
+    """Sec. 2.4: a density proportional to 1/(c + x)^2 has the CDF
+    x (1 + c) / (c + x), whose inverse y c / (1 + c - y) is eq. ISfit's first
+    pole term alone (a0 = 1 + c, a2 = 1, the rest zero); the histogram holds the
+    exact bin integrals, so the least-squares fit reaches that inverse."""
+    h = _bins_of_cdf(lambda x: x * (1 + c) / (c + x))
+    a = oracle.fit_vr(h)[0]
+    y = np.linspace(0, 1, 257)
+    got = np.array([oracle.vr_map(a, t)[0] for t in y])
+    assert np.max(np.abs(got - y * c / (1 + c - y))) < 1e-9
+    assert oracle.vr_fit_cost(a, h) < 1e-18
+
+
+@pytest.mark.parametrize("c", [0.05, 0.5])
+def test_vr_fit_inverts_a_pole_density_above_one(c):
+    """A density proportional to 1/(1 + c - x)^2 has the CDF x c / (1 + c - x),
+    whose inverse y (1 + c) / (c + y) is the second pole term (a1 = -c, a3 = 1)."""
+    h = _bins_of_cdf(lambda x: x * c / (1 + c - x))
+    a = oracle.fit_vr(h)[0]
+    y = np.linspace(0, 1, 257)
+    got = np.array([oracle.vr_map(a, t)[0] for t in y])
+    assert np.max(np.abs(got - y * (1 + c) / (c + y))) < 1e-9
+
+
+def test_vr_fit_of_a_flat_histogram_is_the_identity_within_the_bounds():
+    """A flat histogram has the CDF x itself; the paper's bounds hold for every
+    fit (a0 >= 1.001, a1 <= -0.001, a2 and a3 positive), and an empty row gets
+    the identity map."""
+    x = (np.arange(512) + 0.5) / 512
+    h = np.vstack([np.ones(512), np.exp(-8 * (x - 0.3) ** 2), np.zeros(512)])
+    a = oracle.fit_vr(h)
+    y = np.linspace(0, 1, 129)
+    got = np.array([oracle.vr_map(a[0], t)[0] for t in y])
+    assert np.max(np.abs(got - y)) < 1e-9
+    for row in a[:2]:
+        assert row[0] >= 1.001 and row[1] <= -0.001 and row[2] >= 0 and row[3] >= 0
+    assert tuple(a[2]) == oracle.VR_IDENTITY
+
+
 # ------------------------------------------------------------------ growth loop
 
 
