@@ -210,8 +210,10 @@ int qmc_histogram(qmc_context* ctx, const qmc_integrand* f, uint64_t n, const ui
 
 /*
  * Fit the PolySingular map of eq. ISfit (App. A.5) to the inverse CDF of
- * each dimension's histogram by Levenberg-Marquardt (host only, no GPU):
- * params[6*j + 0..5] receives (p0..p5) with p0 >= 1.001, p1 <= -0.001.  A
+ * each dimension's histogram by Levenberg-Marquardt under the paper's
+ * bounds (host only, no GPU; App. A.1's default stopping rule: 40
+ * iterations, step tolerance 3e-3): params[6*j + 0..5] receives (p0..p5)
+ * with p0 >= 1.001, p1 <= -0.001, p2 >= 0, p3 >= 0.  A
  * dimension whose fit is not strictly increasing on [0,1] gets the identity
  * map and its bit in *fallback_mask (optional).  hist: host [dim * bins].
  */
