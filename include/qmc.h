@@ -170,7 +170,6 @@ typedef struct {
 /* Copy a descriptor to the device (one host-to-device copy). */
 int qmc_create_integrand(qmc_context* ctx, const qmc_integrand_desc* desc, qmc_integrand** out);
 
-/* Free; QMC_EBUSY while a pending request references it. */
 /*
  * One of the six Genz test functions the paper benchmarks (Sec. 5.3):
  * family 1 oscillatory cos(2 pi w_1 + sum c_i x_i), 2 product peak
@@ -183,6 +182,9 @@ int qmc_create_integrand(qmc_context* ctx, const qmc_integrand_desc* desc, qmc_i
  */
 int qmc_create_genz(qmc_context* ctx, int family, uint32_t dim, const double* c, const double* w,
                     qmc_integrand** out);
+
+/* Free an integrand made by qmc_create_integrand or qmc_create_genz;
+ * QMC_EBUSY while a pending request references it. */
 int qmc_destroy_integrand(qmc_integrand* f);
 
 /*
