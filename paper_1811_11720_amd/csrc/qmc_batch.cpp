@@ -200,13 +200,22 @@ int run_batch(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_secon
 
 namespace {
 
+// Launch key of a table-driven job: its variant's index, made negative for a
+// complex job with a general power (neither integer nor half-integer), which
+// needs the kernels that hold the complex logarithm and exponential; the
+// others run in the leaner integer-and-half-integer kernels.
+int launch_key(const qmck::BatchVariant& v, const qmc_integrand* f) {
+  const bool general = f->pu_mode == qmcd::PW_GEN || (f->n_f && f->pf_mode == qmcd::PW_GEN);
+  return (v.cplx && general) ? -1 - v.index() : v.index();
+}
+
 int run_batch_jobs(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_seconds) {
   const uint32_t J = (uint32_t)jobs.size();
   if (kernel_seconds) *kernel_seconds = 0.0;
   if (J == 0) return QMC_OK;
   struct Plan {
     qmck::BatchVariant var;
-    int variant;  // var.index()
+    int variant;  // launch key: launch_key(var, f), or past BATCH_VARIANTS for a specialised kernel
     uint32_t rows, ktiles, groups, group_size;
     uint64_t tile_points;
     size_t part_off, sh_off, row0;
@@ -231,7 +240,7 @@ int run_batch_jobs(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_
     int trc = batch_job_shape(c, b, sh);
     if (trc) return trc;
     p.var = sh.var;
-    p.variant = p.var.index();
+    p.variant = launch_key(p.var, f);
     if (sh.use_jit) {
       // jobs of one specialised kernel form a launch of their own
       p.use_jit = true;
@@ -273,7 +282,7 @@ int run_batch_jobs(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_
     t.job = i;
     t.tiles = 0;
     t.var.fp32 = false;
-    t.variant = t.var.index();
+    t.variant = launch_key(t.var, jobs[i]->f);
     t.use_jit = false;
     t.ktiles = batch_fp32_sample_tiles(plan[i].ktiles);
     t.tiles = t.ktiles * t.groups;
@@ -438,7 +447,8 @@ int run_batch_jobs(qmc_context* c, std::vector<BatchJob*>& jobs, double* kernel_
       sv_of[v] = 0;
       blocks_of[v] = (uint32_t)std::max(1, L.jk.occ_batch) * (uint32_t)c->cus;
     } else {
-      sv_of[v] = L.var.cplx ? 0 : c->batch_sv[L.variant];
+      sv_of[v] = !L.var.cplx ? c->batch_sv[L.variant]
+                 : L.variant < 0 ? qmck::BATCH_SV_COMPLEX_ANY : qmck::BATCH_SV_COMPLEX_INT_HALF;
       blocks_of[v] = (uint32_t)std::max(1, qmck::occupancy_batch(L.var, sv_of[v])) * (uint32_t)c->cus;
     }
     sig.insert(sig.end(), {(uint64_t)L.variant, L.jit ? (uint64_t)(uintptr_t)L.jk.batch : 0, (uint64_t)sv_of[v],

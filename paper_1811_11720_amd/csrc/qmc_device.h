@@ -499,10 +499,22 @@ __device__ __forceinline__ cplx cpow_feyn(cplx w, double p) {
 }
 // v^p folded into num/den (complex): integer and half-integer powers use
 // products and one principal square root
+// Power classes a table-driven complex kernel is built for: every mode, or
+// integer and half-integer powers only.  The general power's complex
+// logarithm and exponential need many registers, and a kernel that contains
+// them spills the whole evaluation's state to scratch memory even when no
+// integrand of the launch takes that path; the host sends integrands with
+// general powers to the POW_ANY kernels.
+enum { POW_ANY = 0, POW_INT_HALF = 1 };
+
+template <int POWS = POW_ANY>
 __device__ __forceinline__ void apply_cpow(cplx v, int mode, int k, double p, cplx& num, cplx& den) {
   if (mode == PW_ONE) return;
   if (mode == PW_GEN) {
-    num = cmul(num, cpow_feyn(v, p));
+    if constexpr (POWS == POW_ANY)
+      num = cmul(num, cpow_feyn(v, p));
+    else
+      num = cmk(__builtin_nan(""), __builtin_nan(""));  // never planned: shows as NaN
     return;
   }
   int ak = k < 0 ? -k : k;
@@ -654,15 +666,33 @@ __device__ __forceinline__ cplx deformed_integrand(const double (&x)[D], const F
 }
 
 // U(z)^pow_u F(z)^pow_f in fp64 from the functor's polynomials
-template <int D, class Fn>
+template <int D, class Fn, int POWS = POW_ANY>
 __device__ __forceinline__ cplx uf_fp64(const Fn& fn, const cplx (&z)[D], const EvalArgs& a, uint32_t& sign) {
   cplx num = cmk(1.0, 0.0), den = cmk(1.0, 0.0);
   cplx Uz = fn.U(z, a);
-  apply_cpow(Uz, a.pu_mode, a.pu_k, a.pow_u, num, den);
+  apply_cpow<POWS>(Uz, a.pu_mode, a.pu_k, a.pow_u, num, den);
   if (a.n_f) {
     cplx Fz = fn.F(z, a);
     sign += (Fz.im > 0.0) ? 1u : 0u;
-    apply_cpow(Fz, a.pf_mode, a.pf_k, a.pow_f, num, den);
+    apply_cpow<POWS>(Fz, a.pf_mode, a.pf_k, a.pow_f, num, den);
+  }
+  return cmul(num, crcp(den));
+}
+
+// The same with the power modes fixed when a kernel is generated for one
+// integrand: integer powers unroll into products, and without a general
+// power the complex logarithm and exponential (and their registers) are left
+// out of the kernel.
+template <int D, int PUM, int PUK, int PFM, int PFK, class Fn>
+__device__ __forceinline__ cplx uf_fp64_fixed(const Fn& fn, const cplx (&z)[D], const EvalArgs& a, uint32_t& sign) {
+  constexpr int POWS = (PUM == PW_GEN || PFM == PW_GEN) ? POW_ANY : POW_INT_HALF;
+  cplx num = cmk(1.0, 0.0), den = cmk(1.0, 0.0);
+  cplx Uz = fn.U(z, a);
+  apply_cpow<POWS>(Uz, PUM, PUK, a.pow_u, num, den);
+  if (a.n_f) {
+    cplx Fz = fn.F(z, a);
+    sign += (Fz.im > 0.0) ? 1u : 0u;
+    apply_cpow<POWS>(Fz, PFM, PFK, a.pow_f, num, den);
   }
   return cmul(num, crcp(den));
 }
@@ -673,8 +703,9 @@ __device__ __forceinline__ cplx uf_fp64(const Fn& fn, const cplx (&z)[D], const 
 // monomial.
 __device__ __forceinline__ void keep_branch() { asm volatile(""); }
 
-// Generic (table-driven) polynomial pieces for the deformed integrand.
-template <int DMAX>
+// Generic (table-driven) polynomial pieces for the deformed integrand, for
+// the power class POWS.
+template <int DMAX, int POWS = POW_ANY>
 struct GenericComplex {
   // Gradient and Hessian of F at real x.  For a monomial v = c prod_j x_j^e_j,
   // dv/dx_j = v e_j / x_j and d2v/dx_j dx_l = v e_j (e_l - [j = l]) / (x_j x_l),
@@ -770,7 +801,7 @@ struct GenericComplex {
     return poly(z, a.n_u, a.n_f, a);
   }
   __device__ __forceinline__ cplx uf(const cplx (&z)[DMAX], const EvalArgs& a, uint32_t& sign) const {
-    return uf_fp64<DMAX>(*this, z, a, sign);
+    return uf_fp64<DMAX, GenericComplex, POWS>(*this, z, a, sign);
   }
 };
 
@@ -875,10 +906,14 @@ __device__ __forceinline__ cplxf cpowf_feyn(cplxf w, float p) {
   sincosf(p * th, &sn, &cs);
   return cplxf{mag * cs, mag * sn};
 }
+template <int POWS = POW_ANY>
 __device__ __forceinline__ void apply_cpow_f32(cplxf v, int mode, int k, double p, cplxf& num, cplxf& den) {
   if (mode == PW_ONE) return;
   if (mode == PW_GEN) {
-    num = cmulf(num, cpowf_feyn(v, (float)p));
+    if constexpr (POWS == POW_ANY)
+      num = cmulf(num, cpowf_feyn(v, (float)p));
+    else
+      num = cplxf{__builtin_nanf(""), __builtin_nanf("")};  // never planned: shows as NaN
     return;
   }
   int ak = k < 0 ? -k : k;
@@ -897,8 +932,8 @@ __device__ __forceinline__ void apply_cpow_f32(cplxf v, int mode, int k, double 
 
 // Deformed integrand with U(z), F(z) and their powers in fp32; the gradient,
 // Hessian and Jacobian determinant come from the fp64 GenericComplex.
-template <int DMAX>
-struct GenericComplexF32 : GenericComplex<DMAX> {
+template <int DMAX, int POWS = POW_ANY>
+struct GenericComplexF32 : GenericComplex<DMAX, POWS> {
   __device__ __forceinline__ cplxf polyf(const cplxf (&z)[DMAX], uint32_t first, uint32_t count,
                                          const EvalArgs& a) const {
     cplxf s = cplxf{0.0f, 0.0f};
@@ -922,11 +957,11 @@ struct GenericComplexF32 : GenericComplex<DMAX> {
     for (int j = 0; j < DMAX; ++j) zf[j] = cplxf{(float)z[j].re, (float)z[j].im};
     cplxf num = cplxf{1.0f, 0.0f}, den = cplxf{1.0f, 0.0f};
     cplxf Uz = polyf(zf, 0, a.n_u, a);
-    apply_cpow_f32(Uz, a.pu_mode, a.pu_k, a.pow_u, num, den);
+    apply_cpow_f32<POWS>(Uz, a.pu_mode, a.pu_k, a.pow_u, num, den);
     if (a.n_f) {
       cplxf Fz = polyf(zf, a.n_u, a.n_f, a);
       sign += (Fz.im > 0.0f) ? 1u : 0u;
-      apply_cpow_f32(Fz, a.pf_mode, a.pf_k, a.pow_f, num, den);
+      apply_cpow_f32<POWS>(Fz, a.pf_mode, a.pf_k, a.pow_f, num, den);
     }
     cplxf f = cmulf(num, crcpf(den));
     return cmk((double)f.re, (double)f.im);

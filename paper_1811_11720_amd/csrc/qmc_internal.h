@@ -83,8 +83,10 @@ inline int batch_tkc(int tsel, bool has_vr) {
   return tsel == TSEL_KOROBOV3 ? TKC_KOROBOV3 : tsel == TSEL_BAKER ? TKC_BAKER : TKC_ANY;
 }
 // Real kernels come with sv index i = 0, 1, 2 (2^i points per decoded
-// monomial); complex kernels have sv index 0 only.
+// monomial); complex kernels with sv index 0 (every power) and 1 (integer and
+// half-integer powers only, far fewer registers: the host's choice per job).
 constexpr int BATCH_SV_VARIANTS = 3;
+constexpr int BATCH_SV_COMPLEX_ANY = 0, BATCH_SV_COMPLEX_INT_HALF = 1;
 BatchFn batch_kernel(const BatchVariant& v, int sv);
 int occupancy_batch(const BatchVariant& v, int sv);
 hipError_t launch_batch(const BatchVariant& v, int sv, const qmcd::EvalArgs* items, const uint32_t* order,

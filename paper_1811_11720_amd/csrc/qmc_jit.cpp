@@ -459,7 +459,8 @@ std::string generate_complex_fn(const qmcj::Spec& s) {
     o << "    return " << (v.real ? "cmk(" + v.name + ", 0.0)" : v.name) << ";\n  }\n";
   }
   o << "  __device__ __forceinline__ cplx uf(const cplx (&z)[" << d
-    << "], const EvalArgs& a, uint32_t& sign) const {\n    return uf_fp64<" << d << ">(*this, z, a, sign);\n  }\n";
+    << "], const EvalArgs& a, uint32_t& sign) const {\n    return uf_fp64_fixed<" << d << ", " << s.pu_mode << ", "
+    << s.pu_k << ", " << s.pf_mode << ", " << s.pf_k << ">(*this, z, a, sign);\n  }\n";
   if (s.vr && s.vr_params) {
     // the fitted map with its parameters as constants (j is unrolled at every call)
     o << "  __device__ __forceinline__ double vr_map(double y, int j, double& w) const {\n"

@@ -85,6 +85,32 @@ def test_alone_equals_in_the_mix_bitwise(ctx):
     assert np.array_equal(again["sums_re"], mixed[5]["sums_re"])
 
 
+def test_complex_general_and_half_integer_powers_share_a_batch(ctx):
+    """Deformed integrands whose powers are all integer or half-integer run in
+    the kernels without the general complex power; one general power (of U or
+    of F) sends a job to the kernels that hold it.  Both kinds, in one batch
+    with a real job, match the oracle, and each equals its result alone."""
+    powers = [(-2.0, -1.5), (-1.3, -1.5), (-2.0, -0.7), (-1.0, -2.5), (-2.5, -1.25), (-3.0, -1.0)]
+    jobs = []
+    for i, (pu, pf) in enumerate(powers):
+        dim = (3, 5, 8, 10, 4, 6)[i]
+        desc = W.sector(900 + i, dim, 3, 6, pu, pf, complex_=True, lam=0.5, neg_frac=0.3)
+        n = (4099, 10007)[i % 2]
+        jobs.append(W.Job(desc, n, cbc.fast_cbc(n, dim), 5, seed=7300 + i,
+                          transform=KOR3 if dim <= 8 else (W.T_BAKER, 0, 0)))
+    jobs.append(W.Job(W.sector(950, 4, 3, 6, -1.3, -0.7), 4099, cbc.fast_cbc(4099, 4), 5, seed=7399, transform=KOR3))
+    mixed = _run(ctx, jobs)
+    for j, r in zip(jobs, mixed):
+        sh = oracle.shifts(j.seed, j.m, j.desc.dim)
+        o = oracle.shift_sums(j.desc, j.n, j.z, j.m, sh, j.transform, threads=THREADS)
+        _check_sums(r["sums_re"], o, r["sums_im"] if j.desc.deform else None,
+                    label=f"d{j.desc.dim} pow {j.desc.pow_u} {j.desc.pow_f}")
+    for k in (0, 1, 2):
+        alone = _run(ctx, [jobs[k]])[0]
+        assert np.array_equal(alone["sums_re"], mixed[k]["sums_re"])
+        assert np.array_equal(alone["sums_im"], mixed[k]["sums_im"])
+
+
 def test_graph_replays_equal_eager(ctx):
     jobs = _mix(10, 4)
     eager_ctx = _ctx(False)
