@@ -111,6 +111,26 @@ def test_complex_general_and_half_integer_powers_share_a_batch(ctx):
         assert np.array_equal(alone["sums_im"], mixed[k]["sums_im"])
 
 
+def test_complex_power_classes_with_fp32_evaluation(ctx):
+    """The fp32-evaluation complex kernels come in the same two power classes
+    (and each fp32 job's fp64 twin follows its job's class)."""
+    jobs = []
+    for i, (pu, pf) in enumerate([(-2.0, -1.5), (-1.3, -1.5), (-2.0, -0.7), (-1.0, -2.5)]):
+        dim = (3, 6, 8, 10)[i]
+        desc = W.sector(960 + i, dim, 3, 6, pu, pf, complex_=True, lam=0.5, neg_frac=0.3)
+        desc.fp32 = True
+        jobs.append(W.Job(desc, 10007, cbc.fast_cbc(10007, dim), 4, seed=7400 + i,
+                          transform=KOR3 if dim <= 8 else (W.T_BAKER, 0, 0)))
+    res = _run(ctx, jobs)
+    for j, r in zip(jobs, res):
+        sh = oracle.shifts(j.seed, j.m, j.desc.dim)
+        o = oracle.shift_sums(j.desc, j.n, j.z, j.m, sh, j.transform, threads=THREADS)
+        # fp32 polynomials and powers: a few 1e-7 relative per evaluation
+        assert np.all(np.abs(r["sums_re"] - o.re) <= 2e-5 * o.abs_re + 1e-300), (j.desc.pow_u, j.desc.pow_f)
+        assert np.all(np.abs(r["sums_im"] - o.im) <= 2e-5 * o.abs_im + 1e-300), (j.desc.pow_u, j.desc.pow_f)
+        assert np.isfinite(r["fp32_err_re"]) and np.isfinite(r["fp32_err_im"])
+
+
 def test_graph_replays_equal_eager(ctx):
     jobs = _mix(10, 4)
     eager_ctx = _ctx(False)
