@@ -875,6 +875,7 @@ int autotune(qmc_context* c, const qmc_request* reqs, uint32_t count, uint32_t* 
     }
     const std::vector<uint64_t> tiles = var.cplx ? std::vector<uint64_t>{512, 1024, 4096}
                                                  : std::vector<uint64_t>{1024, 4096, 16384};
+    // complex kernels: the jobs' power class, not a tuning choice, picks the sv index
     const int nsv = var.cplx ? 1 : qmck::BATCH_SV_VARIANTS;
     // shifts per thread: all the kernel holds (0), or groups of 4 or 2: more,
     // smaller tiles (a small batch spreads over more workgroups) for more
