@@ -32,21 +32,28 @@ using EvalFn = void (*)(qmcd::EvalArgs);
 static EvalFn g_real[DIM_CLASSES][TSEL_COUNT][2] = {QMC_ROW(4), QMC_ROW(8), QMC_ROW(12), QMC_ROW(16), QMC_ROW(16)};
 #undef QMC_ROW
 
-// complex kernels: one table per dimension class, defined in qmc_kernels_c{4,6,8,10,12}.hip
-using EvalTable = EvalFn[TSEL_COUNT][2];
-extern EvalTable g_complex4, g_complex6, g_complex8, g_complex10, g_complex12;
-static EvalTable* const g_complex[DIM_CLASSES] = {&g_complex4, &g_complex6, &g_complex8, &g_complex10, &g_complex12};
+// complex kernels: one table per dimension class, defined in qmc_kernels_c{4,6,8,10,12}.hip,
+// [power class][transform][idx32]; class 1 holds no general complex power
+using ComplexTable = EvalFn[2][TSEL_COUNT][2];
+extern ComplexTable g_complex4, g_complex6, g_complex8, g_complex10, g_complex12;
+static ComplexTable* const g_complex[DIM_CLASSES] = {&g_complex4, &g_complex6, &g_complex8, &g_complex10,
+                                                     &g_complex12};
 
+static int power_class(const qmcd::EvalArgs& a) {
+  return (a.pu_mode == qmcd::PW_GEN || (a.n_f && a.pf_mode == qmcd::PW_GEN)) ? 0 : 1;
+}
+
+// (both power classes of a complex kernel are compiled for the same waves per SIMD)
 int occupancy_eval(bool cplx, int dclass, int tsel, bool idx32) {
   int occ = 0;
-  EvalFn fn = cplx ? (*g_complex[dclass])[tsel][idx32 ? 1 : 0] : g_real[dclass][tsel][idx32 ? 1 : 0];
+  EvalFn fn = cplx ? (*g_complex[dclass])[0][tsel][idx32 ? 1 : 0] : g_real[dclass][tsel][idx32 ? 1 : 0];
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)fn, QMCD_BLOCK, 0) != hipSuccess) return 0;
   return occ;
 }
 
 hipError_t launch_eval_complex(const qmcd::EvalArgs& a, int dclass, int tsel, bool idx32, dim3 grid,
                                hipStream_t st) {
-  EvalFn fn = (*g_complex[dclass])[tsel][idx32 ? 1 : 0];
+  EvalFn fn = (*g_complex[dclass])[power_class(a)][tsel][idx32 ? 1 : 0];
   qmcd::EvalArgs copy = a;
   void* args[] = {&copy};
   return hipLaunchKernel((const void*)fn, grid, dim3(QMCD_BLOCK), args, 0, st);
